@@ -1,0 +1,131 @@
+"""Seeded synthetic workloads for population annealing (PA) runs.
+
+This module only builds *inputs*: run descriptors (lattice size, model, seeds,
+population sizes, sweep count, annealing schedule, resampling and overlap
+choices).  It contains none of the method's arithmetic, so that the CPU oracle
+(``oracle/``) and the GPU library (``paper_2207_05535_amd``) can both consume
+the same descriptors without sharing any code that computes results.
+
+Every random number the method draws is produced inside the method itself by a
+counter-based generator keyed by ``seed`` (replica initialisation, sweeps,
+resampling) or ``disorder_seed`` (Edwards-Anderson couplings), so a descriptor
+fully determines a run.
+
+Workload shapes follow the paper's simulations (Sec. V A): 2D square lattices
+with periodic boundaries, an equidistant schedule beta_i = i * dbeta starting
+at beta_0 = 0 (infinite temperature, uniform population), theta Metropolis
+sweeps per temperature, Ising ferromagnet (J = +1) or +-J spin glass with
+couplings drawn uniformly and independently.
+"""
+from __future__ import annotations
+
+FM = 0          # Ising ferromagnet, Eq. (H_FM)
+EA_PMJ = 1      # Edwards-Anderson +-J spin glass, Eq. (H_EA)
+
+MULTINOMIAL = 0
+NEAREST_INT = 1
+
+Q_NONE = 0
+Q_INDEX_SHIFT = 1
+Q_TWO_POP = 2
+
+RUN_SEED_BASE = 0x5EED_0000_0000
+DISORDER_SEED_BASE = 0xD150_0000_0000
+
+
+def linear_schedule(beta_f: float, K: int) -> list[float]:
+    """K temperature points beta_i = beta_f * i / (K-1), i = 0..K-1.
+
+    beta_0 = 0 exactly and beta_{K-1} = beta_f exactly; K-1 annealing steps.
+    """
+    if K < 2:
+        raise ValueError("K must be >= 2")
+    return [beta_f * i / (K - 1) for i in range(K)]
+
+
+def run_desc(L, model=FM, seed=RUN_SEED_BASE, disorder_seed=DISORDER_SEED_BASE,
+             R=1000, R_cap=None, theta=10, K=101, beta_f=1.0, beta=None,
+             resampling=MULTINOMIAL, overlap=Q_NONE, qhist=0):
+    """One run descriptor as a plain dict (the fields of pa_run_desc)."""
+    if beta is None:
+        beta = linear_schedule(beta_f, K)
+    K = len(beta)
+    if R_cap is None:
+        R_cap = R if resampling == MULTINOMIAL else R + R // 4 + 64
+    return dict(L=int(L), model=int(model), seed=int(seed),
+                disorder_seed=int(disorder_seed), R=int(R), R_cap=int(R_cap),
+                theta=int(theta), K=int(K), beta=[float(b) for b in beta],
+                resampling=int(resampling), overlap=int(overlap),
+                qhist=int(qhist))
+
+
+def with_(desc: dict, **kw) -> dict:
+    """Copy of a descriptor with some fields replaced (beta keeps K in sync)."""
+    d = dict(desc)
+    d.update(kw)
+    if "beta" in kw:
+        d["K"] = len(d["beta"])
+    elif "K" in kw or "beta_f" in kw:
+        bf = kw.pop("beta_f", desc["beta"][-1])
+        d.pop("beta_f", None)
+        d["beta"] = linear_schedule(bf, d["K"])
+    return d
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  Names describe what they are.
+# ---------------------------------------------------------------------------
+
+def fm_L8_R1000(m: int = 0, resampling=MULTINOMIAL) -> dict:
+    """Ising FM, L=8, R=1000, beta 0->1 in 101 points, theta=10."""
+    return run_desc(8, FM, seed=RUN_SEED_BASE + m, R=1000, theta=10, K=101,
+                    beta_f=1.0, resampling=resampling)
+
+
+def fm_L64_R100k(m: int = 0, resampling=MULTINOMIAL, R=100_000, K=200) -> dict:
+    """Ising FM, L=64, R=1e5, beta 0->0.6 in 200 points, theta=10."""
+    return run_desc(64, FM, seed=RUN_SEED_BASE + m, R=R, theta=10, K=K,
+                    beta_f=0.6, resampling=resampling)
+
+
+def ea_L32_two_pop(sample: int = 0, m: int = 0, R=200_000, K=301,
+                   resampling=MULTINOMIAL) -> dict:
+    """EA +-J, L=32, two populations of R on one disorder, beta 0->3, 301 pts."""
+    return run_desc(32, EA_PMJ, seed=RUN_SEED_BASE + m,
+                    disorder_seed=DISORDER_SEED_BASE + sample, R=R, theta=10,
+                    K=K, beta_f=3.0, resampling=resampling, overlap=Q_TWO_POP)
+
+
+def batched_fm_uneven(n_per_L: int = 1024, Ls=(8, 16, 24, 32), R=2000, K=150,
+                      resampling=MULTINOMIAL) -> list[dict]:
+    """Many independent FM runs of uneven L, beta 0->0.6 in K points."""
+    runs = []
+    m = 0
+    for L in Ls:
+        for _ in range(n_per_L):
+            runs.append(run_desc(L, FM, seed=RUN_SEED_BASE + m, R=R, theta=10,
+                                 K=K, beta_f=0.6, resampling=resampling))
+            m += 1
+    return runs
+
+
+def serving_trace(n_requests: int = 500, rate_per_s: float = 20.0,
+                  Ls=(16, 24, 32, 48, 64), R=50_000, K=201, trace_seed=0xA110000):
+    """Poisson arrival trace of EA +-J requests: list of (t_arrival_s, desc).
+
+    Arrival gaps are exponential with the given rate; L is uniform over Ls;
+    each request has its own run seed and disorder seed.  Uses Python's
+    ``random`` only to build the trace (inputs), never inside the method.
+    """
+    import random
+    rng = random.Random(trace_seed)
+    t = 0.0
+    out = []
+    for q in range(n_requests):
+        t += rng.expovariate(rate_per_s)
+        L = Ls[rng.randrange(len(Ls))]
+        d = run_desc(L, EA_PMJ, seed=RUN_SEED_BASE + 0x100000 + q,
+                     disorder_seed=DISORDER_SEED_BASE + q, R=R, theta=10, K=K,
+                     beta_f=3.0, resampling=MULTINOMIAL, overlap=Q_INDEX_SHIFT)
+        out.append((t, d))
+    return out
