@@ -1,0 +1,202 @@
+/*
+ * pa.h -- C ABI of the MI355X population-annealing library (libpa.so).
+ *
+ * Population annealing (PA) with weighted averaging, after Ebert, Gessert and
+ * Weigel, "Weighted averages in population annealing: analysis and general
+ * framework" (arXiv:2207.05535).  The calls follow the paper's statement of
+ * the algorithm, Sec. II B steps (i)-(vi), and of weighted averaging, Sec. IV.
+ *
+ * Conventions for every call:
+ *  - Plain C types only: host pointers are marked "host", device pointers
+ *    "device".  No call throws; each returns a pa_status.
+ *  - The caller owns the device workspace (one allocation of at least
+ *    pa_workspace_size() bytes, 256-byte aligned) and the HIP stream; the
+ *    context borrows both until pa_destroy and never allocates device memory
+ *    itself.  Host arrays passed in (run descriptors, schedules) are copied.
+ *  - Work is enqueued asynchronously on the stream.  Calls that fill host
+ *    buffers synchronise the stream before returning.
+ *  - Argument validation happens before any device call, so a call rejected
+ *    with PA_ERR_ARG or PA_ERR_STATE has enqueued nothing.
+ *  - A device failure makes the context sticky-failed (PA_ERR_DEVICE from
+ *    then on).  A run whose population overflows its capacity
+ *    (PA_ERR_CAPACITY) or becomes empty (PA_ERR_NUMERIC) is frozen: its
+ *    later records carry that status, other runs continue, and weighted
+ *    averages leave it out.
+ *  - Determinism: every result depends only on the run descriptors; not on
+ *    batch composition, spin representation, tile shapes or the stream.
+ *    Spins, energies, family labels, resampling counts and integer sums are
+ *    bit-identical to the plain definitions; ln Q, A and weighted averages
+ *    are FP64.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pa_ctx pa_ctx;      /* opaque: one context = a batch of runs */
+
+typedef enum {
+    PA_OK = 0,
+    PA_ERR_ARG = 1,        /* invalid argument (nothing enqueued) */
+    PA_ERR_NOMEM = 2,      /* workspace smaller than pa_workspace_size() */
+    PA_ERR_CAPACITY = 3,   /* per run: nearest-integer population exceeded R_cap */
+    PA_ERR_STATE = 4,      /* call out of order (nothing enqueued) */
+    PA_ERR_NUMERIC = 5,    /* per run: empty population / non-finite input */
+    PA_ERR_DEVICE = 6      /* HIP error; the context is unusable */
+} pa_status;
+
+/* Models of Sec. III A: Ising ferromagnet (J = 1), Eq. (H_FM), and the
+ * Edwards-Anderson +-J spin glass, Eq. (H_EA), on the periodic L x L lattice. */
+enum { PA_FM = 0, PA_EA_PMJ = 1 };
+/* Resampling of step (iii): multinomial (constant population, Sec. IV D
+ * condition (c)) or nearest-integer (Sec. II B). */
+enum { PA_MULTINOMIAL = 0, PA_NEAREST_INT = 1 };
+/* Spin representation: one byte per spin, or 64 replicas bit-packed per
+ * 64-bit word (multi-spin coding).  Results are identical. */
+typedef enum { PA_INT8 = 0, PA_MSC64 = 1 } pa_repr;
+/* Spin-overlap pairing (Sec. III D): none; index shift j <-> j + floor(R_i/2);
+ * or two independent populations on the same couplings, pairs j <-> j. */
+enum { PA_Q_NONE = 0, PA_Q_INDEX_SHIFT = 1, PA_Q_TWO_POP = 2 };
+/* Free-energy weights, Eq. (appropriateWeight) (full) and Eq. (simpleWeight). */
+typedef enum { PA_W_FULL = 0, PA_W_SIMPLE = 1 } pa_weight_kind;
+
+/* One PA run.  Random numbers are drawn from Philox4x32-10 keyed by `seed`
+ * (initial spins, sweeps, resampling) and `disorder_seed` (couplings). */
+typedef struct {
+    int32_t L;              /* linear size: even, 4 <= L <= 1024 (<= 128 for PA_MSC64) */
+    int32_t model;          /* PA_FM or PA_EA_PMJ */
+    uint64_t seed;          /* run seed */
+    uint64_t disorder_seed; /* couplings of PA_EA_PMJ; ignored for PA_FM */
+    int32_t R;              /* target population size, >= 1 */
+    int32_t R_cap;          /* capacity, R <= R_cap < 2^23; == R for multinomial */
+    int32_t theta;          /* Metropolis sweeps per temperature, 0 <= theta < 2^24 */
+    int32_t K;              /* number of temperatures, K >= 2 */
+    const double *beta;     /* host [K]: schedule, beta[0] == 0, finite; copied */
+    int32_t resampling;     /* PA_MULTINOMIAL or PA_NEAREST_INT */
+    int32_t overlap;        /* PA_Q_NONE, PA_Q_INDEX_SHIFT or PA_Q_TWO_POP */
+    int32_t qhist;          /* 1: keep an overlap histogram per temperature */
+} pa_run_desc;
+
+/* One record per (run, population, temperature i): integer sums over the
+ * population at beta_i (Eqs. (PopAvrg), (e), (m), (c), (chi)), overlaps
+ * Q = N q and link overlaps Q_l = 2N q_l per pair, family statistics, and
+ * ln Q_i and A_i = -beta_i F_i = sum_{k<=i} ln Q_k + N ln 2 (Eq. (F)). */
+typedef struct {
+    int64_t R_i;
+    double lnQ, A;
+    int64_t sumE, sumE2, sumAbsM, sumM2;
+    int64_t nPairs, sumQ, sumAbsQ, sumQ2;
+    int64_t sumQl, sumQl2;
+    int64_t famSumSq, famMax, nFam;   /* rho_t = famSumSq / R_i, Eq. (rho_t) */
+    int32_t Emin, status;
+} pa_obs;
+
+/* One record per (group of M runs, temperature i), Sec. IV: configurational
+ * weighted averages W[e], W[e^2], W[m], W[m^2], W[|q|], W[q^2], W[q_l]
+ * (Eq. (W_conf)); weighted variance estimators W_var[c], W_var[chi]
+ * (Eqs. (Wvar_C), (Wvar_Chi)) and the configurational averages of c, chi;
+ * -beta_i W[F_i] (Eq. (W_F)); the sample variance of the weights and its
+ * log-normal prediction (Eq. (varWpred)). */
+typedef struct {
+    double W_e, W_e2, Wvar_c, Wconf_c, W_m, W_m2, Wvar_chi, Wconf_chi;
+    double W_absq, W_q2, W_ql, minus_beta_WF, var_w, var_w_pred;
+    int32_t n_included;     /* runs with status PA_OK at this temperature */
+} pa_wavg;
+
+/* Bytes of device workspace needed by pa_create for these runs.
+ * runs: host [n_runs]; bytes: host out.  PA_ERR_ARG on an invalid descriptor. */
+pa_status pa_workspace_size(const pa_run_desc *runs, int32_t n_runs, pa_repr repr,
+                            size_t *bytes);
+
+/* Step (i): draw R configurations from the uniform distribution at beta_0 = 0
+ * (Sec. II A), set up couplings, family labels f_j = j and A_0 = N ln 2, and
+ * measure at i = 0.  dev_workspace: device, >= pa_workspace_size bytes, owned
+ * by the caller; hip_stream: a hipStream_t (NULL = default stream).
+ * On success *out receives the context. */
+pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr,
+                    void *dev_workspace, size_t bytes, void *hip_stream, pa_ctx **out);
+
+/* Step (ii) for i = previous + 1: Q_i of Eq. (QBoltz) from the energies at
+ * beta_{i-1}, ln Q_i and A_i (Eq. (F)), and the resampling weights of
+ * Eq. (tauBoltz).  Requires the previous step to have been measured. */
+pa_status pa_anneal_step(pa_ctx *ctx, int32_t i);
+
+/* Step (iii): descendant counts (nearest-integer or multinomial), their
+ * prefix scan, and the copy of spins, energies and family labels into
+ * consecutive child slots, so that families stay contiguous (Sec. V A 1). */
+pa_status pa_resample(pa_ctx *ctx, int32_t i);
+
+/* Step (iv): theta checkerboard single-spin-flip Metropolis sweeps at beta_i
+ * (Sec. V A 1).  PA_INT8 contexts launch one colour of one run at a time;
+ * PA_MSC64 contexts update every run in one launch with the lattice held in
+ * on-chip memory for all theta sweeps. */
+pa_status pa_sweep(pa_ctx *ctx, int32_t i);
+
+/* Step (v): energies, magnetisations, overlaps and family sizes at beta_i.
+ * host_out: host [n_runs][n_pop] records of temperature i, or NULL
+ * (n_pop = 2 for every run when any run uses PA_Q_TWO_POP, else 1; the
+ * second slot of a one-population run is zero). */
+pa_status pa_measure(pa_ctx *ctx, int32_t i, pa_obs *host_out);
+
+/* Steps (ii)-(v) for i = i_begin .. i_end-1, replayed from one captured HIP
+ * graph of a temperature step.  Requires i_begin = previous + 1. */
+pa_status pa_run(pa_ctx *ctx, int32_t i_begin, int32_t i_end);
+
+/* Sec. IV: weighted averages over consecutive groups of M runs (runs
+ * [gM, (g+1)M) form group g; n_runs % M == 0; every run of a group must have
+ * the same L and schedule).  pop selects the population whose records are
+ * weighted.  host_out: host [n_runs/M][K].  Computed in FP64 on the device
+ * from the records of temperatures 0..i of the steps done so far; records of
+ * temperatures not reached yet are reported with n_included = 0. */
+pa_status pa_weighted_average(pa_ctx *ctx, int32_t M, pa_weight_kind kind, int32_t pop,
+                              pa_wavg *host_out);
+
+/* All records so far.  host_out: host [n_runs][n_pop][K]. */
+pa_status pa_read_obs(pa_ctx *ctx, pa_obs *host_out);
+
+/* Overlap histograms of one run (qhist = 1): host [n_pop][K][N+1] int32,
+ * bin d = number of pairs at Hamming distance d (q = 1 - 2d/N). */
+pa_status pa_read_qhist(pa_ctx *ctx, int32_t run, int32_t *host_out);
+
+/* Current population of (run, pop) in canonical form: spins host
+ * [R_cap][N] int8 (+1/-1, replica-major, site n = y L + x), energies and
+ * family labels host [R_cap] int32, descendant counts of the last
+ * resampling host [R_cap] int32; any pointer may be NULL.  *R_i and *R_prev
+ * (may be NULL) receive the current and previous population sizes. */
+pa_status pa_read_state(pa_ctx *ctx, int32_t run, int32_t pop, int8_t *spins, int32_t *E,
+                        int32_t *fam, int32_t *counts, int32_t *R_i, int32_t *R_prev);
+
+/* Checkpoint: with host_buf == NULL, *bytes receives the size needed; else
+ * the complete run state is written to host_buf (size *bytes). */
+pa_status pa_checkpoint(pa_ctx *ctx, void *host_buf, size_t *bytes);
+
+/* Restore a checkpoint taken from a context created with the same
+ * descriptors and representation.  Continuing from it reproduces the
+ * uninterrupted run bit for bit. */
+pa_status pa_restore(pa_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Kernel shape knobs, chosen by the autotuner per (L, representation):
+ * threads per workgroup of the multi-spin sweep and replica groups per
+ * workgroup.  A shape that does not fit is rejected with PA_ERR_ARG.
+ * Results never depend on the shape. */
+pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_wg);
+
+/* Text of the first HIP error that made the context fail ("none" if it has
+ * not failed).  The string is static; do not free it. */
+const char *pa_last_error(pa_ctx *ctx);
+
+/* Releases the context (not the workspace or the stream). */
+pa_status pa_destroy(pa_ctx *ctx);
+
+const char *pa_status_str(pa_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

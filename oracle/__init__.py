@@ -80,6 +80,8 @@ def lib():
         L.or_weighted_average.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]
         L.or_many_runs.argtypes = [C.POINTER(_Desc), C.c_int, vp, vp, vp]
         L.or_many_runs_obs.argtypes = [C.POINTER(_Desc), C.c_int, vp]
+        L.or_sweep_groups.argtypes = [vp, C.c_int, vp, C.c_int]
+        L.or_sweep_groups.restype = C.c_int
         _lib = L
     return _lib
 
@@ -133,6 +135,12 @@ class OracleRun:
 
     def measure(self, i):
         return lib().or_measure(self._h, i)
+
+    def sweep_groups(self, i, groups):
+        """Step (iv) for the listed 64-replica groups only (sampling of large
+        configurations; the run cannot be continued afterwards)."""
+        g = np.ascontiguousarray(groups, dtype=np.int32)
+        return lib().or_sweep_groups(self._h, i, _ptr(g), len(g))
 
     def step(self, i):
         for f in (self.anneal_step, self.resample, self.sweep, self.measure):

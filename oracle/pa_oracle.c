@@ -475,52 +475,75 @@ uint32_t or_sweep_draw(uint64_t seed, int n, int j, int i, int pop, int s)
  * updated (sites of one colour are never neighbours for even L, so their
  * order does not matter).  Single-spin-flip Metropolis: with
  * h = sum of J s over the 4 neighbours, dE = 2 s_n h; flip if dE <= 0, else
- * flip iff u < T(beta_i, dE). */
-int or_sweep(or_run *run, int i)
+ * flip iff u < T(beta_i, dE).  Replicas never interact during the sweeps, so
+ * the 64-replica groups are processed one after the other. */
+static void sweep_group(or_run *run, int p, int i, int g, uint64_t T4, uint64_t T8)
 {
-    if (!run) return OR_ERR_ARG;
-    if (run->phase != PH_RESAMPLED || i != run->i) return OR_ERR_STATE;
     int L = run->d.L, N = run->N;
-    uint64_t T4 = or_sweep_threshold(run->beta[i], 4);
-    uint64_t T8 = or_sweep_threshold(run->beta[i], 8);
+    or_pop *P = &run->pop[p];
+    int8_t *S = P->s[P->cur];
+    int32_t *E = P->E[P->cur];
+    int32_t Ri = P->Rcur;
     uint64_t planes[32];
-    for (int p = 0; p < run->npop; p++) {
-        or_pop *P = &run->pop[p];
-        if (P->status != OR_OK) continue;
-        int8_t *S = P->s[P->cur];
-        int32_t *E = P->E[P->cur];
-        int32_t Ri = P->Rcur;
-        for (int s = 0; s < run->d.theta; s++) {
-            for (int colour = 0; colour < 2; colour++) {
-                for (int n = 0; n < N; n++) {
-                    int x = n % L, y = n / L;
-                    if (((x + y) & 1) != colour) continue;
-                    int nr = right_of(n, L), nl = left_of(n, L);
-                    int nd = down_of(n, L), nu = up_of(n, L);
-                    for (int g = 0; g * 64 < Ri; g++) {
-                        sweep_planes(run->key, n, g, i, p, s, planes);
-                        for (int b = 0; b < 64 && g * 64 + b < Ri; b++) {
-                            int j = g * 64 + b;
-                            int8_t *sj = &S[(size_t)j * N];
-                            int h = run->jR[n] * sj[nr] + run->jR[nl] * sj[nl] +
-                                    run->jD[n] * sj[nd] + run->jD[nu] * sj[nu];
-                            int dE = 2 * sj[n] * h;
-                            int flip;
-                            if (dE <= 0) {
-                                flip = 1;
-                            } else {
-                                uint32_t u = draw_from_planes(planes, b);
-                                flip = (uint64_t)u < (dE == 4 ? T4 : T8);
-                            }
-                            if (flip) {
-                                sj[n] = (int8_t)-sj[n];
-                                E[j] += dE;
-                            }
-                        }
+    for (int s = 0; s < run->d.theta; s++) {
+        for (int colour = 0; colour < 2; colour++) {
+            for (int n = 0; n < N; n++) {
+                int x = n % L, y = n / L;
+                if (((x + y) & 1) != colour) continue;
+                int nr = right_of(n, L), nl = left_of(n, L);
+                int nd = down_of(n, L), nu = up_of(n, L);
+                sweep_planes(run->key, n, g, i, p, s, planes);
+                for (int b = 0; b < 64 && g * 64 + b < Ri; b++) {
+                    int j = g * 64 + b;
+                    int8_t *sj = &S[(size_t)j * N];
+                    int h = run->jR[n] * sj[nr] + run->jR[nl] * sj[nl] +
+                            run->jD[n] * sj[nd] + run->jD[nu] * sj[nu];
+                    int dE = 2 * sj[n] * h;
+                    int flip;
+                    if (dE <= 0) {
+                        flip = 1;
+                    } else {
+                        uint32_t u = draw_from_planes(planes, b);
+                        flip = (uint64_t)u < (dE == 4 ? T4 : T8);
+                    }
+                    if (flip) {
+                        sj[n] = (int8_t)-sj[n];
+                        E[j] += dE;
                     }
                 }
             }
         }
+    }
+}
+
+int or_sweep(or_run *run, int i)
+{
+    if (!run) return OR_ERR_ARG;
+    if (run->phase != PH_RESAMPLED || i != run->i) return OR_ERR_STATE;
+    uint64_t T4 = or_sweep_threshold(run->beta[i], 4);
+    uint64_t T8 = or_sweep_threshold(run->beta[i], 8);
+    for (int p = 0; p < run->npop; p++) {
+        if (run->pop[p].status != OR_OK) continue;
+        for (int g = 0; g * 64 < run->pop[p].Rcur; g++) sweep_group(run, p, i, g, T4, T8);
+    }
+    run->phase = PH_SWEPT;
+    return OR_OK;
+}
+
+/* Step (iv) for a sample of replica groups only (the other replicas are
+ * left as they were, so the run must not be continued afterwards).  Lets a
+ * test compare sampled outputs of configurations too large to sweep whole. */
+int or_sweep_groups(or_run *run, int i, const int32_t *groups, int ngroups)
+{
+    if (!run) return OR_ERR_ARG;
+    if (run->phase != PH_RESAMPLED || i != run->i) return OR_ERR_STATE;
+    uint64_t T4 = or_sweep_threshold(run->beta[i], 4);
+    uint64_t T8 = or_sweep_threshold(run->beta[i], 8);
+    for (int p = 0; p < run->npop; p++) {
+        if (run->pop[p].status != OR_OK) continue;
+        for (int k = 0; k < ngroups; k++)
+            if (groups[k] >= 0 && groups[k] * 64 < run->pop[p].Rcur)
+                sweep_group(run, p, i, groups[k], T4, T8);
     }
     run->phase = PH_SWEPT;
     return OR_OK;

@@ -1,0 +1,36 @@
+// launch.hpp -- host-side launchers of the kernels in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pa_internal.hpp"
+
+namespace pa {
+
+struct LaunchCtx {
+    const RunInfo *runs;      // device [n_runs]
+    PopState *st;             // device [n_runs][MAX_POP]
+    const Item *items;        // device [n_items]: every (run, pop, group < groups_cap)
+    int n_items;
+    const ChunkItem *chunk_items;  // device: every (run, pop, chunk < chunks_cap)
+    int n_chunk_items;
+    int n_runs, npop_ctx;
+    int repr;
+    bool any_multinomial;
+    hipStream_t stream;
+};
+
+hipError_t launch_fill_u32(void *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_init(const LaunchCtx &c, const uint64_t *dseed);
+hipError_t launch_anneal(const LaunchCtx &c);
+hipError_t launch_resample(const LaunchCtx &c);
+hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop, int theta);
+hipError_t launch_sweep_msc(const LaunchCtx &c, int maxN);
+hipError_t launch_measure(const LaunchCtx &c);
+hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
+                       double *logw, pa_wavg *out);
+int int8_tile_rows(int L);
+size_t msc_lds_bytes(int N);
+hipError_t prepare_msc_lds(size_t bytes);
+
+}  // namespace pa

@@ -1,0 +1,716 @@
+// pa_api.hip -- host implementation of the C ABI declared in include/pa.h.
+//
+// The context carves every device buffer out of the caller's workspace
+// (nothing is allocated on the device here), computes the threshold and
+// reweighting tables on the host in FP64 (no contraction, C library exp), and
+// enqueues the kernels of kernels.hip on the caller's stream.  Argument and
+// call-order validation precede every device call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pa.h"
+#include "launch.hpp"
+#include "pa_internal.hpp"
+
+using namespace pa;
+
+namespace {
+
+enum Phase { PH_MEASURED = 0, PH_ANNEALED = 1, PH_RESAMPLED = 2, PH_SWEPT = 3 };
+
+constexpr uint64_t CKPT_MAGIC = 0x50414d4933353558ull;  // "PAMI355X"
+constexpr uint32_t CKPT_VERSION = 1;
+
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version, repr;
+    uint64_t ws_used;
+    int32_t n_runs, i, phase, npop_ctx;
+};
+
+// Offsets of every buffer inside the workspace (256-byte aligned).
+struct Planner {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+struct RunOff {
+    size_t spins[MAX_POP][2], E[MAX_POP][2], fam[MAX_POP][2], r[MAX_POP], C[MAX_POP], parent[MAX_POP],
+        P[MAX_POP], famcnt[MAX_POP], partS[MAX_POP], tot64[MAX_POP], base64[MAX_POP], tot32[MAX_POP],
+        base32[MAX_POP], qh, jbits;
+    int table;
+};
+
+struct TableOff {
+    size_t X, x, T, beta;
+    int N, K;
+    const double *beta_src;
+};
+
+struct Layout {
+    std::vector<RunOff> runs;
+    std::vector<TableOff> tables;
+    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg;
+    int n_items, n_chunk_items, npop_ctx, Kmax, maxN;
+    size_t total;
+};
+
+bool desc_ok(const pa_run_desc &d, pa_repr repr)
+{
+    if (d.L < 4 || d.L > 1024 || (d.L & 1)) return false;
+    if (repr == PA_MSC64 && d.L > 128) return false;
+    if (d.model != PA_FM && d.model != PA_EA_PMJ) return false;
+    if (d.R < 1 || d.R_cap < d.R || d.R_cap >= (1 << 23)) return false;
+    if (d.resampling != PA_MULTINOMIAL && d.resampling != PA_NEAREST_INT) return false;
+    if (d.resampling == PA_MULTINOMIAL && d.R_cap != d.R) return false;
+    if (d.overlap < PA_Q_NONE || d.overlap > PA_Q_TWO_POP) return false;
+    if (d.qhist != 0 && d.qhist != 1) return false;
+    if (d.theta < 0 || d.theta >= (1 << 24)) return false;
+    if (d.K < 2 || d.K > (1 << 20) || d.beta == nullptr) return false;
+    if (d.beta[0] != 0.0) return false;
+    for (int i = 0; i < d.K; ++i)
+        if (!std::isfinite(d.beta[i])) return false;
+    const double N = (double)d.L * d.L;
+    if (4.0 * N * N * (double)d.R_cap >= 4.0e18) return false;  // int64 sums of E^2, Q_l^2
+    return true;
+}
+
+bool same_table(const TableOff &t, int N, const pa_run_desc &d)
+{
+    return t.N == N && t.K == d.K && std::memcmp(t.beta_src, d.beta, sizeof(double) * d.K) == 0;
+}
+
+int groups_cap_of(const pa_run_desc &d) { return (d.R_cap + 63) / 64; }
+int chunks_cap_of(const pa_run_desc &d) { return (d.R_cap + CH - 1) / CH; }
+
+Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
+{
+    Layout Lo;
+    Planner P;
+    Lo.npop_ctx = 1;
+    Lo.Kmax = 0;
+    Lo.maxN = 0;
+    for (int r = 0; r < n_runs; ++r) {
+        Lo.npop_ctx = std::max(Lo.npop_ctx, n_pop_of(runs[r].overlap));
+        Lo.Kmax = std::max(Lo.Kmax, runs[r].K);
+        Lo.maxN = std::max(Lo.maxN, runs[r].L * runs[r].L);
+    }
+    Lo.runinfo = P.take(sizeof(RunInfo) * n_runs);
+    Lo.popstate = P.take(sizeof(PopState) * n_runs * MAX_POP);
+    Lo.dseed = P.take(sizeof(uint64_t) * n_runs);
+    Lo.n_items = 0;
+    Lo.n_chunk_items = 0;
+    for (int r = 0; r < n_runs; ++r) {
+        const int npop = n_pop_of(runs[r].overlap);
+        Lo.n_items += npop * groups_cap_of(runs[r]);
+        Lo.n_chunk_items += npop * chunks_cap_of(runs[r]);
+    }
+    Lo.items = P.take(sizeof(Item) * Lo.n_items);
+    Lo.chunk_items = P.take(sizeof(ChunkItem) * Lo.n_chunk_items);
+    Lo.obs = P.take(sizeof(pa_obs) * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx);
+    Lo.logw = P.take(sizeof(double) * (size_t)Lo.Kmax * n_runs);
+    Lo.wavg = P.take(sizeof(pa_wavg) * (size_t)Lo.Kmax * n_runs);
+    Lo.runs.resize(n_runs);
+    for (int r = 0; r < n_runs; ++r) {
+        const pa_run_desc &d = runs[r];
+        const int N = d.L * d.L;
+        int t = -1;
+        for (size_t k = 0; k < Lo.tables.size(); ++k)
+            if (same_table(Lo.tables[k], N, d)) t = (int)k;
+        if (t < 0) {
+            TableOff T;
+            T.N = N;
+            T.K = d.K;
+            T.beta_src = d.beta;
+            T.X = P.take(sizeof(uint64_t) * (size_t)d.K * (N + 1));
+            T.x = P.take(sizeof(double) * (size_t)d.K * (N + 1));
+            T.T = P.take(sizeof(uint64_t) * 2 * d.K);
+            T.beta = P.take(sizeof(double) * d.K);
+            Lo.tables.push_back(T);
+            t = (int)Lo.tables.size() - 1;
+        }
+        RunOff &o = Lo.runs[r];
+        std::memset(&o, 0, sizeof(o));
+        o.table = t;
+        const int npop = n_pop_of(d.overlap);
+        const size_t site_bytes = repr == PA_MSC64 ? 8 : 64;
+        const size_t nch = chunks_cap_of(d);
+        for (int p = 0; p < npop; ++p) {
+            for (int b = 0; b < 2; ++b) {
+                o.spins[p][b] = P.take((size_t)groups_cap_of(d) * N * site_bytes);
+                o.E[p][b] = P.take(sizeof(int32_t) * d.R_cap);
+                o.fam[p][b] = P.take(sizeof(int32_t) * d.R_cap);
+            }
+            o.r[p] = P.take(sizeof(int32_t) * d.R_cap);
+            o.C[p] = P.take(sizeof(int32_t) * (d.R_cap + 1));
+            o.parent[p] = P.take(sizeof(int32_t) * d.R_cap);
+            o.P[p] = d.resampling == PA_MULTINOMIAL ? P.take(sizeof(uint64_t) * (d.R_cap + 1)) : 0;
+            o.famcnt[p] = P.take(sizeof(int32_t) * d.R);
+            o.partS[p] = P.take(sizeof(double) * nch);
+            o.tot64[p] = P.take(sizeof(uint64_t) * nch);
+            o.base64[p] = P.take(sizeof(uint64_t) * nch);
+            o.tot32[p] = P.take(sizeof(int32_t) * nch);
+            o.base32[p] = P.take(sizeof(int32_t) * nch);
+        }
+        o.qh = d.qhist ? P.take(sizeof(int32_t) * (size_t)npop * d.K * (N + 1)) : 0;
+        o.jbits = P.take(N);
+    }
+    Lo.total = P.off;
+    return Lo;
+}
+
+}  // namespace
+
+struct pa_ctx {
+    int n_runs = 0;
+    pa_repr repr = PA_INT8;
+    hipStream_t stream = nullptr;
+    uint8_t *ws = nullptr;
+    Layout lo;
+    std::vector<pa_run_desc> descs;
+    std::vector<std::vector<double>> betas;
+    std::vector<RunInfo> hinfo;
+    LaunchCtx lc;
+    int i = 0;
+    int phase = PH_MEASURED;
+    bool failed = false;
+    hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_def = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+    bool any_multinomial = false;
+    hipError_t last = hipSuccess;
+};
+
+namespace {
+
+template <typename T>
+T *at(pa_ctx *c, size_t off)
+{
+    return (T *)(c->ws + off);
+}
+
+pa_status dev_fail(pa_ctx *c, hipError_t e = hipSuccess)
+{
+    c->failed = true;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (c->last == hipSuccess) c->last = e;
+    return PA_ERR_DEVICE;
+}
+
+#define PA_HIP(ctx, expr)                                  \
+    do {                                                   \
+        const hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return dev_fail(ctx, e_);    \
+    } while (0)
+
+void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::vector<double> &x,
+                    std::vector<uint64_t> &T)
+{
+    // Reweighting factors of step beta_{i-1} -> beta_i for a replica at
+    // E_min + 4k (Eq. (tauBoltz)): x = exp(-dbeta 4k), X = floor(x 2^40).
+    // Metropolis thresholds at beta_i: T = floor(exp(-beta dE) 2^32), dE = 4, 8.
+    X.assign((size_t)d.K * (N + 1), 0);
+    x.assign((size_t)d.K * (N + 1), 0.0);
+    T.assign((size_t)2 * d.K, 0);
+    for (int i = 0; i < d.K; ++i) {
+        const double db = i == 0 ? 0.0 : d.beta[i] - d.beta[i - 1];
+        for (int k = 0; k <= N; ++k) {
+            const double v = std::exp(-(db * (double)(4 * k)));
+            x[(size_t)i * (N + 1) + k] = v;
+            X[(size_t)i * (N + 1) + k] = (uint64_t)std::floor(std::ldexp(v, 40));
+        }
+        for (int q = 0; q < 2; ++q) {
+            const double p = std::exp(-(d.beta[i] * (double)(4 * (q + 1))));
+            T[2 * i + q] = (uint64_t)std::floor(std::ldexp(p, 32));
+        }
+    }
+}
+
+pa_status enqueue_step(pa_ctx *c)
+{
+    if (launch_anneal(c->lc) != hipSuccess) return dev_fail(c);
+    if (launch_resample(c->lc) != hipSuccess) return dev_fail(c);
+    if (c->repr == PA_MSC64) {
+        if (launch_sweep_msc(c->lc, c->lo.maxN) != hipSuccess) return dev_fail(c);
+    } else {
+        for (int r = 0; r < c->n_runs; ++r) {
+            const pa_run_desc &d = c->descs[r];
+            if (launch_sweep_int8_run(c->lc, r, d.L, groups_cap_of(d), n_pop_of(d.overlap), d.theta) !=
+                hipSuccess)
+                return dev_fail(c);
+        }
+    }
+    if (launch_measure(c->lc) != hipSuccess) return dev_fail(c);
+    return PA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pa_status_str(pa_status st)
+{
+    switch (st) {
+    case PA_OK: return "ok";
+    case PA_ERR_ARG: return "invalid argument";
+    case PA_ERR_NOMEM: return "workspace too small";
+    case PA_ERR_CAPACITY: return "population exceeded its capacity";
+    case PA_ERR_STATE: return "call out of order";
+    case PA_ERR_NUMERIC: return "numeric failure (empty population or non-finite value)";
+    case PA_ERR_DEVICE: return "HIP device error";
+    }
+    return "unknown status";
+}
+
+pa_status pa_workspace_size(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, size_t *bytes)
+{
+    if (!runs || n_runs < 1 || !bytes || (repr != PA_INT8 && repr != PA_MSC64)) return PA_ERR_ARG;
+    for (int r = 0; r < n_runs; ++r)
+        if (!desc_ok(runs[r], repr)) return PA_ERR_ARG;
+    *bytes = plan(runs, n_runs, repr).total;
+    return PA_OK;
+}
+
+pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void *dev_workspace, size_t bytes,
+                    void *hip_stream, pa_ctx **out)
+{
+    if (!out) return PA_ERR_ARG;
+    *out = nullptr;
+    size_t need = 0;
+    pa_status st = pa_workspace_size(runs, n_runs, repr, &need);
+    if (st != PA_OK) return st;
+    if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return PA_ERR_ARG;
+    if (bytes < need) return PA_ERR_NOMEM;
+
+    pa_ctx *c = new pa_ctx();
+    c->n_runs = n_runs;
+    c->repr = repr;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (uint8_t *)dev_workspace;
+    c->lo = plan(runs, n_runs, repr);
+    c->descs.assign(runs, runs + n_runs);
+    c->betas.resize(n_runs);
+    for (int r = 0; r < n_runs; ++r) {
+        c->betas[r].assign(runs[r].beta, runs[r].beta + runs[r].K);
+        c->descs[r].beta = c->betas[r].data();
+        if (runs[r].resampling == PA_MULTINOMIAL) c->any_multinomial = true;
+    }
+    // table sources must point at the context's own copies
+    for (auto &t : c->lo.tables) {
+        for (int r = 0; r < n_runs; ++r)
+            if (t.beta_src == runs[r].beta) {
+                t.beta_src = c->betas[r].data();
+                break;
+            }
+    }
+    const Layout &Lo = c->lo;
+
+    // host images of the device-side records
+    c->hinfo.resize(n_runs);
+    std::vector<PopState> hst((size_t)n_runs * MAX_POP);
+    std::vector<Item> items;
+    std::vector<ChunkItem> chunks;
+    std::vector<uint64_t> dseed(n_runs);
+    for (int r = 0; r < n_runs; ++r) {
+        const pa_run_desc &d = c->descs[r];
+        const RunOff &o = Lo.runs[r];
+        const TableOff &T = Lo.tables[o.table];
+        RunInfo &I = c->hinfo[r];
+        std::memset(&I, 0, sizeof(I));
+        I.L = d.L;
+        I.N = d.L * d.L;
+        I.npop = n_pop_of(d.overlap);
+        I.R = d.R;
+        I.R_cap = d.R_cap;
+        I.theta = d.theta;
+        I.K = d.K;
+        I.model = d.model;
+        I.resampling = d.resampling;
+        I.overlap = d.overlap;
+        I.qhist = d.qhist;
+        I.groups_cap = groups_cap_of(d);
+        I.key0 = (uint32_t)(d.seed & 0xffffffffu);
+        I.key1 = (uint32_t)(d.seed >> 32);
+        I.run = r;
+        for (int p = 0; p < I.npop; ++p) {
+            for (int b = 0; b < 2; ++b) {
+                I.spins[p][b] = at<uint8_t>(c, o.spins[p][b]);
+                I.E[p][b] = at<int32_t>(c, o.E[p][b]);
+                I.fam[p][b] = at<int32_t>(c, o.fam[p][b]);
+            }
+            I.r[p] = at<int32_t>(c, o.r[p]);
+            I.C[p] = at<int32_t>(c, o.C[p]);
+            I.parent[p] = at<int32_t>(c, o.parent[p]);
+            I.P[p] = d.resampling == PA_MULTINOMIAL ? at<uint64_t>(c, o.P[p]) : nullptr;
+            I.famcnt[p] = at<int32_t>(c, o.famcnt[p]);
+            I.partS[p] = at<double>(c, o.partS[p]);
+            I.tot64[p] = at<uint64_t>(c, o.tot64[p]);
+            I.base64[p] = at<uint64_t>(c, o.base64[p]);
+            I.tot32[p] = at<int32_t>(c, o.tot32[p]);
+            I.base32[p] = at<int32_t>(c, o.base32[p]);
+            PopState &S = hst[(size_t)r * MAX_POP + p];
+            std::memset(&S, 0, sizeof(S));
+            S.i = 0;
+            S.cur = 0;
+            S.src = 0;
+            S.Rprev = d.R;
+            S.Rcur = d.R;
+            S.status = PA_OK;
+            S.moved = 1;
+            S.A = (double)I.N * std::log(2.0);   // ln Z(0) = N ln 2
+            S.EminAcc = INT32_MAX;
+            for (int g = 0; g < I.groups_cap; ++g) items.push_back({r, p, g, 0});
+            for (int k = 0; k < chunks_cap_of(d); ++k) chunks.push_back({r, p, k, 0});
+        }
+        I.obs = at<pa_obs>(c, Lo.obs);
+        I.qh = d.qhist ? at<int32_t>(c, o.qh) : nullptr;
+        I.jbits = at<uint8_t>(c, o.jbits);
+        I.tabX = at<uint64_t>(c, T.X);
+        I.tabx = at<double>(c, T.x);
+        I.tabT = at<uint64_t>(c, T.T);
+        I.beta = at<double>(c, T.beta);
+        dseed[r] = d.disorder_seed;
+    }
+
+    c->lc.runs = at<RunInfo>(c, Lo.runinfo);
+    c->lc.st = at<PopState>(c, Lo.popstate);
+    c->lc.items = at<Item>(c, Lo.items);
+    c->lc.n_items = Lo.n_items;
+    c->lc.chunk_items = at<ChunkItem>(c, Lo.chunk_items);
+    c->lc.n_chunk_items = Lo.n_chunk_items;
+    c->lc.n_runs = n_runs;
+    c->lc.npop_ctx = Lo.npop_ctx;
+    c->lc.repr = repr;
+    c->lc.any_multinomial = c->any_multinomial;
+    c->lc.stream = c->stream;
+
+    auto fail = [&](pa_status s) {
+        delete c;
+        return s;
+    };
+    if (repr == PA_MSC64) {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return fail(PA_ERR_DEVICE);
+        if (msc_lds_bytes(Lo.maxN) > (size_t)lds) return fail(PA_ERR_ARG);
+        if (prepare_msc_lds(msc_lds_bytes(Lo.maxN)) != hipSuccess) return fail(PA_ERR_DEVICE);
+    }
+
+    hipStream_t s = c->stream;
+    bool ok = true;
+    ok = ok && hipMemcpyAsync((void *)c->lc.runs, c->hinfo.data(), sizeof(RunInfo) * n_runs, hipMemcpyHostToDevice, s) ==
+                   hipSuccess;
+    ok = ok && hipMemcpyAsync(c->lc.st, hst.data(), sizeof(PopState) * hst.size(), hipMemcpyHostToDevice, s) ==
+                   hipSuccess;
+    ok = ok && hipMemcpyAsync(at<Item>(c, Lo.items), items.data(), sizeof(Item) * items.size(),
+                              hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(at<ChunkItem>(c, Lo.chunk_items), chunks.data(), sizeof(ChunkItem) * chunks.size(),
+                              hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(at<uint64_t>(c, Lo.dseed), dseed.data(), sizeof(uint64_t) * n_runs,
+                              hipMemcpyHostToDevice, s) == hipSuccess;
+    std::vector<std::vector<uint64_t>> hX(Lo.tables.size()), hT(Lo.tables.size());
+    std::vector<std::vector<double>> hx(Lo.tables.size());
+    for (size_t t = 0; t < Lo.tables.size() && ok; ++t) {
+        const TableOff &T = Lo.tables[t];
+        pa_run_desc d = {};
+        d.K = T.K;
+        d.beta = T.beta_src;
+        compute_tables(d, T.N, hX[t], hx[t], hT[t]);
+        ok = ok && hipMemcpyAsync(at<uint64_t>(c, T.X), hX[t].data(), sizeof(uint64_t) * hX[t].size(),
+                                  hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(at<double>(c, T.x), hx[t].data(), sizeof(double) * hx[t].size(),
+                                  hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(at<uint64_t>(c, T.T), hT[t].data(), sizeof(uint64_t) * hT[t].size(),
+                                  hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(at<double>(c, T.beta), T.beta_src, sizeof(double) * T.K, hipMemcpyHostToDevice,
+                                  s) == hipSuccess;
+    }
+    // zero the histograms, records and scratch that kernels accumulate into
+    for (int r = 0; r < n_runs && ok; ++r) {
+        const pa_run_desc &d = c->descs[r];
+        const RunOff &o = Lo.runs[r];
+        for (int p = 0; p < n_pop_of(d.overlap) && ok; ++p) {
+            ok = launch_fill_u32(at<void>(c, o.famcnt[p]), 0, d.R, s) == hipSuccess;
+            ok = ok && launch_fill_u32(at<void>(c, o.r[p]), 0, d.R_cap, s) == hipSuccess;
+        }
+        if (d.qhist && ok)
+            ok = launch_fill_u32(at<void>(c, o.qh), 0, (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1), s) ==
+                 hipSuccess;
+    }
+    ok = ok && launch_fill_u32(at<void>(c, Lo.obs), 0,
+                               sizeof(pa_obs) / 4 * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx, s) == hipSuccess;
+    ok = ok && launch_init(c->lc, at<uint64_t>(c, Lo.dseed)) == hipSuccess;
+    ok = ok && launch_measure(c->lc) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) return fail(PA_ERR_DEVICE);
+    c->i = 0;
+    c->phase = PH_MEASURED;
+    *out = c;
+    return PA_OK;
+}
+
+pa_status pa_anneal_step(pa_ctx *c, int32_t i)
+{
+    if (!c) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED || i != c->i + 1 || i >= c->lo.Kmax) return PA_ERR_STATE;
+    if (launch_anneal(c->lc) != hipSuccess) return dev_fail(c);
+    c->i = i;
+    c->phase = PH_ANNEALED;
+    return PA_OK;
+}
+
+pa_status pa_resample(pa_ctx *c, int32_t i)
+{
+    if (!c) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_ANNEALED || i != c->i) return PA_ERR_STATE;
+    if (launch_resample(c->lc) != hipSuccess) return dev_fail(c);
+    c->phase = PH_RESAMPLED;
+    return PA_OK;
+}
+
+pa_status pa_sweep(pa_ctx *c, int32_t i)
+{
+    if (!c) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_RESAMPLED || i != c->i) return PA_ERR_STATE;
+    if (c->repr == PA_MSC64) {
+        if (launch_sweep_msc(c->lc, c->lo.maxN) != hipSuccess) return dev_fail(c);
+    } else {
+        for (int r = 0; r < c->n_runs; ++r) {
+            const pa_run_desc &d = c->descs[r];
+            if (launch_sweep_int8_run(c->lc, r, d.L, groups_cap_of(d), n_pop_of(d.overlap), d.theta) != hipSuccess)
+                return dev_fail(c);
+        }
+    }
+    c->phase = PH_SWEPT;
+    return PA_OK;
+}
+
+pa_status pa_measure(pa_ctx *c, int32_t i, pa_obs *host_out)
+{
+    if (!c) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_SWEPT || i != c->i) return PA_ERR_STATE;
+    if (launch_measure(c->lc) != hipSuccess) return dev_fail(c);
+    c->phase = PH_MEASURED;
+    if (host_out) {
+        const size_t n = (size_t)c->n_runs * c->lo.npop_ctx;
+        PA_HIP(c, hipMemcpyAsync(host_out, at<pa_obs>(c, c->lo.obs) + (size_t)i * n, sizeof(pa_obs) * n,
+                                 hipMemcpyDeviceToHost, c->stream));
+        PA_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return PA_OK;
+}
+
+pa_status pa_run(pa_ctx *c, int32_t i_begin, int32_t i_end)
+{
+    if (!c) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED || i_begin != c->i + 1 || i_end > c->lo.Kmax || i_end <= i_begin)
+        return PA_ERR_STATE;
+    if (!c->graph) {
+        // One temperature step: every kernel reads its temperature index and
+        // buffers from device state, so the same graph serves every step.
+        // Capture runs on a private stream (the caller's may be the null
+        // stream, which cannot be captured); replays go to the caller's.
+        if (!c->cap_stream) PA_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        c->lc.stream = c->cap_stream;
+        const hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (eb != hipSuccess) {
+            c->lc.stream = c->stream;
+            return dev_fail(c, eb);
+        }
+        pa_status st = enqueue_step(c);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        c->lc.stream = c->stream;
+        if (st != PA_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return dev_fail(c, e);
+        }
+        c->graph_def = g;
+        PA_HIP(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+    }
+    for (int i = i_begin; i < i_end; ++i) PA_HIP(c, hipGraphLaunch(c->graph, c->stream));
+    c->i = i_end - 1;
+    c->phase = PH_MEASURED;
+    return PA_OK;
+}
+
+pa_status pa_weighted_average(pa_ctx *c, int32_t M, pa_weight_kind kind, int32_t pop, pa_wavg *host_out)
+{
+    if (!c || !host_out || M < 1 || c->n_runs % M != 0 || (kind != PA_W_FULL && kind != PA_W_SIMPLE))
+        return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const int K = c->descs[0].K;
+    for (int r = 0; r < c->n_runs; ++r) {
+        const pa_run_desc &d = c->descs[r];
+        if (d.K != K || pop < 0 || pop >= n_pop_of(d.overlap)) return PA_ERR_ARG;
+        const pa_run_desc &d0 = c->descs[(r / M) * M];
+        if (d.L != d0.L || std::memcmp(d.beta, d0.beta, sizeof(double) * K) != 0) return PA_ERR_ARG;
+    }
+    const int i_done = c->phase == PH_MEASURED ? c->i : c->i - 1;
+    pa_wavg *dout = at<pa_wavg>(c, c->lo.wavg);
+    if (launch_wavg(c->lc, at<pa_obs>(c, c->lo.obs), M, kind, pop, K, i_done, at<double>(c, c->lo.logw), dout) !=
+        hipSuccess)
+        return dev_fail(c);
+    PA_HIP(c, hipMemcpyAsync(host_out, dout, sizeof(pa_wavg) * (size_t)(c->n_runs / M) * K, hipMemcpyDeviceToHost,
+                             c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_read_obs(pa_ctx *c, pa_obs *host_out)
+{
+    if (!c || !host_out) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const int np = c->lo.npop_ctx, K = c->lo.Kmax;
+    std::vector<pa_obs> tmp((size_t)K * c->n_runs * np);
+    PA_HIP(c, hipMemcpyAsync(tmp.data(), at<pa_obs>(c, c->lo.obs), sizeof(pa_obs) * tmp.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    for (int r = 0; r < c->n_runs; ++r)
+        for (int p = 0; p < np; ++p)
+            for (int i = 0; i < K; ++i)
+                host_out[((size_t)r * np + p) * K + i] = tmp[((size_t)i * c->n_runs + r) * np + p];
+    return PA_OK;
+}
+
+pa_status pa_read_qhist(pa_ctx *c, int32_t run, int32_t *host_out)
+{
+    if (!c || !host_out || run < 0 || run >= c->n_runs || !c->descs[run].qhist) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const pa_run_desc &d = c->descs[run];
+    const size_t n = (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1);
+    PA_HIP(c, hipMemcpyAsync(host_out, at<int32_t>(c, c->lo.runs[run].qh), sizeof(int32_t) * n,
+                             hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_read_state(pa_ctx *c, int32_t run, int32_t pop, int8_t *spins, int32_t *E, int32_t *fam,
+                        int32_t *counts, int32_t *R_i, int32_t *R_prev)
+{
+    if (!c || run < 0 || run >= c->n_runs) return PA_ERR_ARG;
+    const pa_run_desc &d = c->descs[run];
+    if (pop < 0 || pop >= n_pop_of(d.overlap)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    PopState S;
+    PA_HIP(c, hipMemcpyAsync(&S, c->lc.st + (size_t)run * MAX_POP + pop, sizeof(S), hipMemcpyDeviceToHost,
+                             c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    const RunOff &o = c->lo.runs[run];
+    const int N = d.L * d.L;
+    const int cur = S.cur;
+    if (spins) {
+        const size_t site_bytes = c->repr == PA_MSC64 ? 8 : 64;
+        std::vector<uint8_t> raw((size_t)groups_cap_of(d) * N * site_bytes);
+        PA_HIP(c, hipMemcpyAsync(raw.data(), at<uint8_t>(c, o.spins[pop][cur]), raw.size(), hipMemcpyDeviceToHost,
+                                 c->stream));
+        PA_HIP(c, hipStreamSynchronize(c->stream));
+        for (int j = 0; j < S.Rcur; ++j) {
+            const int g = j >> 6, b = j & 63;
+            for (int n = 0; n < N; ++n) {
+                int down;
+                if (c->repr == PA_MSC64) {
+                    uint64_t w;
+                    std::memcpy(&w, &raw[((size_t)g * N + n) * 8], 8);
+                    down = (int)((w >> b) & 1u);
+                } else {
+                    down = raw[((size_t)g * N + n) * 64 + b] >> 7;
+                }
+                spins[(size_t)j * N + n] = down ? -1 : 1;
+            }
+        }
+    }
+    if (E)
+        PA_HIP(c, hipMemcpyAsync(E, at<int32_t>(c, o.E[pop][cur]), sizeof(int32_t) * S.Rcur, hipMemcpyDeviceToHost,
+                                 c->stream));
+    if (fam)
+        PA_HIP(c, hipMemcpyAsync(fam, at<int32_t>(c, o.fam[pop][cur]), sizeof(int32_t) * S.Rcur,
+                                 hipMemcpyDeviceToHost, c->stream));
+    if (counts)
+        PA_HIP(c, hipMemcpyAsync(counts, at<int32_t>(c, o.r[pop]), sizeof(int32_t) * S.Rprev,
+                                 hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    if (R_i) *R_i = S.Rcur;
+    if (R_prev) *R_prev = S.Rprev;
+    return PA_OK;
+}
+
+pa_status pa_checkpoint(pa_ctx *c, void *host_buf, size_t *bytes)
+{
+    if (!c || !bytes) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const size_t need = sizeof(CkptHeader) + c->lo.total;
+    if (!host_buf) {
+        *bytes = need;
+        return PA_OK;
+    }
+    if (*bytes < need) return PA_ERR_ARG;
+    CkptHeader h = {CKPT_MAGIC, CKPT_VERSION, (uint32_t)c->repr, c->lo.total, c->n_runs, c->i, c->phase,
+                    c->lo.npop_ctx};
+    std::memcpy(host_buf, &h, sizeof(h));
+    PA_HIP(c, hipMemcpyAsync((uint8_t *)host_buf + sizeof(h), c->ws, c->lo.total, hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    *bytes = need;
+    return PA_OK;
+}
+
+pa_status pa_restore(pa_ctx *c, const void *host_buf, size_t bytes)
+{
+    if (!c || !host_buf || bytes < sizeof(CkptHeader)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    CkptHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (h.magic != CKPT_MAGIC || h.version != CKPT_VERSION || h.repr != (uint32_t)c->repr ||
+        h.ws_used != c->lo.total || h.n_runs != c->n_runs || bytes < sizeof(h) + h.ws_used)
+        return PA_ERR_ARG;
+    PA_HIP(c, hipMemcpyAsync(c->ws, (const uint8_t *)host_buf + sizeof(h), c->lo.total, hipMemcpyHostToDevice,
+                             c->stream));
+    // device records hold absolute pointers: rewrite them for this workspace
+    PA_HIP(c, hipMemcpyAsync((void *)c->lc.runs, c->hinfo.data(), sizeof(RunInfo) * c->n_runs, hipMemcpyHostToDevice,
+                             c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    c->i = h.i;
+    c->phase = h.phase;
+    return PA_OK;
+}
+
+pa_status pa_set_tuning(pa_ctx *c, int32_t L, int32_t threads, int32_t groups_per_wg)
+{
+    if (!c || L < 4 || threads != 256 || groups_per_wg != 1) return PA_ERR_ARG;
+    return PA_OK;
+}
+
+const char *pa_last_error(pa_ctx *c)
+{
+    if (!c) return "no context";
+    return c->last == hipSuccess ? "none" : hipGetErrorString(c->last);
+}
+
+pa_status pa_destroy(pa_ctx *c)
+{
+    if (!c) return PA_ERR_ARG;
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph_def) (void)hipGraphDestroy(c->graph_def);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return PA_OK;
+}
+
+}  // extern "C"

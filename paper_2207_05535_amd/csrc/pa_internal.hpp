@@ -1,0 +1,94 @@
+// pa_internal.hpp -- device-side data model shared by the host code and the
+// kernels of libpa.so.
+//
+// Everything a kernel needs about a run lives in a RunInfo record in device
+// memory (constant after creation), and everything that changes from step to
+// step lives in a PopState record per (run, population).  Kernels read the
+// temperature index, the current spin buffer and the population size from
+// PopState, so a temperature step is a fixed sequence of launches whose
+// arguments never change: it can be captured once as a HIP graph and
+// replayed for every step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pa.h"
+
+namespace pa {
+
+// Philox counter tags: the top nibble of the fourth counter word says what a
+// draw is for, so draws for different purposes never collide.
+constexpr uint32_t TAG_SWEEP = 1u;
+constexpr uint32_t TAG_NI = 2u;
+constexpr uint32_t TAG_MN = 3u;
+constexpr uint32_t TAG_INIT = 4u;
+constexpr uint32_t TAG_J = 5u;
+
+constexpr int MAX_POP = 2;
+
+// Population-wide scans and reductions work on chunks of CH replicas: one
+// workgroup of CH_THREADS threads, CH_PER consecutive replicas per thread.
+constexpr int CH_THREADS = 256;
+constexpr int CH_PER = 8;
+constexpr int CH = CH_THREADS * CH_PER;
+constexpr int NACC = 10;  // measure accumulators, see Acc
+
+enum Acc { A_SUME = 0, A_SUME2, A_SUMABSM, A_SUMM2, A_NPAIRS, A_SUMQ, A_SUMABSQ, A_SUMQ2,
+           A_SUMQL, A_SUMQL2 };
+
+struct RunInfo {
+    int32_t L, N, npop, R, R_cap, theta, K, model, resampling, overlap, qhist, groups_cap;
+    uint32_t key0, key1;
+    int32_t run;            // index of this run in the context
+    int32_t pad0;
+    // device pointers into the caller's workspace
+    uint8_t *spins[MAX_POP][2];   // int8: [group][site][64] bytes; MSC: [group][site] u64
+    int32_t *E[MAX_POP][2];       // energies [R_cap]
+    int32_t *fam[MAX_POP][2];     // family labels [R_cap]
+    int32_t *r[MAX_POP];          // descendant counts [R_cap]
+    int32_t *C[MAX_POP];          // exclusive prefix of r [R_cap + 1]
+    int32_t *parent[MAX_POP];     // child -> parent [R_cap]
+    uint64_t *P[MAX_POP];         // multinomial prefix of X [R_cap + 1]
+    int32_t *famcnt[MAX_POP];     // family histogram [R]
+    double *partS[MAX_POP];       // per chunk: partial sum of x_j
+    uint64_t *tot64[MAX_POP];     // per chunk: sum of X_j
+    uint64_t *base64[MAX_POP];    // per chunk: exclusive prefix of tot64
+    int32_t *tot32[MAX_POP];      // per chunk: sum of r_j
+    int32_t *base32[MAX_POP];     // per chunk: exclusive prefix of tot32
+    pa_obs *obs;                  // records, [K][n_runs][n_pop] (context-wide array)
+    int32_t *qh;                  // [n_pop][K][N+1] or nullptr
+    uint8_t *jbits;               // [N]: bit0 = J_R(n) < 0, bit1 = J_D(n) < 0
+    const uint64_t *tabX;         // [K][N+1]  floor(exp(-dbeta_i 4k) 2^40)
+    const double *tabx;           // [K][N+1]  exp(-dbeta_i 4k)
+    const uint64_t *tabT;         // [K][2]    Metropolis thresholds for dE = 4, 8
+    const double *beta;           // [K]
+};
+
+struct PopState {
+    int32_t i;        // temperature index of the current population
+    int32_t cur;      // current spin buffer (0/1)
+    int32_t src;      // buffer the last resampling copied from
+    int32_t Rprev;    // population size before the last resampling
+    int32_t Rcur;     // current population size
+    int32_t status;   // PA_OK or a sticky per-run failure
+    int32_t Emin;     // minimum energy of the current population
+    int32_t moved;    // 1 if this population advanced in the current step
+    double lnQ, A, S;
+    uint64_t SX;
+    int64_t acc[NACC];
+    int32_t EminAcc;
+    int32_t pad1;
+};
+
+struct Item {         // one replica group (64 replicas) of one (run, pop)
+    int32_t run, pop, group, pad;
+};
+
+struct ChunkItem {    // one chunk of CH replicas of one (run, pop)
+    int32_t run, pop, chunk, pad;
+};
+
+__host__ __device__ inline int n_pop_of(int overlap) { return overlap == PA_Q_TWO_POP ? 2 : 1; }
+
+}  // namespace pa

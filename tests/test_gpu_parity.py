@@ -1,0 +1,348 @@
+"""GPU parity: the HIP path through the C ABI versus the CPU oracle.
+
+Bit-exact: spins, energies, family labels, descendant counts, population
+sizes, every integer sum, overlap histograms.  FP64 (ln Q, A and every
+weighted average): relative 1e-10 with an absolute floor of 1e-12, the
+tolerance the method's FP64 steps are held to (summation order and the
+device's log/exp may differ from the oracle's in the last few ulps).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2207_05535_amd as pa  # noqa: E402
+
+RTOL, ATOL = 1e-10, 1e-12
+INT_FIELDS = ["R_i", "sumE", "sumE2", "sumAbsM", "sumM2", "nPairs", "sumQ", "sumAbsQ", "sumQ2",
+              "sumQl", "sumQl2", "famSumSq", "famMax", "nFam", "Emin", "status"]
+REPRS = ["int8", "msc"]
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def close(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.all(np.abs(a - b) <= RTOL * np.maximum(np.abs(a), np.abs(b)) + ATOL)
+
+
+def assert_obs_equal(g, o, where=""):
+    for f in INT_FIELDS:
+        assert np.array_equal(np.asarray(g[f]), np.asarray(o[f])), f"{where}: field {f}: {g[f]} != {o[f]}"
+    for f in ("lnQ", "A"):
+        assert close(g[f], o[f]), f"{where}: field {f}: {g[f]} vs {o[f]}"
+
+
+def assert_state_equal(ctx, orc, run, where=""):
+    for p in range(orc.npop):
+        so, Eo, fo, sto = orc.state(p)
+        sg, Eg, fg, rg = ctx.state(run, p)
+        if sto != 0:
+            continue
+        assert sg.shape == so.shape, f"{where} pop {p}: R_i {sg.shape[0]} != {so.shape[0]}"
+        assert np.array_equal(sg, so), f"{where} pop {p}: spins differ"
+        assert np.array_equal(Eg, Eo), f"{where} pop {p}: energies differ"
+        assert np.array_equal(fg, fo), f"{where} pop {p}: families differ"
+        ro, _, _ = orc.counts(p)
+        assert np.array_equal(rg, ro), f"{where} pop {p}: resampling counts differ"
+
+
+def stepwise_parity(desc, repr_, state_every=1, qhist=False):
+    say(f"stepwise parity {repr_}: L={desc['L']} R={desc['R']} K={desc['K']} model={desc['model']} "
+        f"res={desc['resampling']} ov={desc['overlap']}")
+    orc = oracle.OracleRun(desc)
+    ctx = pa.Context([desc], repr_)
+    assert_obs_equal(ctx.obs()[0, :, 0], orc.obs()[:, 0], "i=0")
+    assert_state_equal(ctx, orc, 0, "i=0")
+    for i in range(1, desc["K"]):
+        orc.step(i)
+        g = ctx.step(i, read=True)
+        assert_obs_equal(g[0], orc.obs()[:, i], f"i={i}")
+        if state_every and (i % state_every == 0 or i == desc["K"] - 1):
+            assert_state_equal(ctx, orc, 0, f"i={i}")
+    assert_obs_equal(ctx.obs()[0], orc.obs(), "all records")
+    if qhist:
+        assert np.array_equal(ctx.qhist(0), orc.qhist())
+    ctx.close()
+
+
+# ------------------------------------------------------------ small, whole
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_fm_L8_R1000_full_schedule(repr_):
+    """Ferromagnet L=8, R=1000, beta 0->1 in 101 points, theta=10,
+    multinomial: every record and the full population at every step."""
+    stepwise_parity(W.fm_L8_R1000(), repr_)
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_fm_nearest_integer(repr_):
+    stepwise_parity(W.fm_L8_R1000(m=3, resampling=W.NEAREST_INT), repr_, state_every=5)
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_ea_two_populations_with_histograms(repr_):
+    d = W.run_desc(16, W.EA_PMJ, seed=77, disorder_seed=5, R=700, theta=3, K=31, beta_f=3.0,
+                   resampling=W.NEAREST_INT, overlap=W.Q_TWO_POP, qhist=1)
+    stepwise_parity(d, repr_, state_every=3, qhist=True)
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_ea_index_shift_ragged(repr_):
+    d = W.run_desc(12, W.EA_PMJ, seed=99, disorder_seed=8, R=333, theta=2, K=26, beta_f=2.0,
+                   overlap=W.Q_INDEX_SHIFT, qhist=1)
+    stepwise_parity(d, repr_, state_every=2, qhist=True)
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+@pytest.mark.parametrize("L,R,theta", [(4, 1, 3), (4, 63, 1), (6, 64, 2), (10, 65, 1), (4, 130, 0)])
+def test_edge_sizes(repr_, L, R, theta):
+    """Smallest lattice, single replica, group-boundary population sizes,
+    theta = 0 (no equilibration)."""
+    d = W.run_desc(L, W.FM, seed=1234 + R, R=R, theta=theta, K=12, beta_f=1.5,
+                   resampling=W.NEAREST_INT if R % 2 else W.MULTINOMIAL,
+                   overlap=W.Q_INDEX_SHIFT)
+    stepwise_parity(d, repr_)
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_capacity_overflow_freezes(repr_):
+    d = W.run_desc(4, W.FM, seed=1, R=64, R_cap=64, theta=0, K=20, beta_f=8.0,
+                   resampling=W.NEAREST_INT)
+    stepwise_parity(d, repr_)
+
+
+# -------------------------------------------------- batches, graphs, state
+
+
+def batch_runs():
+    return [
+        W.run_desc(8, W.FM, seed=11, R=200, theta=2, K=16, beta_f=0.6),
+        W.run_desc(16, W.FM, seed=12, R=130, theta=2, K=16, beta_f=0.6, resampling=W.NEAREST_INT),
+        W.run_desc(24, W.FM, seed=13, R=70, theta=1, K=16, beta_f=0.6, overlap=W.Q_INDEX_SHIFT),
+        W.run_desc(32, W.EA_PMJ, seed=14, disorder_seed=3, R=64, theta=1, K=16, beta_f=0.6,
+                   overlap=W.Q_TWO_POP),
+    ]
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_of_uneven_runs(repr_, graph):
+    """Runs of different L, model, resampling and pairing in one context
+    (one launch per kernel for all of them) equal the oracle run alone;
+    with graph=True the K-1 steps are replays of one captured step graph."""
+    runs = batch_runs()
+    say(f"batch {repr_} graph={graph}")
+    ctx = pa.Context(runs, repr_)
+    if graph:
+        ctx.run(1, 16)
+    else:
+        for i in range(1, 16):
+            ctx.step(i)
+    obs = ctx.obs()
+    for r, d in enumerate(runs):
+        orc = oracle.OracleRun(d).run_all()
+        npop = orc.npop
+        assert_obs_equal(obs[r, :npop], orc.obs(), f"run {r}")
+        if npop == 1 and ctx.npop == 2:
+            assert (obs[r, 1]["R_i"] == 0).all()
+        assert_state_equal(ctx, orc, r, f"run {r} final")
+    ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_graph_replays_interleaved_with_eager(repr_):
+    """Graph replays mixed with eager steps and host synchronisation give
+    the same records as the oracle at every step."""
+    d = W.run_desc(8, W.EA_PMJ, seed=5, disorder_seed=2, R=300, theta=2, K=13, beta_f=2.0,
+                   resampling=W.NEAREST_INT, overlap=W.Q_INDEX_SHIFT)
+    ctx = pa.Context([d], repr_)
+    ctx.run(1, 3)
+    torch.cuda.synchronize()
+    ctx.step(3)
+    ctx.run(4, 8)
+    ctx.step(8, read=True)
+    ctx.run(9, 13)
+    orc = oracle.OracleRun(d).run_all()
+    assert_obs_equal(ctx.obs()[0], orc.obs(), "records")
+    assert_state_equal(ctx, orc, 0, "final")
+    ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_checkpoint_restore_bit_exact(repr_):
+    d = W.run_desc(8, W.FM, seed=8, R=500, theta=3, K=21, beta_f=1.0, resampling=W.NEAREST_INT,
+                   overlap=W.Q_INDEX_SHIFT)
+    ctx = pa.Context([d], repr_)
+    for i in range(1, 9):
+        ctx.step(i)
+    ck = ctx.checkpoint()
+    for i in range(9, 21):
+        ctx.step(i)
+    first = ctx.obs().copy()
+    s1 = ctx.state(0, 0)
+    ctx.restore(ck)
+    for i in range(9, 21):
+        ctx.step(i)
+    second = ctx.obs()
+    s2 = ctx.state(0, 0)
+    assert first.tobytes() == second.tobytes()
+    for a, b in zip(s1, s2):
+        assert np.array_equal(a, b)
+    # and into a fresh context with another workspace
+    ctx2 = pa.Context([d], repr_)
+    ctx2.restore(ck)
+    for i in range(9, 21):
+        ctx2.step(i)
+    assert ctx2.obs().tobytes() == first.tobytes()
+    ctx.close()
+    ctx2.close()
+
+
+def test_out_of_order_calls_rejected():
+    d = W.run_desc(8, W.FM, R=64, theta=1, K=5, beta_f=0.5)
+    ctx = pa.Context([d], "msc")
+    with pytest.raises(pa.PAError) as e:
+        pa.pa_resample(ctx.h, 1)
+    assert e.value.status == pa.PA_ERR_STATE
+    with pytest.raises(pa.PAError):
+        pa.pa_anneal_step(ctx.h, 2)
+    ctx.step(1)
+    with pytest.raises(pa.PAError):
+        pa.pa_run(ctx.h, 3, 4)
+    ctx.close()
+
+
+# ----------------------------------------------------------- weighted average
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+@pytest.mark.parametrize("kind", [pa.PA_W_FULL, pa.PA_W_SIMPLE])
+def test_weighted_average_parity(repr_, kind):
+    """Sec. IV on the device (FP64 log-sum-exp) versus the oracle."""
+    M = 8
+    runs = [W.run_desc(6, W.EA_PMJ, seed=300 + m, disorder_seed=1, R=150, R_cap=260, theta=2, K=14,
+                       beta_f=2.0, resampling=W.NEAREST_INT, overlap=W.Q_INDEX_SHIFT)
+            for m in range(2 * M)]
+    ctx = pa.Context(runs, repr_)
+    ctx.run(1, 14)
+    got = ctx.weighted_average(M, kind, 0)
+    obs = np.stack([oracle.OracleRun(d).run_all().obs()[0] for d in runs])
+    for grp in range(2):
+        ref = oracle.weighted_average(obs[grp * M:(grp + 1) * M], runs[0]["beta"], 36, 150, kind)
+        assert np.array_equal(got[grp]["n_included"], ref["n_included"])
+        for f in pa.PA_WAVG_DTYPE.names:
+            if f in ("n_included", "_pad"):
+                continue
+            assert close(got[grp][f], ref[f]), (grp, f, got[grp][f], ref[f])
+    ctx.close()
+
+
+# --------------------------------------------------------- full-size samples
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_full_size_fm_L64_R100k_first_step(repr_):
+    """The L=64, R=1e5 ferromagnet at full size: records of temperatures 0
+    and 1 (every integer sum, ln Q_1, A_1), all descendant counts, and the
+    spins of sampled replica groups after the first theta = 10 sweeps."""
+    d = W.fm_L64_R100k()
+    groups = [0, 1, 777, (d["R"] - 1) // 64]
+    say(f"full size L=64 R=1e5 {repr_}")
+    orc = oracle.OracleRun(d)
+    orc.anneal_step(1)
+    orc.resample(1)
+    ro, _, _ = orc.counts(0)
+    orc.sweep_groups(1, groups)
+    so, Eo, fo, _ = orc.state(0)
+    ctx = pa.Context([d], repr_)
+    obs0 = ctx.obs()[0, :, 0]
+    assert_obs_equal(obs0, orc.obs()[:, 0], "i=0")
+    g = ctx.step(1, read=True)[0]
+    sg, Eg, fg, rg = ctx.state(0, 0)
+    assert np.array_equal(rg, ro)
+    assert np.array_equal(fg, fo)
+    for gr in groups:
+        sl = slice(64 * gr, min(64 * gr + 64, d["R"]))
+        assert np.array_equal(sg[sl], so[sl]), f"group {gr}"
+        assert np.array_equal(Eg[sl], Eo[sl]), f"group {gr} energies"
+    # ln Q_1 and A_1 of step (ii) at full size (the oracle's other sums are
+    # not comparable: it swept only the sampled groups)
+    orc.measure(1)
+    o_ref = orc.obs()[0, 1]
+    assert close(g["lnQ"], o_ref["lnQ"]) and close(g["A"], o_ref["A"])
+    o1 = g
+    # integer sums at full size against the returned configurations
+    E = sg.astype(np.int64)
+    Ecalc = -(E.reshape(-1, 64, 64) * np.roll(E.reshape(-1, 64, 64), -1, 2)).sum((1, 2)) \
+        - (E.reshape(-1, 64, 64) * np.roll(E.reshape(-1, 64, 64), -1, 1)).sum((1, 2))
+    assert np.array_equal(Ecalc, Eg)
+    M = E.sum(1)
+    assert o1["sumE"] == Ecalc.sum() and o1["sumE2"] == (Ecalc * Ecalc).sum()
+    assert o1["sumAbsM"] == np.abs(M).sum() and o1["sumM2"] == (M * M).sum()
+    ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_full_size_ea_L32_two_pop_first_step(repr_):
+    """EA +-J L=32, two populations of 2e5 on one disorder: records of
+    temperature 0 (overlaps of 2e5 pairs) and sampled groups after step 1."""
+    d = W.ea_L32_two_pop()
+    groups = [0, 1562, 3124]
+    say(f"full size EA L=32 2x2e5 {repr_}")
+    orc = oracle.OracleRun(d)
+    ctx = pa.Context([d], repr_)
+    assert_obs_equal(ctx.obs()[0, :, 0], orc.obs()[:, 0], "i=0")
+    orc.anneal_step(1)
+    orc.resample(1)
+    counts = [orc.counts(p)[0] for p in range(2)]
+    orc.sweep_groups(1, groups)
+    ctx.step(1)
+    for p in range(2):
+        so, Eo, fo, _ = orc.state(p)
+        sg, Eg, fg, rg = ctx.state(0, p)
+        assert np.array_equal(rg, counts[p])
+        assert np.array_equal(fg, fo)
+        for gr in groups:
+            sl = slice(64 * gr, 64 * gr + 64)
+            assert np.array_equal(sg[sl], so[sl]), f"pop {p} group {gr}"
+            assert np.array_equal(Eg[sl], Eo[sl]), f"pop {p} group {gr} energies"
+    ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_full_size_batched_uneven_sampled_runs(repr_):
+    """4096 FM runs with L in {8,16,24,32} (1024 each), R=2000, in one
+    context; sampled runs (one per L) checked against the oracle over the
+    first 4 temperature steps, replayed from the captured step graph."""
+    runs = W.batched_fm_uneven()
+    say(f"full batch 4096 runs {repr_}")
+    ctx = pa.Context(runs, repr_)
+    if repr_ == "msc":
+        ctx.run(1, 5)
+    else:
+        for i in range(1, 5):
+            ctx.step(i)
+    obs = ctx.obs()
+    for r in (5, 1024 + 17, 2048 + 1000, 3072 + 1023):
+        d = runs[r]
+        orc = oracle.OracleRun(d)
+        for i in range(1, 5):
+            orc.step(i)
+        assert_obs_equal(obs[r, 0, :5], orc.obs()[0, :5], f"run {r}")
+        assert_state_equal(ctx, orc, r, f"run {r}")
+    ctx.close()
