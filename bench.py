@@ -1,0 +1,309 @@
+#!/usr/bin/env python3
+"""Spin flips per nanosecond of population annealing on one MI355X.
+
+Workload: 2D Ising ferromagnet, L = 64 periodic, R = 100000 replicas,
+beta linear 0 -> 0.6 in 200 points (199 temperature steps), theta = 10
+checkerboard Metropolis sweeps per temperature, multinomial resampling,
+seeded synthetic initial states.
+
+One "step" is one temperature step of the whole hot path: reweighting and
+ln Q (step ii), resampling with contiguous copies (step iii), theta sweeps
+(step iv) and measurement (step v); the timed region ends with the FP64
+weighted average over the runs (Sec. IV).  Flips = attempted single-spin
+updates, sum over steps of theta * R_i * N.
+
+Headline value: the batched path (64 replicas bit-packed per word, lattice
+held in LDS for all theta sweeps, every kernel of a step captured in one HIP
+graph and replayed).  Reported beside it: the plain path (int8 spins, one
+colour of one run per launch, host-driven steps) on the same workload, whose
+records must equal the batched path's bit for bit; the dominant kernel's
+ALU roofline; and the CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue slots per lane on gfx950: 256 CUs x 4 SIMDs x 16 lanes per clock
+# at 2.4 GHz.  A 32x32->64 multiply-add (v_mad_u64_u32) occupies 4 slots.
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic VALU lane-slots of the bit-sliced Metropolis update:
+# one Philox4x32-10 call = 10 rounds x (2 multiply-adds x 4 + 2 three-way XORs)
+# = 100, plus two bit planes of the most-significant-first comparison (64-bit
+# select/and/or/xor, 14 each) = 128 per call; one site update of a 64-replica
+# word (neighbour XORs, bond-count classes, flip) = 38.
+OPS_PER_CALL = 128
+OPS_PER_WORD = 38
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ensure_built():
+    import paper_2207_05535_amd as pa
+    if not os.path.exists(pa.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "metropolis.hpp", "philox.hpp", "pa_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2207_05535_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, launches_units):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    e = t.get(kernel)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def flips_of(obs_rows, desc, i0, i1):
+    N = desc["L"] ** 2
+    return sum(int(obs_rows[i]["R_i"]) * desc["theta"] * N for i in range(i0, i1))
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    f = math.floor(k)
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_gpu(desc, steps, warmup, do_plain):
+    import numpy as np
+    import torch
+
+    import paper_2207_05535_amd as pa
+
+    torch.cuda.set_device(0)
+    K1 = 1 + steps
+    res = {}
+
+    # ---------------- batched path: bit-packed words, graph-replayed steps
+    log(f"batched path: create L={desc['L']} R={desc['R']}")
+    ctx = pa.Context([desc], "msc")
+    ck = ctx.checkpoint()
+    ctx.run(1, 1 + warmup)                       # instantiates the step graph
+    torch.cuda.synchronize()
+    ctx.restore(ck)
+    torch.cuda.synchronize()
+    log(f"batched path: timing {steps} steps")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    ctx.run(1, K1)
+    wavg = ctx.weighted_average(1, pa.PA_W_FULL, 0)   # Sec. IV, FP64 on the device
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall_s = t1 - t0
+    dev_s = ev0.elapsed_time(ev1) / 1e3
+    obs_graph = ctx.obs()[0, 0].copy()
+    flips = flips_of(obs_graph, desc, 1, K1)
+    res["batched"] = dict(wall_s=wall_s, dev_s=dev_s, flips=flips,
+                          free_energy=float(wavg[0]["minus_beta_WF"][steps]))
+
+    # ---------------- same path, eager, with events around every sweep launch
+    log("batched path: per-kernel timing pass")
+    ctx.restore(ck)
+    torch.cuda.synchronize()
+    st0 = ctx.stats()
+    sweep_ms, step_ms = [], []
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for k, i in enumerate(range(1, K1)):
+        a, b, c = evs[k]
+        a.record()
+        ctx.anneal_step(i)
+        ctx.resample(i)
+        b.record()
+        ctx.sweep(i)
+        c.record()
+        ctx.measure(i)
+    done = torch.cuda.Event(enable_timing=True)
+    done.record()
+    torch.cuda.synchronize()
+    for k in range(steps):
+        a, b, c = evs[k]
+        nxt = evs[k + 1][0] if k + 1 < steps else done
+        sweep_ms.append(b.elapsed_time(c))
+        step_ms.append(a.elapsed_time(nxt))
+    st1 = ctx.stats()
+    obs_eager = ctx.obs()[0, 0].copy()
+    assert obs_eager.tobytes() == obs_graph.tobytes(), "graph replay differs from eager steps"
+    words = st1["words"] - st0["words"]
+    calls = st1["calls"] - st0["calls"]
+    res["batched"].update(sweep_ms=sweep_ms, step_ms=step_ms, words=words, calls=calls,
+                          sweep_flips=st1["flips"] - st0["flips"])
+    ctx.close()
+    del ck
+
+    # ---------------- plain path: int8 spins, one colour of one run per launch
+    if do_plain:
+        log("plain path: create")
+        pctx = pa.Context([desc], "int8")
+        pck = pctx.checkpoint()
+        for i in range(1, 1 + warmup):
+            pctx.step(i)
+        torch.cuda.synchronize()
+        pctx.restore(pck)
+        del pck
+        torch.cuda.synchronize()
+        log(f"plain path: timing {steps} steps")
+        sw = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for k, i in enumerate(range(1, K1)):
+            pctx.anneal_step(i)
+            pctx.resample(i)
+            sev[k][0].record()
+            pctx.sweep(i)
+            sev[k][1].record()
+            pctx.measure(i)
+        pw = pctx.weighted_average(1, pa.PA_W_FULL, 0)
+        e1.record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for a, b in sev:
+            sw.append(a.elapsed_time(b))
+        obs_plain = pctx.obs()[0, 0].copy()
+        ints = [f for f in pa.PA_OBS_DTYPE.names if f not in ("lnQ", "A")]
+        same = all(np.array_equal(obs_plain[f][:K1], obs_graph[f][:K1]) for f in ints)
+        same_fp = bool(np.allclose(obs_plain["A"][:K1], obs_graph["A"][:K1], rtol=1e-12, atol=0))
+        res["plain"] = dict(wall_s=t1 - t0, dev_s=e0.elapsed_time(e1) / 1e3, sweep_ms=sw,
+                            bit_exact=bool(same and same_fp),
+                            free_energy=float(pw[0]["minus_beta_WF"][steps]))
+        pctx.close()
+    return res
+
+
+def cpu_baseline(desc, max_seconds=20.0):
+    """The oracle (single-threaded C, as it stands) on a bounded sample of
+    the same workload: R = 2000 of the 1e5 replicas, the same lattice, theta
+    and schedule, whole temperature steps from i = 1 until ~max_seconds."""
+    import oracle
+    import workloads as W
+    d = W.with_(desc, R=2000, R_cap=2000)
+    run = oracle.OracleRun(d)
+    t0 = time.perf_counter()
+    flips = 0
+    i = 0
+    while time.perf_counter() - t0 < max_seconds and i + 1 < d["K"]:
+        i += 1
+        run.step(i)
+        flips += int(run.obs()[0, i]["R_i"]) * d["theta"] * d["L"] ** 2
+    dt = time.perf_counter() - t0
+    return dict(value=flips / dt / 1e9, unit="spin flips/ns", cores=1, kind="oracle",
+                sample=f"L=64 FM, R=2000 (of 100000), theta=10, temperature steps 1..{i} of the "
+                       f"200-point schedule, whole steps (ii)-(v); {flips} flips in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=199)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs one population-annealing "
+              "workload per GPU and uses no collectives; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import workloads as W
+    desc = W.fm_L64_R100k()
+    steps = max(1, min(args.steps, desc["K"] - 1))
+    warmup = max(1, min(args.warmup, desc["K"] - 1))
+    ensure_built()
+    res = run_gpu(desc, steps, warmup, not args.no_plain)
+
+    b = res["batched"]
+    value = b["flips"] / b["wall_s"] / 1e9
+    sweep_avg_s = sum(b["sweep_ms"]) / len(b["sweep_ms"]) / 1e3
+    ops_per_launch = (OPS_PER_CALL * b["calls"] + OPS_PER_WORD * b["words"]) / steps
+    achieved = ops_per_launch / sweep_avg_s
+    traffic = measured_traffic("k_sweep_msc", steps)
+    line = {
+        "metric": "spin flips/ns on 1 MI355X (batched vs plain), % of roofline, p99 latency",
+        "value": round(value, 3),
+        "unit": "spin flips/ns",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(b["wall_s"] * 1e3 / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D Ising ferromagnet L=64 periodic, R=100000, beta 0->0.6 in 200 points, "
+                        "theta=10, multinomial resampling (199 temperature steps)",
+            "L": 64, "R": 100000, "theta": 10, "K": 200, "steps_timed": steps,
+            "path": "batched: 64 replicas per u64 word, lattice in LDS for all sweeps, "
+                    "graph-replayed steps",
+        },
+        "flips": b["flips"],
+        "device_s": round(b["dev_s"], 6),
+        "latency_ms_per_step": {"p50": round(percentile(b["step_ms"], 0.5), 4),
+                                "p99": round(percentile(b["step_ms"], 0.99), 4)},
+        "sweep_kernel": {"name": "k_sweep_msc", "avg_ms": round(sweep_avg_s * 1e3, 4),
+                         "flips_per_ns": round(b["sweep_flips"] / steps / sweep_avg_s / 1e9, 3),
+                         "philox_calls_per_word": round(b["calls"] / max(1, b["words"]), 4)},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4),
+                     "peak": round(PEAK_LANE_OPS / 1e12, 4), "unit": "Tlane-op/s",
+                     "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic},
+    }
+    if "plain" in res:
+        p = res["plain"]
+        N = desc["L"] ** 2
+        plain_sweep_avg = sum(p["sweep_ms"]) / len(p["sweep_ms"]) / 1e3 / (2 * desc["theta"])
+        # algorithmic bytes per int8 colour launch: read every site of the
+        # run once (both colours, 1 byte per spin), write the updated colour
+        bytes_launch = 1.5 * N * desc["R"]
+        line["plain_int8"] = {
+            "flips_per_ns": round(b["flips"] / p["wall_s"] / 1e9, 3),
+            "ms_per_step": round(p["wall_s"] * 1e3 / steps, 4),
+            "sweep_launch_avg_ms": round(plain_sweep_avg * 1e3, 4),
+            "sweep_hbm_GBps": round(bytes_launch / plain_sweep_avg / 1e9, 1),
+            "sweep_hbm_frac": round(bytes_launch / plain_sweep_avg / 1e9 / HBM_PEAK_GBS, 4),
+            "bit_exact_vs_batched": p["bit_exact"],
+        }
+        line["batched_over_plain"] = round(p["wall_s"] / b["wall_s"], 3)
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(desc)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,6 +186,12 @@ pa_status pa_restore(pa_ctx *ctx, const void *host_buf, size_t bytes);
  * Results never depend on the shape. */
 pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_wg);
 
+/* Exact work counters of the sweep kernels since pa_create: host_out[3] =
+ * {site updates of 64-replica words, Philox4x32-10 calls, attempted
+ * single-spin flips}.  Used to express sweep throughput against the
+ * integer-ALU roofline. */
+pa_status pa_read_stats(pa_ctx *ctx, uint64_t *host_out);
+
 /* Text of the first HIP error that made the context fail ("none" if it has
  * not failed).  The string is static; do not free it. */
 const char *pa_last_error(pa_ctx *ctx);

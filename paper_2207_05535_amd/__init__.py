@@ -79,6 +79,7 @@ def lib():
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
             "pa_set_tuning": [vp, i32, i32, i32],
+            "pa_read_stats": [vp, vp],
             "pa_destroy": [vp],
         }
         for name, args in sig.items():
@@ -203,6 +204,12 @@ def pa_set_tuning(h, L, threads, groups_per_wg):
     _chk("pa_set_tuning", lib().pa_set_tuning(h, L, threads, groups_per_wg), h)
 
 
+def pa_read_stats(h):
+    out = np.zeros(3, np.uint64)
+    _chk("pa_read_stats", lib().pa_read_stats(h, _p(out)), h)
+    return out
+
+
 def pa_destroy(h):
     _chk("pa_destroy", lib().pa_destroy(h))
 
@@ -294,6 +301,11 @@ class Context:
         out = np.zeros((npop, len(d["beta"]), d["L"] ** 2 + 1), np.int32)
         pa_read_qhist(self.h, run, out)
         return out
+
+    def stats(self):
+        """(word-site updates, Philox calls, attempted flips) of the sweeps."""
+        w, c, f = (int(x) for x in pa_read_stats(self.h))
+        return dict(words=w, calls=c, flips=f)
 
     def checkpoint(self):
         n = pa_checkpoint(self.h)

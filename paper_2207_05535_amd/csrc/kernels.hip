@@ -515,6 +515,20 @@ __global__ void __launch_bounds__(256) k_copy(const Item *items, const RunInfo *
 
 // ------------------------------------------------------------- step (iv)
 
+// One atomic per wavefront: the sweep kernels' exact work counts.
+__device__ __forceinline__ void flush_stats(unsigned long long *stats, uint32_t words, uint32_t calls,
+                                            uint32_t flips)
+{
+    const unsigned long long w = wave_sum<unsigned long long>(words);
+    const unsigned long long c = wave_sum<unsigned long long>(calls);
+    const unsigned long long f = wave_sum<unsigned long long>(flips);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&stats[ST_WORDS], w);
+        atomicAdd(&stats[ST_CALLS], c);
+        atomicAdd(&stats[ST_FLIPS], f);
+    }
+}
+
 __device__ __forceinline__ uint64_t jmask(uint8_t b, int bit) { return ((b >> bit) & 1u) ? ~0ull : 0ull; }
 
 // Plain path: one colour of one run per launch, int8 spins.  A workgroup
@@ -522,7 +536,8 @@ __device__ __forceinline__ uint64_t jmask(uint8_t b, int bit) { return ((b >> bi
 // rows y0-1 .. y0+T (bit-packed, 8 bytes per site) in LDS, then updates its
 // own colour's sites in place in HBM, one site (64 replicas) per thread.
 __global__ void __launch_bounds__(256) k_sweep_int8(const RunInfo *runs, const PopState *st, int run,
-                                                     int pop, int s, int colour, int T, int ntiles)
+                                                     int pop, int s, int colour, int T, int ntiles,
+                                                     unsigned long long *stats)
 {
     extern __shared__ uint64_t nb[];
     const RunInfo &R = runs[run];
@@ -549,6 +564,8 @@ __global__ void __launch_bounds__(256) k_sweep_int8(const RunInfo *runs, const P
     const Thresholds Th = thresholds_of(R.tabT, i);
     const uint32_t c3 = (TAG_SWEEP << 28) | ((uint32_t)pop << 24) | (uint32_t)s;
     const uint64_t valid = (Rc - g * 64 >= 64) ? ~0ull : ((1ull << (Rc - g * 64)) - 1);
+    const uint32_t lanes = (uint32_t)__popcll(valid);
+    uint32_t nwords = 0, ncalls = 0;
     for (int idx = threadIdx.x; idx < rows * half; idx += blockDim.x) {
         const int yy = idx / half, m = idx - yy * half;
         const int y = y0 + yy;
@@ -566,7 +583,8 @@ __global__ void __launch_bounds__(256) k_sweep_int8(const RunInfo *runs, const P
         const uint8_t jn = R.jbits[n];
         const uint64_t F = flip_mask(w, wr, wl, wd, wu, jmask(jn, 0), jmask(R.jbits[y * L + xl], 0),
                                      jmask(jn, 1), jmask(R.jbits[yu * L + x], 1), Th, valid,
-                                     (uint32_t)n, (uint32_t)g, (uint32_t)i, c3, R.key0, R.key1);
+                                     (uint32_t)n, (uint32_t)g, (uint32_t)i, c3, R.key0, R.key1, ncalls);
+        ++nwords;
         if (F) {
             apply64(v, F);
             p[0] = v[0];
@@ -575,12 +593,14 @@ __global__ void __launch_bounds__(256) k_sweep_int8(const RunInfo *runs, const P
             p[3] = v[3];
         }
     }
+    flush_stats(stats, nwords, ncalls, nwords * lanes);
 }
 
 // Batched path: every (run, pop, group) item of the context in one launch;
 // the group's lattice (N words) and couplings stay in LDS for all theta
 // sweeps, split by colour so that a colour's sites are contiguous.
-__global__ void __launch_bounds__(256) k_sweep_msc(const Item *items, const RunInfo *runs, const PopState *st)
+__global__ void __launch_bounds__(256) k_sweep_msc(const Item *items, const RunInfo *runs, const PopState *st,
+                                                    unsigned long long *stats)
 {
     extern __shared__ uint64_t lat[];
     const Item it = items[blockIdx.x];
@@ -602,6 +622,8 @@ __global__ void __launch_bounds__(256) k_sweep_msc(const Item *items, const RunI
     const Thresholds Th = thresholds_of(R.tabT, i);
     const uint32_t c3p = (TAG_SWEEP << 28) | ((uint32_t)it.pop << 24);
     const uint64_t valid = (Rc - g * 64 >= 64) ? ~0ull : ((1ull << (Rc - g * 64)) - 1);
+    const uint32_t lanes = (uint32_t)__popcll(valid);
+    uint32_t nwords = 0, ncalls = 0;
     for (int s = 0; s < R.theta; ++s) {
         for (int colour = 0; colour < 2; ++colour) {
             __syncthreads();
@@ -619,7 +641,9 @@ __global__ void __launch_bounds__(256) k_sweep_msc(const Item *items, const RunI
                                              oth[yd * half + m], oth[yu * half + m], jmask(jn, 0),
                                              jmask(jb[y * L + xl], 0), jmask(jn, 1),
                                              jmask(jb[yu * L + x], 1), Th, valid, (uint32_t)n,
-                                             (uint32_t)g, (uint32_t)i, c3p | (uint32_t)s, R.key0, R.key1);
+                                             (uint32_t)g, (uint32_t)i, c3p | (uint32_t)s, R.key0, R.key1,
+                                             ncalls);
+                ++nwords;
                 own[k] = w ^ F;
             }
         }
@@ -629,6 +653,7 @@ __global__ void __launch_bounds__(256) k_sweep_msc(const Item *items, const RunI
         const int y = n / L, x = n - y * L;
         base[n] = lat[((x + y) & 1) * nh + y * half + (x >> 1)];
     }
+    flush_stats(stats, nwords, ncalls, nwords * lanes);
 }
 
 // -------------------------------------------------------------- step (v)
@@ -1055,7 +1080,7 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
         for (int colour = 0; colour < 2; ++colour)
             for (int p = 0; p < npop; ++p) {
                 k_sweep_int8<<<groups_cap * ntiles, 256, lds, c.stream>>>(c.runs, c.st, run, p, s, colour, T,
-                                                                          ntiles);
+                                                                          ntiles, c.stats);
                 PA_CHECK_LAUNCH();
             }
     return hipSuccess;
@@ -1063,7 +1088,7 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
 
 hipError_t launch_sweep_msc(const LaunchCtx &c, int maxN)
 {
-    k_sweep_msc<<<c.n_items, 256, msc_lds_bytes(maxN), c.stream>>>(c.items, c.runs, c.st);
+    k_sweep_msc<<<c.n_items, 256, msc_lds_bytes(maxN), c.stream>>>(c.items, c.runs, c.st, c.stats);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ struct LaunchCtx {
     int n_runs, npop_ctx;
     int repr;
     bool any_multinomial;
+    unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
     hipStream_t stream;
 };
 

@@ -31,7 +31,7 @@ __device__ __forceinline__ uint64_t flip_mask(uint64_t w, uint64_t nr, uint64_t 
                                               uint64_t nu, uint64_t jr, uint64_t jl, uint64_t jd,
                                               uint64_t ju, const Thresholds &T, uint64_t valid,
                                               uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                              uint32_t k0, uint32_t k1)
+                                              uint32_t k0, uint32_t k1, uint32_t &calls)
 {
     const uint64_t d0 = w ^ nr ^ jr;
     const uint64_t d1 = w ^ nl ^ jl;
@@ -48,6 +48,7 @@ __device__ __forceinline__ uint64_t flip_mask(uint64_t w, uint64_t nr, uint64_t 
     uint64_t acc = 0;
     for (uint32_t c = 0; und != 0 && c < 16; ++c) {
         const u32x4 o = philox10(c0 | (c << 20), c1, c2, c3, k0, k1);
+        ++calls;
         const uint64_t pa_ = (uint64_t)o.x | ((uint64_t)o.y << 32);
         const uint64_t pb_ = (uint64_t)o.z | ((uint64_t)o.w << 32);
         const int sh = 31 - 2 * (int)c;

@@ -61,7 +61,7 @@ struct TableOff {
 struct Layout {
     std::vector<RunOff> runs;
     std::vector<TableOff> tables;
-    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg;
+    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats;
     int n_items, n_chunk_items, npop_ctx, Kmax, maxN;
     size_t total;
 };
@@ -109,6 +109,7 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     Lo.runinfo = P.take(sizeof(RunInfo) * n_runs);
     Lo.popstate = P.take(sizeof(PopState) * n_runs * MAX_POP);
     Lo.dseed = P.take(sizeof(uint64_t) * n_runs);
+    Lo.stats = P.take(sizeof(uint64_t) * NSTAT);
     Lo.n_items = 0;
     Lo.n_chunk_items = 0;
     for (int r = 0; r < n_runs; ++r) {
@@ -393,6 +394,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.npop_ctx = Lo.npop_ctx;
     c->lc.repr = repr;
     c->lc.any_multinomial = c->any_multinomial;
+    c->lc.stats = at<unsigned long long>(c, Lo.stats);
     c->lc.stream = c->stream;
 
     auto fail = [&](pa_status s) {
@@ -449,6 +451,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
             ok = launch_fill_u32(at<void>(c, o.qh), 0, (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1), s) ==
                  hipSuccess;
     }
+    ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, 2 * NSTAT, s) == hipSuccess;
     ok = ok && launch_fill_u32(at<void>(c, Lo.obs), 0,
                                sizeof(pa_obs) / 4 * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx, s) == hipSuccess;
     ok = ok && launch_init(c->lc, at<uint64_t>(c, Lo.dseed)) == hipSuccess;
@@ -694,6 +697,15 @@ pa_status pa_restore(pa_ctx *c, const void *host_buf, size_t bytes)
 pa_status pa_set_tuning(pa_ctx *c, int32_t L, int32_t threads, int32_t groups_per_wg)
 {
     if (!c || L < 4 || threads != 256 || groups_per_wg != 1) return PA_ERR_ARG;
+    return PA_OK;
+}
+
+pa_status pa_read_stats(pa_ctx *c, uint64_t *host_out)
+{
+    if (!c || !host_out) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    PA_HIP(c, hipMemcpyAsync(host_out, c->lc.stats, sizeof(uint64_t) * 3, hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
     return PA_OK;
 }
 

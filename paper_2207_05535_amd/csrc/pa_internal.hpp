@@ -81,6 +81,10 @@ struct PopState {
     int32_t pad1;
 };
 
+// Work counters of the sweep kernels (exact, for the ALU roofline):
+// word-site updates (64 replicas of one site), Philox calls, attempted flips.
+enum Stat { ST_WORDS = 0, ST_CALLS = 1, ST_FLIPS = 2, NSTAT = 4 };
+
 struct Item {         // one replica group (64 replicas) of one (run, pop)
     int32_t run, pop, group, pad;
 };
