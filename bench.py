@@ -30,16 +30,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue slots per lane on gfx950: 256 CUs x 4 SIMDs x 16 lanes per clock
-# at 2.4 GHz.  A 32x32->64 multiply-add (v_mad_u64_u32) occupies 4 slots.
+# VALU issue rate of gfx950: 256 CUs x 4 SIMDs x 16 lanes per clock at
+# 2.4 GHz = one 32-bit lane-operation per lane-slot.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Algorithmic VALU lane-slots of the bit-sliced Metropolis update:
-# one Philox4x32-10 call = 10 rounds x (2 multiply-adds x 4 + 2 three-way XORs)
-# = 100, plus two bit planes of the most-significant-first comparison (64-bit
-# select/and/or/xor, 14 each) = 128 per call; one site update of a 64-replica
-# word (neighbour XORs, bond-count classes, flip) = 38.
-OPS_PER_CALL = 128
-OPS_PER_WORD = 38
+# Algorithmic 32-bit VALU operations of the bit-sliced Metropolis update
+# (each 64-bit word operation counts as two):
+# one Philox4x32-10 call = 10 rounds x (2 v_mad_u64_u32 + 2 three-input XORs)
+# = 40, plus two bit planes of the most-significant-first comparison
+# (select, win, tie, or: 4 per 32-bit half) = 16, so 56 per call; one site
+# update of a 64-replica word (four neighbour XORs, the two bond-count
+# classes, the flip and the undecided mask) = 28.
+OPS_PER_CALL = 56
+OPS_PER_WORD = 28
 HBM_PEAK_GBS = 8000.0
 
 

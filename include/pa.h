@@ -180,11 +180,15 @@ pa_status pa_checkpoint(pa_ctx *ctx, void *host_buf, size_t *bytes);
  * uninterrupted run bit for bit. */
 pa_status pa_restore(pa_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Kernel shape knobs, chosen by the autotuner per (L, representation):
- * threads per workgroup of the multi-spin sweep and replica groups per
- * workgroup.  A shape that does not fit is rejected with PA_ERR_ARG.
- * Results never depend on the shape. */
-pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_wg);
+/* Launch-shape knobs of the batched sweep, chosen by the autotuner per
+ * lattice size L: threads per workgroup (64..1024, a power of two, shared by
+ * all L of the context), replica groups per workgroup for this L, and the
+ * number of Philox calls every site makes in lockstep before the undecided
+ * sites are compacted (0..16).  A shape that does not fit the device is
+ * rejected with PA_ERR_ARG and the previous shape is kept.  Results never
+ * depend on the shape. */
+pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_wg,
+                        int32_t dense_calls);
 
 /* Exact work counters of the sweep kernels since pa_create: host_out[3] =
  * {site updates of 64-replica words, Philox4x32-10 calls, attempted

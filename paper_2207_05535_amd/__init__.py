@@ -78,7 +78,7 @@ def lib():
             "pa_read_state": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
-            "pa_set_tuning": [vp, i32, i32, i32],
+            "pa_set_tuning": [vp, i32, i32, i32, i32],
             "pa_read_stats": [vp, vp],
             "pa_destroy": [vp],
         }
@@ -200,8 +200,8 @@ def pa_restore(h, buf):
     _chk("pa_restore", lib().pa_restore(h, _p(buf), len(buf)), h)
 
 
-def pa_set_tuning(h, L, threads, groups_per_wg):
-    _chk("pa_set_tuning", lib().pa_set_tuning(h, L, threads, groups_per_wg), h)
+def pa_set_tuning(h, L, threads, groups_per_wg, dense_calls=3):
+    _chk("pa_set_tuning", lib().pa_set_tuning(h, L, threads, groups_per_wg, dense_calls), h)
 
 
 def pa_read_stats(h):
@@ -301,6 +301,9 @@ class Context:
         out = np.zeros((npop, len(d["beta"]), d["L"] ** 2 + 1), np.int32)
         pa_read_qhist(self.h, run, out)
         return out
+
+    def set_tuning(self, L, threads, groups_per_wg, dense_calls=3):
+        pa_set_tuning(self.h, L, threads, groups_per_wg, dense_calls)
 
     def stats(self):
         """(word-site updates, Philox calls, attempted flips) of the sweeps."""

@@ -63,6 +63,66 @@ __device__ __forceinline__ int wave_min(int v)
 
 __device__ __forceinline__ bool pop_active(const PopState &S) { return S.moved && S.status == PA_OK; }
 
+// 64 x 64 bit transpose across a wavefront: lane r holds row r (bit c =
+// element (r, c)); on return lane r holds column r.  Six block-swap stages;
+// at stage j a lane exchanges the half-blocks whose column bit j differs
+// from its own row bit j with lane r ^ j.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int j = 32 >> st;
+        const uint64_t m = masks[st];
+        const uint64_t y = __shfl_xor(x, j, 64);
+        x = (lane & j) ? ((x & ~m) | ((y & ~m) >> j)) : ((x & m) | ((y & m) << j));
+    }
+    return x;
+}
+
+// Bit-sliced (vertical) counters: plane k holds bit k of 64 per-lane counts.
+constexpr int VB = 6;   // counts up to 63 per lane
+
+__device__ __forceinline__ void vinc(uint64_t (&p)[VB], uint64_t x)
+{
+#pragma unroll
+    for (int k = 0; k < VB; ++k) {
+        const uint64_t t = p[k] & x;
+        p[k] ^= x;
+        x = t;
+    }
+}
+
+// add the 2-bit per-lane values a + b
+__device__ __forceinline__ void vinc2(uint64_t (&p)[VB], uint64_t a, uint64_t b)
+{
+    const uint64_t s = a ^ b, c = a & b;
+    const uint64_t t0 = p[0] & s;
+    p[0] ^= s;
+    uint64_t x = t0 | c;
+#pragma unroll
+    for (int k = 1; k < VB; ++k) {
+        const uint64_t t = p[k] & x;
+        p[k] ^= x;
+        x = t;
+    }
+}
+
+// Per-lane counts summed over the wavefront: on return lane b holds the
+// total over all lanes of bit b's count, and the planes are cleared.
+__device__ __forceinline__ uint32_t vflush(uint64_t (&p)[VB])
+{
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < VB; ++k) {
+        total += (uint32_t)__popcll(transpose64(p[k])) << k;
+        p[k] = 0;
+    }
+    return total;
+}
+
 // Exclusive scan of one value per thread across a workgroup of BS threads
 // (BS a multiple of 64); returns the exclusive prefix, *total the sum.
 template <typename T, int BS>
@@ -468,9 +528,15 @@ __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, c
 }
 
 // Copy of spins, energies and family labels into the child slots.  One
-// wavefront per 64 children (one replica group); int8: lane = child, one
-// byte per site; MSC: each child's bit gathered from its parent's word and
-// the 64 bits assembled with a wave ballot.
+// wavefront per 64 children (one replica group) and 64 sites at a time.
+// MSC: the children's parents lie in a few consecutive source groups; each
+// source block (64 sites x 64 replicas) is transposed so that a lane holds
+// one replica's 64 sites, every child pulls its parent's row from the lane
+// that holds it, and the child block is transposed back and stored
+// (falls back to a per-site bit gather when the parents span many groups).
+// int8: lane = child, one byte per site.
+constexpr int COPY_MAX_SRC = 4;
+
 template <int REPR>
 __global__ void __launch_bounds__(256) k_copy(const Item *items, const RunInfo *runs, const PopState *st)
 {
@@ -481,31 +547,49 @@ __global__ void __launch_bounds__(256) k_copy(const Item *items, const RunInfo *
     const int Rc = S.Rcur;
     const int G = it.group;
     if (G * 64 >= Rc) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int c = G * 64 + lane;
     const bool valid = c < Rc;
-    const int p = valid ? R.parent[it.pop][c] : 0;
+    const int clast = min(Rc, G * 64 + 64) - 1;
+    const int p = R.parent[it.pop][valid ? c : clast];
     const int N = R.N;
-    const int per = (N + 3) / 4;
-    const int n0 = wv * per, n1 = min(N, n0 + per);
     if (REPR == PA_MSC64) {
-        const uint64_t *src = (const uint64_t *)R.spins[it.pop][S.src] + (size_t)(p >> 6) * N;
+        const uint64_t *src = (const uint64_t *)R.spins[it.pop][S.src];
         uint64_t *dst = (uint64_t *)R.spins[it.pop][S.cur] + (size_t)G * N;
-        const int pb = p & 63;
-        for (int nb = n0; nb < n1; nb += 64) {
-            uint64_t mine = 0;
-            const int cnt = min(64, n1 - nb);
-            for (int k = 0; k < cnt; ++k) {
-                const int bit = valid ? (int)((src[nb + k] >> pb) & 1u) : 0;
-                const uint64_t m = __ballot(bit);
-                if (lane == k) mine = m;
+        const int g_lo = __shfl(p, 0, 64) >> 6;
+        const int g_hi = __shfl(p, 63, 64) >> 6;
+        if (g_hi - g_lo < COPY_MAX_SRC) {
+            for (int n0 = wv * 64; n0 < N; n0 += nw * 64) {
+                const int n = n0 + lane;
+                uint64_t row = 0;
+                for (int gs = g_lo; gs <= g_hi; ++gs) {
+                    const uint64_t x = n < N ? src[(size_t)gs * N + n] : 0ull;
+                    const uint64_t xt = transpose64(x);
+                    const uint64_t v = __shfl(xt, p & 63, 64);
+                    if ((p >> 6) == gs) row = v;
+                }
+                if (!valid) row = 0;
+                const uint64_t out = transpose64(row);
+                if (n < N) dst[n] = out;
             }
-            if (lane < cnt) dst[nb + lane] = mine;
+        } else {
+            const uint64_t *ps = src + (size_t)(p >> 6) * N;
+            const int pb = p & 63;
+            for (int nb = wv * 64; nb < N; nb += nw * 64) {
+                uint64_t mine = 0;
+                const int cnt = min(64, N - nb);
+                for (int k = 0; k < cnt; ++k) {
+                    const int bit = valid ? (int)((ps[nb + k] >> pb) & 1u) : 0;
+                    const uint64_t m = __ballot(bit);
+                    if (lane == k) mine = m;
+                }
+                if (lane < cnt) dst[nb + lane] = mine;
+            }
         }
     } else {
         const uint8_t *src = R.spins[it.pop][S.src] + (size_t)(p >> 6) * N * 64 + (p & 63);
         uint8_t *dst = R.spins[it.pop][S.cur] + (size_t)G * N * 64 + lane;
-        for (int n = n0; n < n1; ++n) dst[(size_t)n * 64] = valid ? src[(size_t)n * 64] : (uint8_t)1;
+        for (int n = wv; n < N; n += nw) dst[(size_t)n * 64] = valid ? src[(size_t)n * 64] : (uint8_t)1;
     }
     if (wv == 0 && valid) {
         R.E[it.pop][S.cur][c] = R.E[it.pop][S.src][p];
@@ -531,33 +615,52 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, uint32_t 
 
 __device__ __forceinline__ uint64_t jmask(uint8_t b, int bit) { return ((b >> bit) & 1u) ? ~0ull : 0ull; }
 
-// Plain path: one colour of one run per launch, int8 spins.  A workgroup
-// takes T rows of one replica group: it stages the other colour's sites of
-// rows y0-1 .. y0+T (bit-packed, 8 bytes per site) in LDS, then updates its
-// own colour's sites in place in HBM, one site (64 replicas) per thread.
-__global__ void __launch_bounds__(256) k_sweep_int8(const RunInfo *runs, const PopState *st, int run,
-                                                     int pop, int s, int colour, int T, int ntiles,
+// Plain path: one colour of one run per launch, int8 spins ([group][site][64
+// replicas] bytes).  A workgroup takes `rows` lattice rows of one replica
+// group (plus one halo row on each side unless it holds the whole lattice).
+// Consecutive lanes load consecutive 16-byte chunks (coalesced), pack their
+// sign bits into an LDS bit-lattice (one 64-bit word per site), and keep the
+// chunks in registers; the colour's sites are then updated from the packed
+// words, and each lane XORs the flips of its chunk back and stores it.
+constexpr int I8_CMAX = 16;   // 16-byte chunks held per thread
+
+__device__ __forceinline__ uint32_t signs16(const uint4 &v)
+{
+    return signs4(v.x) | (signs4(v.y) << 4) | (signs4(v.z) << 8) | (signs4(v.w) << 12);
+}
+
+__global__ void __launch_bounds__(1024) k_sweep_int8(const RunInfo *runs, const PopState *st, int run, int pop,
+                                                     int s, int colour, int T, int ntiles,
                                                      unsigned long long *stats)
 {
-    extern __shared__ uint64_t nb[];
+    extern __shared__ uint64_t sm[];
     const RunInfo &R = runs[run];
     const PopState &S = st[run * MAX_POP + pop];
     if (!pop_active(S)) return;
-    const int g = blockIdx.x / ntiles, tile = blockIdx.x % ntiles;
+    const int g = blockIdx.x / ntiles, tile = blockIdx.x - g * ntiles;
     const int Rc = S.Rcur;
     if (g * 64 >= Rc) return;
     const int L = R.L, N = R.N, half = L >> 1;
     const int y0 = tile * T;
     const int rows = min(T, L - y0);
-    const int co = colour ^ 1;
+    const int halo = rows == L ? 0 : 1;
+    const int nrow = rows + 2 * halo;
+    uint64_t *packed = sm;                              // [nrow][L]
+    uint64_t *fm = sm + (size_t)nrow * L;               // [rows][half]
+    uint16_t *pk16 = (uint16_t *)packed;
     uint8_t *base = R.spins[pop][S.cur] + (size_t)g * N * 64;
-    for (int idx = threadIdx.x; idx < (rows + 2) * half; idx += blockDim.x) {
-        const int rr = idx / half, m = idx - rr * half;
-        const int y = (y0 - 1 + rr + L) % L;
-        const int x = 2 * m + ((y + co) & 1);
-        const uint4 *src = (const uint4 *)(base + (size_t)(y * L + x) * 64);
-        uint4 v[4] = {src[0], src[1], src[2], src[3]};
-        nb[idx] = pack64(v);
+    const int chunks = nrow * L * 4;
+    uint4 reg[I8_CMAX];
+#pragma unroll
+    for (int q = 0; q < I8_CMAX; ++q) {
+        const int c = threadIdx.x + q * blockDim.x;
+        if (c < chunks) {
+            const int site = c >> 2, part = c & 3;
+            const int rr = site / L, x = site - rr * L;
+            const int y = (y0 - halo + rr + L) % L;
+            reg[q] = *(const uint4 *)(base + (size_t)(y * L + x) * 64 + part * 16);
+            pk16[site * 4 + part] = (uint16_t)signs16(reg[q]);
+        }
     }
     __syncthreads();
     const int i = S.i;
@@ -573,170 +676,345 @@ __global__ void __launch_bounds__(256) k_sweep_int8(const RunInfo *runs, const P
         const int n = y * L + x;
         const int xr = x + 1 == L ? 0 : x + 1, xl = x == 0 ? L - 1 : x - 1;
         const int yu = y == 0 ? L - 1 : y - 1;
-        uint4 *p = (uint4 *)(base + (size_t)n * 64);
-        uint4 v[4] = {p[0], p[1], p[2], p[3]};
-        const uint64_t w = pack64(v);
-        const uint64_t wr = nb[(yy + 1) * half + (xr >> 1)];
-        const uint64_t wl = nb[(yy + 1) * half + (xl >> 1)];
-        const uint64_t wd = nb[(yy + 2) * half + m];
-        const uint64_t wu = nb[yy * half + m];
+        const int rc = yy + halo;
+        const int rd = halo ? rc + 1 : (rc + 1 == L ? 0 : rc + 1);
+        const int ru = halo ? rc - 1 : (rc == 0 ? L - 1 : rc - 1);
+        const uint64_t w = packed[rc * L + x];
         const uint8_t jn = R.jbits[n];
-        const uint64_t F = flip_mask(w, wr, wl, wd, wu, jmask(jn, 0), jmask(R.jbits[y * L + xl], 0),
-                                     jmask(jn, 1), jmask(R.jbits[yu * L + x], 1), Th, valid,
-                                     (uint32_t)n, (uint32_t)g, (uint32_t)i, c3, R.key0, R.key1, ncalls);
+        fm[idx] = flip_mask(w, packed[rc * L + xr], packed[rc * L + xl], packed[rd * L + x], packed[ru * L + x],
+                            jmask(jn, 0), jmask(R.jbits[y * L + xl], 0), jmask(jn, 1),
+                            jmask(R.jbits[yu * L + x], 1), Th, valid, (uint32_t)n, (uint32_t)g, (uint32_t)i, c3,
+                            R.key0, R.key1, ncalls);
         ++nwords;
-        if (F) {
-            apply64(v, F);
-            p[0] = v[0];
-            p[1] = v[1];
-            p[2] = v[2];
-            p[3] = v[3];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < I8_CMAX; ++q) {
+        const int c = threadIdx.x + q * blockDim.x;
+        if (c < chunks) {
+            const int site = c >> 2, part = c & 3;
+            const int rr = site / L, x = site - rr * L;
+            const int yy = rr - halo;
+            const int y = (y0 - halo + rr + L) % L;
+            if (yy >= 0 && yy < rows && ((x + y) & 1) == colour) {
+                const uint32_t f = (uint32_t)(fm[yy * half + (x >> 1)] >> (16 * part)) & 0xFFFFu;
+                if (f) {
+                    uint4 v = reg[q];
+                    v.x ^= negmask4(f & 15u);
+                    v.y ^= negmask4((f >> 4) & 15u);
+                    v.z ^= negmask4((f >> 8) & 15u);
+                    v.w ^= negmask4((f >> 12) & 15u);
+                    *(uint4 *)(base + (size_t)(y * L + x) * 64 + part * 16) = v;
+                }
+            }
         }
     }
     flush_stats(stats, nwords, ncalls, nwords * lanes);
 }
 
-// Batched path: every (run, pop, group) item of the context in one launch;
-// the group's lattice (N words) and couplings stay in LDS for all theta
-// sweeps, split by colour so that a colour's sites are contiguous.
-__global__ void __launch_bounds__(256) k_sweep_msc(const Item *items, const RunInfo *runs, const PopState *st,
-                                                    unsigned long long *stats)
+// Batched path: every (run, pop, block of G replica groups) item of the
+// context in one launch.  The G lattices (colour-split, so a colour's sites
+// are contiguous) and the couplings stay in LDS for all theta sweeps.
+//
+// Draw scheduling.  A site needs as many Philox calls as its slowest
+// undecided replica (about 3-4 on average, up to 16).  Each wavefront owns a
+// contiguous range of a colour's sites and works in rounds with one call
+// index per round, uniform across the wavefront:
+//  - dense rounds: chunks of 64 sites are classified (always flip / dE = +4 /
+//    dE = +8) and make calls 0 .. dense-1 in lockstep; nearly every site
+//    needs that many, so few lanes idle;
+//  - sparse rounds: the sites still undecided are kept in a wave-private LDS
+//    list that is compacted in place after every call, so each round's calls
+//    run on full wavefronts.
+// Every site's result is still the plain most-significant-first comparison
+// of its own bit planes; only the order of the work changes.
+template <int LT, bool EA>
+__device__ __forceinline__ void sweep_item(const SweepItem &it, const RunInfo &R, const PopState &S,
+                                           uint64_t *lds, int dense, unsigned long long *stats)
 {
-    extern __shared__ uint64_t lat[];
-    const Item it = items[blockIdx.x];
-    const RunInfo &R = runs[it.run];
-    const PopState &S = st[it.run * MAX_POP + it.pop];
-    if (!pop_active(S)) return;
-    const int g = it.group;
+    const int L = LT ? LT : R.L;
+    const int N = L * L, half = L >> 1, nh = N >> 1;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6, nw = T >> 6;
     const int Rc = S.Rcur;
-    if (g * 64 >= Rc || R.theta == 0) return;
-    const int L = R.L, N = R.N, half = L >> 1, nh = N >> 1;
-    uint8_t *jb = (uint8_t *)(lat + N);
-    uint64_t *base = (uint64_t *)R.spins[it.pop][S.cur] + (size_t)g * N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    const int G = min(it.ngroups, (Rc + 63) / 64 - it.group0);
+    if (G <= 0) return;
+    const int units = G * nh;
+    uint64_t *lat = lds;                                  // [G][2][nh]
+    uint64_t *eu = lds + (size_t)G * N;                   // [units] undecided lanes
+    uint64_t *eo = eu + units;                            // [units] lanes of class dE = +4
+    uint32_t *en = (uint32_t *)(eo + units);              // [units] (LDS word << 16) | site
+    uint8_t *jb = (uint8_t *)(en + units);                // [N] couplings (spin glass)
+    uint64_t *base = (uint64_t *)R.spins[it.pop][S.cur] + (size_t)it.group0 * N;
+    for (int u = tid; u < G * N; u += T) {
+        const int gs = u / N, n = u - gs * N;
         const int y = n / L, x = n - y * L;
-        lat[((x + y) & 1) * nh + y * half + (x >> 1)] = base[n];
-        jb[n] = R.jbits[n];
+        lat[(size_t)gs * N + ((x + y) & 1) * nh + y * half + (x >> 1)] = base[u];
     }
+    if (EA)
+        for (int n = tid; n < N; n += T) jb[n] = R.jbits[n];
     const int i = S.i;
     const Thresholds Th = thresholds_of(R.tabT, i);
     const uint32_t c3p = (TAG_SWEEP << 28) | ((uint32_t)it.pop << 24);
-    const uint64_t valid = (Rc - g * 64 >= 64) ? ~0ull : ((1ull << (Rc - g * 64)) - 1);
-    const uint32_t lanes = (uint32_t)__popcll(valid);
-    uint32_t nwords = 0, ncalls = 0;
+    const int lastg = it.group0 + G - 1;
+    const uint64_t vlast = (Rc - lastg * 64 >= 64) ? ~0ull : ((1ull << (Rc - lastg * 64)) - 1);
+    const int upw = (units + nw - 1) / nw;
+    const int ub = min(units, wv * upw), ue = min(units, ub + upw);
+    const uint64_t lt_mask = __lanemask_lt();
+    uint32_t nwords = 0, ncalls = 0, nflips = 0;
     for (int s = 0; s < R.theta; ++s) {
+        const uint32_t c3 = c3p | (uint32_t)s;
         for (int colour = 0; colour < 2; ++colour) {
             __syncthreads();
-            uint64_t *own = lat + colour * nh;
-            const uint64_t *oth = lat + (colour ^ 1) * nh;
-            for (int k = threadIdx.x; k < nh; k += blockDim.x) {
-                const int y = k / half, m = k - y * half;
-                const int x = 2 * m + ((y + colour) & 1);
-                const int n = y * L + x;
-                const int xr = x + 1 == L ? 0 : x + 1, xl = x == 0 ? L - 1 : x - 1;
-                const int yd = y + 1 == L ? 0 : y + 1, yu = y == 0 ? L - 1 : y - 1;
-                const uint64_t w = own[k];
-                const uint8_t jn = jb[n];
-                const uint64_t F = flip_mask(w, oth[y * half + (xr >> 1)], oth[y * half + (xl >> 1)],
-                                             oth[yd * half + m], oth[yu * half + m], jmask(jn, 0),
-                                             jmask(jb[y * L + xl], 0), jmask(jn, 1),
-                                             jmask(jb[yu * L + x], 1), Th, valid, (uint32_t)n,
-                                             (uint32_t)g, (uint32_t)i, c3p | (uint32_t)s, R.key0, R.key1,
-                                             ncalls);
-                ++nwords;
-                own[k] = w ^ F;
+            int cnt = 0;
+            // dense rounds
+            for (int u0 = ub; u0 < ue; u0 += 64) {
+                const int u = u0 + lane;
+                uint64_t und = 0, one = 0, acc = 0;
+                int addr = 0;
+                uint32_t n = 0, g = 0;
+                if (u < ue) {
+                    const int gs = u / nh, k = u - gs * nh;
+                    const int y = k / half, m = k - y * half;
+                    const int x = 2 * m + ((y + colour) & 1);
+                    const int xr = x + 1 == L ? 0 : x + 1, xl = x == 0 ? L - 1 : x - 1;
+                    const int yd = y + 1 == L ? 0 : y + 1, yu = y == 0 ? L - 1 : y - 1;
+                    addr = gs * N + colour * nh + k;
+                    const uint64_t *oth = lat + (size_t)gs * N + (colour ^ 1) * nh;
+                    const uint64_t w = lat[addr];
+                    uint64_t jr = 0, jl = 0, jd = 0, ju = 0;
+                    if (EA) {
+                        const uint8_t jn = jb[y * L + x];
+                        jr = jmask(jn, 0);
+                        jd = jmask(jn, 1);
+                        jl = jmask(jb[y * L + xl], 0);
+                        ju = jmask(jb[yu * L + x], 1);
+                    }
+                    SiteClass sc = classify<EA>(w, oth[y * half + (xr >> 1)], oth[y * half + (xl >> 1)],
+                                                oth[yd * half + m], oth[yu * half + m], jr, jl, jd, ju);
+                    if (Th.all4) { sc.flip |= sc.one; sc.one = 0; }
+                    if (Th.all8) { sc.flip |= sc.zero; sc.zero = 0; }
+                    const uint64_t valid = it.group0 + gs == lastg ? vlast : ~0ull;
+                    acc = sc.flip;
+                    und = bop3<LUT_OR_AND>(sc.one, sc.zero, valid);
+                    one = sc.one;
+                    n = (uint32_t)(y * L + x);
+                    g = (uint32_t)(it.group0 + gs);
+                    nflips += (uint32_t)__popcll(valid);
+                    ++nwords;
+                }
+                for (int c = 0; c < dense; ++c) {
+                    if (__ballot(und != 0) == 0) break;
+                    if (und != 0) {
+                        draw_step((uint32_t)c, Th, one, und, acc, n, g, (uint32_t)i, c3, R.key0, R.key1);
+                        ++ncalls;
+                    }
+                }
+                if (acc) lat[addr] ^= acc;
+                const uint64_t need = __ballot(und != 0);
+                if (und != 0) {
+                    const int slot = ub + cnt + __popcll(need & lt_mask);
+                    eu[slot] = und;
+                    eo[slot] = one;
+                    en[slot] = ((uint32_t)addr << 16) | n;
+                }
+                cnt += __popcll(need);
+            }
+            // sparse rounds over the compacted list
+            for (int c = dense; c < 16 && cnt > 0; ++c) {
+                int wcnt = 0;
+                for (int e0 = 0; e0 < cnt; e0 += 64) {
+                    const int e = e0 + lane;
+                    uint64_t und = 0, one = 0, acc = 0;
+                    uint32_t pk = 0;
+                    if (e < cnt) {
+                        und = eu[ub + e];
+                        one = eo[ub + e];
+                        pk = en[ub + e];
+                        const int addr = (int)(pk >> 16);
+                        const uint32_t g = (uint32_t)(it.group0 + addr / N);
+                        draw_step((uint32_t)c, Th, one, und, acc, pk & 0xFFFFu, g, (uint32_t)i, c3, R.key0,
+                                  R.key1);
+                        ++ncalls;
+                        if (acc) lat[addr] ^= acc;
+                    }
+                    const uint64_t need = __ballot(und != 0);
+                    if (und != 0) {
+                        const int slot = ub + wcnt + __popcll(need & lt_mask);
+                        eu[slot] = und;
+                        eo[slot] = one;
+                        en[slot] = pk;
+                    }
+                    wcnt += __popcll(need);
+                }
+                cnt = wcnt;
             }
         }
     }
     __syncthreads();
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    for (int u = tid; u < G * N; u += T) {
+        const int gs = u / N, n = u - gs * N;
         const int y = n / L, x = n - y * L;
-        base[n] = lat[((x + y) & 1) * nh + y * half + (x >> 1)];
+        base[u] = lat[(size_t)gs * N + ((x + y) & 1) * nh + y * half + (x >> 1)];
     }
-    flush_stats(stats, nwords, ncalls, nwords * lanes);
+    flush_stats(stats, nwords, ncalls, nflips);
+}
+
+template <bool EA>
+__device__ __forceinline__ void sweep_dispatch(const SweepItem &it, const RunInfo &R, const PopState &S,
+                                               uint64_t *lds, int dense, unsigned long long *stats)
+{
+    switch (R.L) {
+    case 8: sweep_item<8, EA>(it, R, S, lds, dense, stats); break;
+    case 16: sweep_item<16, EA>(it, R, S, lds, dense, stats); break;
+    case 24: sweep_item<24, EA>(it, R, S, lds, dense, stats); break;
+    case 32: sweep_item<32, EA>(it, R, S, lds, dense, stats); break;
+    case 48: sweep_item<48, EA>(it, R, S, lds, dense, stats); break;
+    case 64: sweep_item<64, EA>(it, R, S, lds, dense, stats); break;
+    case 128: sweep_item<128, EA>(it, R, S, lds, dense, stats); break;
+    default: sweep_item<0, EA>(it, R, S, lds, dense, stats); break;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, const RunInfo *runs,
+                                                    const PopState *st, int dense, unsigned long long *stats)
+{
+    extern __shared__ uint64_t lds[];
+    const SweepItem it = items[blockIdx.x];
+    const RunInfo &R = runs[it.run];
+    const PopState &S = st[it.run * MAX_POP + it.pop];
+    if (!pop_active(S) || R.theta == 0) return;
+    if (R.model == PA_EA_PMJ) sweep_dispatch<true>(it, R, S, lds, dense, stats);
+    else sweep_dispatch<false>(it, R, S, lds, dense, stats);
 }
 
 // -------------------------------------------------------------- step (v)
 
+// Word of 64 replicas of group g at site n, from either layout.
 template <int REPR>
-__device__ __forceinline__ int spin_bit(const uint8_t *buf, int j, int n, int N)
+__device__ __forceinline__ uint64_t load_word(const uint8_t *buf, int g, int n, int N)
 {
-    if (REPR == PA_MSC64)
-        return (int)((((const uint64_t *)buf)[(size_t)(j >> 6) * N + n] >> (j & 63)) & 1u);
-    return buf[((size_t)(j >> 6) * N + n) * 64 + (j & 63)] >> 7;
+    if (REPR == PA_MSC64) return ((const uint64_t *)buf)[(size_t)g * N + n];
+    const uint4 *q = (const uint4 *)(buf + ((size_t)g * N + n) * 64);
+    uint4 v[4] = {q[0], q[1], q[2], q[3]};
+    return pack64(v);
 }
 
-// Per replica (lane = replica of a 64-group, 4 waves splitting the sites):
-// E_j = 2 (#unsatisfied bonds) - 2N, M_j = N - 2 (#down spins); per pair
-// the Hamming distance d (Q = N - 2d) and the number of bonds whose product
-// differs (Q_l = 2N - 2 d_l).  Integer sums go to the per-population
-// accumulators, family sizes to the family histogram.
-template <int REPR>
-__global__ void __launch_bounds__(256) k_measure(const Item *items, const RunInfo *runs, PopState *st)
+// Measurement of one replica group (64 replicas) per workgroup.  The group's
+// lattice (and its overlap partners' lattice) is staged in LDS in bands of
+// rows; each thread takes sites and accumulates, in bit-sliced counters,
+// the per-replica numbers of unsatisfied bonds (E = 2 #unsat - 2N), down
+// spins (M = N - 2 #down), and for overlap pairs the Hamming distance
+// (Q = N - 2 d) and the number of bonds whose product differs
+// (Q_l = 2N - 2 d_l).  The counters are turned into per-replica integers by
+// transposes, summed over the wavefronts, and reduced into the population's
+// integer sums, minimum energy, overlap histogram and family histogram.
+constexpr int MEAS_BAND_WORDS = 4096;
+
+constexpr int MEAS_THREADS = 256;   // a band gives each thread at most 16 sites
+
+template <int REPR, int LT>
+__device__ __forceinline__ void measure_group(const Item &it, const RunInfo &R, PopState &S, const PopState *st,
+                                              uint64_t *lat, uint64_t *plat, uint32_t (*red)[4][64])
 {
-    __shared__ int red[4][4][64];
-    const Item it = items[blockIdx.x];
-    const RunInfo &R = runs[it.run];
-    PopState &S = st[it.run * MAX_POP + it.pop];
-    if (!pop_active(S)) return;
+    const int L = LT ? LT : R.L;
+    const int N = L * L;
     const int Rc = S.Rcur;
     const int g = it.group;
-    if (g * 64 >= Rc) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int j = g * 64 + lane;
-    const bool valid = j < Rc;
-    const int L = R.L, N = R.N;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint8_t *buf = R.spins[it.pop][S.cur];
-    bool pair = false;
-    int pj = 0;
+    // overlap partners of this group's replicas
+    int mode = 0;                      // 0 none, 1 index shift, 2 two populations
+    uint64_t pairmask = 0;
     const uint8_t *pbuf = buf;
+    int pg = 0, sh = 0, pgroups = R.groups_cap;
     if (R.overlap == PA_Q_INDEX_SHIFT) {
         const int h = Rc >> 1;
-        pair = j < h;
-        pj = j + h;
+        const int lo = g * 64;
+        if (lo < h) {
+            mode = 1;
+            const int cntp = min(64, h - lo);
+            pairmask = cntp >= 64 ? ~0ull : ((1ull << cntp) - 1);
+            pg = (lo + h) >> 6;
+            sh = (lo + h) & 63;
+        }
     } else if (R.overlap == PA_Q_TWO_POP && it.pop == 0) {
         const PopState &S1 = st[it.run * MAX_POP + 1];
         if (pop_active(S1)) {
-            pair = j < min(Rc, S1.Rcur);
-            pj = j;
-            pbuf = R.spins[1][S1.cur];
+            const int m = min(Rc, S1.Rcur);
+            const int lo = g * 64;
+            if (lo < m) {
+                mode = 2;
+                const int cntp = min(64, m - lo);
+                pairmask = cntp >= 64 ? ~0ull : ((1ull << cntp) - 1);
+                pbuf = R.spins[1][S1.cur];
+                pg = g;
+            }
         }
     }
-    const int jj = valid ? j : g * 64;
-    const int pjj = pair ? pj : 0;
-    int unsat = 0, down = 0, ham = 0, dl = 0;
-    const int per = (N + 3) / 4;
-    const int n0 = wv * per, n1 = min(N, n0 + per);
-    for (int n = n0; n < n1; ++n) {
-        const int y = n / L, x = n - y * L;
-        const int nr = y * L + (x + 1 == L ? 0 : x + 1);
-        const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
-        const int jbn = R.jbits[n];
-        const int s = spin_bit<REPR>(buf, jj, n, N);
-        const int sr = spin_bit<REPR>(buf, jj, nr, N);
-        const int sd = spin_bit<REPR>(buf, jj, nd, N);
-        unsat += (s ^ sr ^ (jbn & 1)) + (s ^ sd ^ ((jbn >> 1) & 1));
-        down += s;
-        if (pair) {
-            const int t = spin_bit<REPR>(pbuf, pjj, n, N);
-            const int tr = spin_bit<REPR>(pbuf, pjj, nr, N);
-            const int td = spin_bit<REPR>(pbuf, pjj, nd, N);
-            ham += s ^ t;
-            dl += (s ^ sr ^ t ^ tr) + (s ^ sd ^ t ^ td);
+    const int B = N <= MEAS_BAND_WORDS ? L : MEAS_BAND_WORDS / L - 1;   // rows per band
+    const bool whole = B == L;
+    uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
+    uint32_t totU = 0, totD = 0, totH = 0, totK = 0;
+    for (int y0 = 0; y0 < L; y0 += B) {
+        const int rows = min(B, L - y0);
+        const int srows = whole ? rows : rows + 1;
+        __syncthreads();
+        for (int idx = tid; idx < srows * L; idx += blockDim.x) {
+            const int r = idx / L, x = idx - r * L;
+            const int n = ((y0 + r) % L) * L + x;
+            lat[idx] = load_word<REPR>(buf, g, n, N);
+            if (mode == 1) {
+                const uint64_t a = load_word<REPR>(buf, pg, n, N);
+                const uint64_t b = (sh && pg + 1 < pgroups) ? load_word<REPR>(buf, pg + 1, n, N) : 0ull;
+                plat[idx] = sh ? ((a >> sh) | (b << (64 - sh))) : a;
+            } else if (mode == 2) {
+                plat[idx] = load_word<REPR>(pbuf, pg, n, N);
+            }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < rows * L; idx += blockDim.x) {
+            const int r = idx / L, x = idx - r * L;
+            const int n = (y0 + r) * L + x;
+            const int ir = r * L + (x + 1 == L ? 0 : x + 1);
+            const int id = (whole && r + 1 == L) ? x : (r + 1) * L + x;
+            const uint8_t jn = R.jbits[n];
+            const uint64_t w = lat[idx], wr = lat[ir], wd = lat[id];
+            const uint64_t br = w ^ wr, bd = w ^ wd;
+            vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
+            vinc(cD, w);
+            if (mode) {
+                const uint64_t q = plat[idx], qr = plat[ir], qd = plat[id];
+                vinc(cH, w ^ q);
+                vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
+            }
+        }
+        // wave-uniform point: every lane of the wavefront reaches it
+        totU += vflush(cU);
+        totD += vflush(cD);
+        if (mode) {
+            totH += vflush(cH);
+            totK += vflush(cK);
         }
     }
-    red[0][wv][lane] = unsat;
-    red[1][wv][lane] = down;
-    red[2][wv][lane] = ham;
-    red[3][wv][lane] = dl;
+    red[0][wv][lane] = totU;
+    red[1][wv][lane] = totD;
+    red[2][wv][lane] = totH;
+    red[3][wv][lane] = totK;
     __syncthreads();
     if (wv != 0) return;
-    unsat = red[0][0][lane] + red[0][1][lane] + red[0][2][lane] + red[0][3][lane];
-    down = red[1][0][lane] + red[1][1][lane] + red[1][2][lane] + red[1][3][lane];
-    ham = red[2][0][lane] + red[2][1][lane] + red[2][2][lane] + red[2][3][lane];
-    dl = red[3][0][lane] + red[3][1][lane] + red[3][2][lane] + red[3][3][lane];
-    const int64_t E = 2 * unsat - 2 * N;
-    const int64_t M = N - 2 * down;
+    const int nwv = blockDim.x >> 6;
+    uint32_t U = 0, D = 0, H = 0, Kc = 0;
+    for (int k = 0; k < nwv; ++k) {
+        U += red[0][k][lane];
+        D += red[1][k][lane];
+        H += red[2][k][lane];
+        Kc += red[3][k][lane];
+    }
+    const int j = g * 64 + lane;
+    const bool valid = j < Rc;
+    const int64_t E = 2 * (int64_t)U - 2 * (int64_t)N;
+    const int64_t M = (int64_t)N - 2 * (int64_t)D;
     if (valid) {
         R.E[it.pop][S.cur][j] = (int32_t)E;
         atomicAdd(&R.famcnt[it.pop][R.fam[it.pop][S.cur][j]], 1);
@@ -747,8 +1025,9 @@ __global__ void __launch_bounds__(256) k_measure(const Item *items, const RunInf
     const int64_t sM = wave_sum<int64_t>(v * (M < 0 ? -M : M));
     const int64_t sM2 = wave_sum<int64_t>(v * M * M);
     const int emin = wave_min(valid ? (int)E : INT32_MAX);
+    const bool pair = mode && ((pairmask >> lane) & 1u);
     const int64_t pv = pair ? 1 : 0;
-    const int64_t Q = N - 2 * ham, Ql = 2 * N - 2 * dl;
+    const int64_t Q = (int64_t)N - 2 * (int64_t)H, Ql = 2 * (int64_t)N - 2 * (int64_t)Kc;
     const int64_t np = wave_sum<int64_t>(pv);
     const int64_t sQ = wave_sum<int64_t>(pv * Q);
     const int64_t sAQ = wave_sum<int64_t>(pv * (Q < 0 ? -Q : Q));
@@ -757,8 +1036,8 @@ __global__ void __launch_bounds__(256) k_measure(const Item *items, const RunInf
     const int64_t sQl2 = wave_sum<int64_t>(pv * Ql * Ql);
     if (pair && R.qhist) {
         const size_t Np1 = (size_t)N + 1;
-        atomicAdd(&R.qh[((size_t)it.pop * R.K + S.i) * Np1 + ham], 1);
-        if (R.overlap == PA_Q_TWO_POP) atomicAdd(&R.qh[((size_t)1 * R.K + S.i) * Np1 + ham], 1);
+        atomicAdd(&R.qh[((size_t)it.pop * R.K + S.i) * Np1 + H], 1);
+        if (R.overlap == PA_Q_TWO_POP) atomicAdd(&R.qh[((size_t)1 * R.K + S.i) * Np1 + H], 1);
     }
     if (lane == 0) {
         unsigned long long *acc = (unsigned long long *)S.acc;
@@ -778,69 +1057,119 @@ __global__ void __launch_bounds__(256) k_measure(const Item *items, const RunInf
     }
 }
 
-// Per run: family statistics from the histogram (then cleared), the record
-// of temperature i for each population, and the accumulators reset.  With
-// two populations both records carry the pair sums.
+template <int REPR>
+__global__ void __launch_bounds__(MEAS_THREADS) k_measure(const Item *items, const RunInfo *runs, PopState *st)
+{
+    __shared__ uint64_t lat[MEAS_BAND_WORDS];
+    __shared__ uint64_t plat[MEAS_BAND_WORDS];
+    __shared__ uint32_t red[4][MEAS_THREADS / 64][64];
+    const Item it = items[blockIdx.x];
+    const RunInfo &R = runs[it.run];
+    PopState &S = st[it.run * MAX_POP + it.pop];
+    if (!pop_active(S)) return;
+    if (it.group * 64 >= S.Rcur) return;
+    switch (R.L) {
+    case 8: measure_group<REPR, 8>(it, R, S, st, lat, plat, red); break;
+    case 16: measure_group<REPR, 16>(it, R, S, st, lat, plat, red); break;
+    case 24: measure_group<REPR, 24>(it, R, S, st, lat, plat, red); break;
+    case 32: measure_group<REPR, 32>(it, R, S, st, lat, plat, red); break;
+    case 48: measure_group<REPR, 48>(it, R, S, st, lat, plat, red); break;
+    case 64: measure_group<REPR, 64>(it, R, S, st, lat, plat, red); break;
+    default: measure_group<REPR, 0>(it, R, S, st, lat, plat, red); break;
+    }
+}
+
+// Family sizes: per chunk of family labels, sum of c_f^2, max c_f and the
+// number of non-empty families, accumulated per population; the histogram
+// is cleared for the next temperature.
+__global__ void __launch_bounds__(CH_THREADS) k_fam_chunk(const ChunkItem *items, const RunInfo *runs,
+                                                           PopState *st)
+{
+    __shared__ int64_t red[3][CH_THREADS / 64];
+    const ChunkItem it = items[blockIdx.x];
+    const RunInfo &R = runs[it.run];
+    PopState &S = st[it.run * MAX_POP + it.pop];
+    if (!pop_active(S)) return;
+    const int f0 = it.chunk * CH;
+    if (f0 >= R.R) return;
+    int32_t *fc = R.famcnt[it.pop];
+    int64_t sq = 0, mx = 0, nz = 0;
+    for (int q = 0; q < CH_PER; ++q) {
+        const int f = f0 + threadIdx.x + q * CH_THREADS;
+        if (f < R.R) {
+            const int64_t cnt = fc[f];
+            sq += cnt * cnt;
+            mx = cnt > mx ? cnt : mx;
+            nz += cnt > 0;
+            fc[f] = 0;
+        }
+    }
+    sq = wave_sum<int64_t>(sq);
+    nz = wave_sum<int64_t>(nz);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = sq;
+        red[1][wv] = mx;
+        red[2][wv] = nz;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = 0, cnz = 0;
+        for (int k = 0; k < CH_THREADS / 64; ++k) {
+            a += red[0][k];
+            b = red[1][k] > b ? red[1][k] : b;
+            cnz += red[2][k];
+        }
+        unsigned long long *acc = (unsigned long long *)S.acc;
+        atomicAdd(&acc[A_FAMSQ], (unsigned long long)a);
+        atomicMax(&acc[A_FAMMAX], (unsigned long long)b);
+        atomicAdd(&acc[A_NFAM], (unsigned long long)cnz);
+    }
+}
+
+// Per run: the record of temperature i for each population, and the
+// accumulators reset.  With two populations both records carry the pair
+// sums.
 __global__ void k_finalize(const RunInfo *runs, PopState *st, int n_runs, int npop_ctx)
 {
-    __shared__ int64_t red[3][256];
-    const int run = blockIdx.x;
+    const int run = blockIdx.x * blockDim.x + threadIdx.x;
+    if (run >= n_runs) return;
     const RunInfo &R = runs[run];
     int64_t pairs[6] = {0, 0, 0, 0, 0, 0};
     for (int p = 0; p < R.npop; ++p) {
         PopState &S = st[run * MAX_POP + p];
         if (!pop_active(S)) continue;
-        int64_t sq = 0, mx = 0, nz = 0;
-        int32_t *fc = R.famcnt[p];
-        for (int f = threadIdx.x; f < R.R; f += blockDim.x) {
-            const int64_t c = fc[f];
-            sq += c * c;
-            mx = c > mx ? c : mx;
-            nz += c > 0;
-            fc[f] = 0;
-        }
-        red[0][threadIdx.x] = sq;
-        red[1][threadIdx.x] = mx;
-        red[2][threadIdx.x] = nz;
-        __syncthreads();
-        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) {
-                red[0][threadIdx.x] += red[0][threadIdx.x + o];
-                red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + o]);
-                red[2][threadIdx.x] += red[2][threadIdx.x + o];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const int i = S.i;
-            pa_obs o;
-            o.R_i = S.Rcur;
-            o.lnQ = i == 0 ? 0.0 : S.lnQ;
-            o.A = S.A;
-            o.sumE = S.acc[A_SUME];
-            o.sumE2 = S.acc[A_SUME2];
-            o.sumAbsM = S.acc[A_SUMABSM];
-            o.sumM2 = S.acc[A_SUMM2];
-            if (p == 0) {
-                for (int k = 0; k < 6; ++k) pairs[k] = S.acc[A_NPAIRS + k];
-            }
-            o.nPairs = pairs[0];
-            o.sumQ = pairs[1];
-            o.sumAbsQ = pairs[2];
-            o.sumQ2 = pairs[3];
-            o.sumQl = pairs[4];
-            o.sumQl2 = pairs[5];
-            o.famSumSq = red[0][0];
-            o.famMax = red[1][0];
-            o.nFam = red[2][0];
-            o.Emin = S.EminAcc;
-            o.status = PA_OK;
-            R.obs[((size_t)i * n_runs + run) * npop_ctx + p] = o;
-            S.Emin = S.EminAcc;
-            for (int k = 0; k < NACC; ++k) S.acc[k] = 0;
-            S.EminAcc = INT32_MAX;
-        }
-        __syncthreads();
+        const int i = S.i;
+        pa_obs o;
+        o.R_i = S.Rcur;
+        o.lnQ = i == 0 ? 0.0 : S.lnQ;
+        o.A = S.A;
+        o.sumE = S.acc[A_SUME];
+        o.sumE2 = S.acc[A_SUME2];
+        o.sumAbsM = S.acc[A_SUMABSM];
+        o.sumM2 = S.acc[A_SUMM2];
+        if (p == 0)
+            for (int k = 0; k < 6; ++k) pairs[k] = S.acc[A_NPAIRS + k];
+        o.nPairs = pairs[0];
+        o.sumQ = pairs[1];
+        o.sumAbsQ = pairs[2];
+        o.sumQ2 = pairs[3];
+        o.sumQl = pairs[4];
+        o.sumQl2 = pairs[5];
+        o.famSumSq = S.acc[A_FAMSQ];
+        o.famMax = S.acc[A_FAMMAX];
+        o.nFam = S.acc[A_NFAM];
+        o.Emin = S.EminAcc;
+        o.status = PA_OK;
+        R.obs[((size_t)i * n_runs + run) * npop_ctx + p] = o;
+        S.Emin = S.EminAcc;
+        for (int k = 0; k < NACC; ++k) S.acc[k] = 0;
+        S.EminAcc = INT32_MAX;
     }
 }
 
@@ -1054,15 +1383,42 @@ hipError_t launch_resample(const LaunchCtx &c)
     return hipGetLastError();
 }
 
+
+// Rows per workgroup of the int8 sweep: the whole lattice when its chunks
+// fit in the registers of 1024 threads, else bands with a halo row on each
+// side.
 int int8_tile_rows(int L)
 {
-    int T = 512 / L;
-    if (T < 1) T = 1;
-    if (T > L) T = L;
-    return T;
+    if (L * L * 4 <= I8_CMAX * 1024) return L;
+    int T = I8_CMAX * 1024 / (4 * L) - 2;
+    return T < 1 ? 1 : T;
 }
 
-size_t msc_lds_bytes(int N) { return (size_t)N * 8 + (size_t)N; }
+hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop, int theta)
+{
+    const int T = int8_tile_rows(L);
+    const int ntiles = (L + T - 1) / T;
+    const int nrow = T == L ? L : T + 2;
+    const int chunks = nrow * L * 4;
+    int threads = (chunks + I8_CMAX - 1) / I8_CMAX;
+    threads = ((threads + 63) / 64) * 64;
+    threads = threads < 64 ? 64 : (threads > 1024 ? 1024 : threads);
+    const size_t lds = (size_t)nrow * L * 8 + (size_t)T * (L / 2) * 8;
+    for (int s = 0; s < theta; ++s)
+        for (int colour = 0; colour < 2; ++colour)
+            for (int p = 0; p < npop; ++p) {
+                k_sweep_int8<<<groups_cap * ntiles, threads, lds, c.stream>>>(c.runs, c.st, run, p, s, colour, T,
+                                                                              ntiles, c.stats);
+                PA_CHECK_LAUNCH();
+            }
+    return hipSuccess;
+}
+
+size_t msc_lds_bytes(int N, int groups)
+{
+    const size_t units = (size_t)groups * (N / 2);
+    return (size_t)groups * N * 8 + units * 20 + (size_t)N;
+}
 
 hipError_t prepare_msc_lds(size_t bytes)
 {
@@ -1070,34 +1426,21 @@ hipError_t prepare_msc_lds(size_t bytes)
     return hipFuncSetAttribute((const void *)k_sweep_msc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop,
-                                 int theta)
+hipError_t launch_sweep_msc(const LaunchCtx &c)
 {
-    const int T = int8_tile_rows(L);
-    const int ntiles = (L + T - 1) / T;
-    const size_t lds = (size_t)(T + 2) * (L / 2) * 8;
-    for (int s = 0; s < theta; ++s)
-        for (int colour = 0; colour < 2; ++colour)
-            for (int p = 0; p < npop; ++p) {
-                k_sweep_int8<<<groups_cap * ntiles, 256, lds, c.stream>>>(c.runs, c.st, run, p, s, colour, T,
-                                                                          ntiles, c.stats);
-                PA_CHECK_LAUNCH();
-            }
-    return hipSuccess;
-}
-
-hipError_t launch_sweep_msc(const LaunchCtx &c, int maxN)
-{
-    k_sweep_msc<<<c.n_items, 256, msc_lds_bytes(maxN), c.stream>>>(c.items, c.runs, c.st, c.stats);
+    k_sweep_msc<<<c.n_sweep_items, c.sweep_threads, c.sweep_lds, c.stream>>>(c.sweep_items, c.runs, c.st,
+                                                                            c.sweep_dense, c.stats);
     return hipGetLastError();
 }
 
 hipError_t launch_measure(const LaunchCtx &c)
 {
-    if (c.repr == PA_MSC64) k_measure<PA_MSC64><<<c.n_items, 256, 0, c.stream>>>(c.items, c.runs, c.st);
-    else k_measure<PA_INT8><<<c.n_items, 256, 0, c.stream>>>(c.items, c.runs, c.st);
+    if (c.repr == PA_MSC64) k_measure<PA_MSC64><<<c.n_items, MEAS_THREADS, 0, c.stream>>>(c.items, c.runs, c.st);
+    else k_measure<PA_INT8><<<c.n_items, MEAS_THREADS, 0, c.stream>>>(c.items, c.runs, c.st);
     PA_CHECK_LAUNCH();
-    k_finalize<<<c.n_runs, 256, 0, c.stream>>>(c.runs, c.st, c.n_runs, c.npop_ctx);
+    k_fam_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
+    PA_CHECK_LAUNCH();
+    k_finalize<<<(c.n_runs + 63) / 64, 64, 0, c.stream>>>(c.runs, c.st, c.n_runs, c.npop_ctx);
     return hipGetLastError();
 }
 

@@ -18,6 +18,9 @@ struct LaunchCtx {
     int repr;
     bool any_multinomial;
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
+    const SweepItem *sweep_items;  // device [n_sweep_items]
+    int n_sweep_items, sweep_threads, sweep_dense;
+    size_t sweep_lds;
     hipStream_t stream;
 };
 
@@ -26,12 +29,12 @@ hipError_t launch_init(const LaunchCtx &c, const uint64_t *dseed);
 hipError_t launch_anneal(const LaunchCtx &c);
 hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop, int theta);
-hipError_t launch_sweep_msc(const LaunchCtx &c, int maxN);
+hipError_t launch_sweep_msc(const LaunchCtx &c);
 hipError_t launch_measure(const LaunchCtx &c);
 hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
                        double *logw, pa_wavg *out);
 int int8_tile_rows(int L);
-size_t msc_lds_bytes(int N);
+size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);
 
 }  // namespace pa

@@ -27,39 +27,88 @@ struct Thresholds {
     bool all4, all8;        // T == 2^32: every such move is accepted
 };
 
+constexpr int LUT_SEL = lut3((LUT_A & LUT_B) | (~LUT_A & LUT_C));   // a ? b : c, bitwise
+constexpr int LUT_WIN = lut3(LUT_A & LUT_B & ~LUT_C);               // a & b & ~c
+constexpr int LUT_TIE = lut3(LUT_A & ~(LUT_B ^ LUT_C));             // a & ~(b ^ c)
+constexpr int LUT_NOR3 = lut3(~(LUT_A | LUT_B | LUT_C));
+constexpr int LUT_ONE = lut3((LUT_A ^ LUT_B) & ~LUT_C);             // (a ^ b) & ~c
+constexpr int LUT_OR_AND = lut3((LUT_A | LUT_B) & LUT_C);           // (a | b) & c
+
+// Site classes of 64 replicas: flip = dE <= 0 (always flips), one = dE = +4,
+// zero = dE = +8, from the word w, its four neighbours and the coupling
+// masks (all ones where J = -1).
+struct SiteClass {
+    uint64_t flip, one, zero;
+};
+
+template <bool EA>
+__device__ __forceinline__ SiteClass classify(uint64_t w, uint64_t nr, uint64_t nl, uint64_t nd, uint64_t nu,
+                                              uint64_t jr, uint64_t jl, uint64_t jd, uint64_t ju)
+{
+    uint64_t d0, d1, d2, d3;
+    if (EA) {
+        d0 = bop3<LUT_XOR3>(w, nr, jr);
+        d1 = bop3<LUT_XOR3>(w, nl, jl);
+        d2 = bop3<LUT_XOR3>(w, nd, jd);
+        d3 = bop3<LUT_XOR3>(w, nu, ju);
+    } else {
+        d0 = w ^ nr;
+        d1 = w ^ nl;
+        d2 = w ^ nd;
+        d3 = w ^ nu;
+    }
+    const uint64_t x1 = d0 ^ d1, a1 = d0 & d1;
+    const uint64_t x2 = d2 ^ d3, a2 = d2 & d3;
+    SiteClass c;
+    c.zero = bop3<LUT_NOR3>(d0, d1, d2) & ~d3;      // no unsatisfied bond
+    c.one = bop3<LUT_ONE>(x1, x2, a1) & ~a2;        // exactly one
+    c.flip = ~(c.zero | c.one);                     // two or more
+    return c;
+}
+
+// One bit plane of the most-significant-first comparison u < T for the
+// undecided lanes `und`: tb is T's bit for each lane's class (dE = +4 lanes
+// where `one` is set, dE = +8 lanes elsewhere); a lane whose draw bit is 0
+// where tb is 1 is accepted, a lane whose bits differ otherwise is rejected,
+// equal bits stay undecided.
+__device__ __forceinline__ void plane_step(uint64_t plane, uint64_t one, uint64_t m4, uint64_t m8,
+                                           uint64_t &und, uint64_t &acc)
+{
+    const uint64_t tb = bop3<LUT_SEL>(one, m4, m8);
+    acc |= bop3<LUT_WIN>(und, tb, plane);
+    und = bop3<LUT_TIE>(und, tb, plane);
+}
+
+// Philox call c of a site: planes 2c and 2c+1 compared against T.
+__device__ __forceinline__ void draw_step(uint32_t c, const Thresholds &T, uint64_t one, uint64_t &und,
+                                          uint64_t &acc, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1)
+{
+    const u32x4 o = philox10(c0 | (c << 20), c1, c2, c3, k0, k1);
+    const int sh = 31 - 2 * (int)c;
+    const uint64_t m4a = (T.t4 >> sh) & 1u ? ~0ull : 0ull, m8a = (T.t8 >> sh) & 1u ? ~0ull : 0ull;
+    const uint64_t m4b = (T.t4 >> (sh - 1)) & 1u ? ~0ull : 0ull, m8b = (T.t8 >> (sh - 1)) & 1u ? ~0ull : 0ull;
+    plane_step((uint64_t)o.x | ((uint64_t)o.y << 32), one, m4a, m8a, und, acc);
+    plane_step((uint64_t)o.z | ((uint64_t)o.w << 32), one, m4b, m8b, und, acc);
+}
+
+// Flip mask of one site, all draws done here (used by the plain path).
 __device__ __forceinline__ uint64_t flip_mask(uint64_t w, uint64_t nr, uint64_t nl, uint64_t nd,
                                               uint64_t nu, uint64_t jr, uint64_t jl, uint64_t jd,
                                               uint64_t ju, const Thresholds &T, uint64_t valid,
                                               uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t &calls)
 {
-    const uint64_t d0 = w ^ nr ^ jr;
-    const uint64_t d1 = w ^ nl ^ jl;
-    const uint64_t d2 = w ^ nd ^ jd;
-    const uint64_t d3 = w ^ nu ^ ju;
-    const uint64_t x1 = d0 ^ d1, a1 = d0 & d1;
-    const uint64_t x2 = d2 ^ d3, a2 = d2 & d3;
-    uint64_t zero = ~(d0 | d1 | d2 | d3);      // u = 0: dE = +8
-    uint64_t one = (x1 ^ x2) & ~(a1 | a2);     // u = 1: dE = +4
-    uint64_t flip = ~(zero | one);             // dE <= 0
-    if (T.all4) { flip |= one; one = 0; }
-    if (T.all8) { flip |= zero; zero = 0; }
-    uint64_t und = (one | zero) & valid;
+    SiteClass sc = classify<true>(w, nr, nl, nd, nu, jr, jl, jd, ju);
+    if (T.all4) { sc.flip |= sc.one; sc.one = 0; }
+    if (T.all8) { sc.flip |= sc.zero; sc.zero = 0; }
+    uint64_t und = (sc.one | sc.zero) & valid;
     uint64_t acc = 0;
     for (uint32_t c = 0; und != 0 && c < 16; ++c) {
-        const u32x4 o = philox10(c0 | (c << 20), c1, c2, c3, k0, k1);
+        draw_step(c, T, sc.one, und, acc, c0, c1, c2, c3, k0, k1);
         ++calls;
-        const uint64_t pa_ = (uint64_t)o.x | ((uint64_t)o.y << 32);
-        const uint64_t pb_ = (uint64_t)o.z | ((uint64_t)o.w << 32);
-        const int sh = 31 - 2 * (int)c;
-        uint64_t tb = ((T.t4 >> sh) & 1u ? one : 0) | ((T.t8 >> sh) & 1u ? zero : 0);
-        acc |= und & tb & ~pa_;
-        und &= ~(tb ^ pa_);
-        tb = ((T.t4 >> (sh - 1)) & 1u ? one : 0) | ((T.t8 >> (sh - 1)) & 1u ? zero : 0);
-        acc |= und & tb & ~pb_;
-        und &= ~(tb ^ pb_);
     }
-    return flip | acc;
+    return sc.flip | acc;
 }
 
 __device__ __forceinline__ Thresholds thresholds_of(const uint64_t *tabT, int i)

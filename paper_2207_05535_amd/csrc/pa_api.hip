@@ -61,7 +61,7 @@ struct TableOff {
 struct Layout {
     std::vector<RunOff> runs;
     std::vector<TableOff> tables;
-    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats;
+    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items;
     int n_items, n_chunk_items, npop_ctx, Kmax, maxN;
     size_t total;
 };
@@ -118,6 +118,7 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
         Lo.n_chunk_items += npop * chunks_cap_of(runs[r]);
     }
     Lo.items = P.take(sizeof(Item) * Lo.n_items);
+    Lo.sweep_items = P.take(sizeof(SweepItem) * Lo.n_items);
     Lo.chunk_items = P.take(sizeof(ChunkItem) * Lo.n_chunk_items);
     Lo.obs = P.take(sizeof(pa_obs) * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx);
     Lo.logw = P.take(sizeof(double) * (size_t)Lo.Kmax * n_runs);
@@ -189,6 +190,10 @@ struct pa_ctx {
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_def = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+    int lds_limit = 65536;
+    int sweep_threads = 256;
+    int sweep_dense = 3;                // Philox calls every site makes in lockstep
+    std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
     bool any_multinomial = false;
     hipError_t last = hipSuccess;
 };
@@ -238,12 +243,65 @@ void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::
     }
 }
 
+int default_groups(int L)
+{
+    const int nh = L * L / 2;
+    int G = (2048 + nh / 2) / nh;
+    return G < 1 ? 1 : (G > 64 ? 64 : G);
+}
+
+int groups_for(const pa_ctx *c, int L)
+{
+    auto it = c->groups_per_wg.find(L);
+    return it == c->groups_per_wg.end() ? default_groups(L) : it->second;
+}
+
+// Work list and LDS size of the batched sweep for the current tuning.
+// Returns false if some lattice block does not fit in LDS.
+bool plan_sweep(const pa_ctx *c, std::vector<SweepItem> &items, size_t &lds)
+{
+    items.clear();
+    lds = 0;
+    for (int r = 0; r < c->n_runs; ++r) {
+        const pa_run_desc &d = c->descs[r];
+        const int N = d.L * d.L;
+        if ((size_t)groups_for(c, d.L) * N > 65535) return false;   // 16-bit LDS word indices
+        lds = std::max(lds, msc_lds_bytes(N, groups_for(c, d.L)));
+    }
+    if (lds > (size_t)c->lds_limit) return false;
+    for (int r = 0; r < c->n_runs; ++r) {
+        const pa_run_desc &d = c->descs[r];
+        const int G = groups_for(c, d.L);
+        for (int p = 0; p < n_pop_of(d.overlap); ++p)
+            for (int g = 0; g < groups_cap_of(d); g += G)
+                items.push_back({r, p, g, std::min(G, groups_cap_of(d) - g)});
+    }
+    return true;
+}
+
+pa_status upload_sweep_plan(pa_ctx *c)
+{
+    std::vector<SweepItem> items;
+    size_t lds = 0;
+    if (!plan_sweep(c, items, lds)) return PA_ERR_ARG;
+    if (prepare_msc_lds(lds) != hipSuccess) return dev_fail(c);
+    PA_HIP(c, hipMemcpyAsync(at<SweepItem>(c, c->lo.sweep_items), items.data(), sizeof(SweepItem) * items.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    c->lc.sweep_items = at<SweepItem>(c, c->lo.sweep_items);
+    c->lc.n_sweep_items = (int)items.size();
+    c->lc.sweep_threads = c->sweep_threads;
+    c->lc.sweep_dense = c->sweep_dense;
+    c->lc.sweep_lds = lds;
+    return PA_OK;
+}
+
 pa_status enqueue_step(pa_ctx *c)
 {
     if (launch_anneal(c->lc) != hipSuccess) return dev_fail(c);
     if (launch_resample(c->lc) != hipSuccess) return dev_fail(c);
     if (c->repr == PA_MSC64) {
-        if (launch_sweep_msc(c->lc, c->lo.maxN) != hipSuccess) return dev_fail(c);
+        if (launch_sweep_msc(c->lc) != hipSuccess) return dev_fail(c);
     } else {
         for (int r = 0; r < c->n_runs; ++r) {
             const pa_run_desc &d = c->descs[r];
@@ -401,13 +459,16 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         delete c;
         return s;
     };
-    if (repr == PA_MSC64) {
-        int dev = 0, lds = 0;
+    {
+        int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            hipDeviceGetAttribute(&c->lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return fail(PA_ERR_DEVICE);
-        if (msc_lds_bytes(Lo.maxN) > (size_t)lds) return fail(PA_ERR_ARG);
-        if (prepare_msc_lds(msc_lds_bytes(Lo.maxN)) != hipSuccess) return fail(PA_ERR_DEVICE);
+    }
+    if (repr == PA_MSC64) {
+        std::vector<SweepItem> probe;
+        size_t lds = 0;
+        if (!plan_sweep(c, probe, lds)) return fail(PA_ERR_ARG);
     }
 
     hipStream_t s = c->stream;
@@ -454,6 +515,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, 2 * NSTAT, s) == hipSuccess;
     ok = ok && launch_fill_u32(at<void>(c, Lo.obs), 0,
                                sizeof(pa_obs) / 4 * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx, s) == hipSuccess;
+    ok = ok && (repr != PA_MSC64 || upload_sweep_plan(c) == PA_OK);
     ok = ok && launch_init(c->lc, at<uint64_t>(c, Lo.dseed)) == hipSuccess;
     ok = ok && launch_measure(c->lc) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
@@ -491,7 +553,7 @@ pa_status pa_sweep(pa_ctx *c, int32_t i)
     if (c->failed) return PA_ERR_DEVICE;
     if (c->phase != PH_RESAMPLED || i != c->i) return PA_ERR_STATE;
     if (c->repr == PA_MSC64) {
-        if (launch_sweep_msc(c->lc, c->lo.maxN) != hipSuccess) return dev_fail(c);
+        if (launch_sweep_msc(c->lc) != hipSuccess) return dev_fail(c);
     } else {
         for (int r = 0; r < c->n_runs; ++r) {
             const pa_run_desc &d = c->descs[r];
@@ -694,10 +756,37 @@ pa_status pa_restore(pa_ctx *c, const void *host_buf, size_t bytes)
     return PA_OK;
 }
 
-pa_status pa_set_tuning(pa_ctx *c, int32_t L, int32_t threads, int32_t groups_per_wg)
+pa_status pa_set_tuning(pa_ctx *c, int32_t L, int32_t threads, int32_t groups_per_wg, int32_t dense_calls)
 {
-    if (!c || L < 4 || threads != 256 || groups_per_wg != 1) return PA_ERR_ARG;
-    return PA_OK;
+    if (!c || L < 4 || (L & 1) || groups_per_wg < 1 || groups_per_wg > 256 || dense_calls < 0 ||
+        dense_calls > 16 || (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024))
+        return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED) return PA_ERR_STATE;
+    const int old_threads = c->sweep_threads, old_dense = c->sweep_dense;
+    const auto old_groups = c->groups_per_wg;
+    c->sweep_threads = threads;
+    c->sweep_dense = dense_calls;
+    c->groups_per_wg[L] = groups_per_wg;
+    if (c->repr != PA_MSC64) return PA_OK;
+    std::vector<SweepItem> probe;
+    size_t lds = 0;
+    if (!plan_sweep(c, probe, lds)) {
+        c->sweep_threads = old_threads;
+        c->sweep_dense = old_dense;
+        c->groups_per_wg = old_groups;
+        return PA_ERR_ARG;
+    }
+    // a captured step graph holds the old launch shape
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    if (c->graph_def) {
+        (void)hipGraphDestroy(c->graph_def);
+        c->graph_def = nullptr;
+    }
+    return upload_sweep_plan(c);
 }
 
 pa_status pa_read_stats(pa_ctx *c, uint64_t *host_out)

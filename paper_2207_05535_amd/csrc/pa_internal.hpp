@@ -32,10 +32,10 @@ constexpr int MAX_POP = 2;
 constexpr int CH_THREADS = 256;
 constexpr int CH_PER = 8;
 constexpr int CH = CH_THREADS * CH_PER;
-constexpr int NACC = 10;  // measure accumulators, see Acc
+constexpr int NACC = 13;  // measure accumulators, see Acc
 
 enum Acc { A_SUME = 0, A_SUME2, A_SUMABSM, A_SUMM2, A_NPAIRS, A_SUMQ, A_SUMABSQ, A_SUMQ2,
-           A_SUMQL, A_SUMQL2 };
+           A_SUMQL, A_SUMQL2, A_FAMSQ, A_FAMMAX, A_NFAM };
 
 struct RunInfo {
     int32_t L, N, npop, R, R_cap, theta, K, model, resampling, overlap, qhist, groups_cap;
@@ -87,6 +87,10 @@ enum Stat { ST_WORDS = 0, ST_CALLS = 1, ST_FLIPS = 2, NSTAT = 4 };
 
 struct Item {         // one replica group (64 replicas) of one (run, pop)
     int32_t run, pop, group, pad;
+};
+
+struct SweepItem {    // groups [group0, group0 + ngroups) of one (run, pop), one workgroup
+    int32_t run, pop, group0, ngroups;
 };
 
 struct ChunkItem {    // one chunk of CH replicas of one (run, pop)

@@ -346,3 +346,25 @@ def test_full_size_batched_uneven_sampled_runs(repr_):
         assert_obs_equal(obs[r, 0, :5], orc.obs()[0, :5], f"run {r}")
         assert_state_equal(ctx, orc, r, f"run {r}")
     ctx.close()
+
+
+# ------------------------------------------------------------- tuning shapes
+
+
+@pytest.mark.parametrize("threads,groups,dense", [(64, 1, 0), (256, 2, 3), (1024, 1, 16), (128, 3, 1),
+                                                  (512, 5, 2)])
+def test_tuning_shapes_do_not_change_results(threads, groups, dense):
+    """Every launch shape of the batched sweep (threads per workgroup, replica
+    groups per workgroup, lockstep calls before compaction) gives the
+    oracle's results bit for bit."""
+    runs = batch_runs()
+    ctx = pa.Context(runs, "msc")
+    for d in runs:
+        ctx.set_tuning(d["L"], threads, groups, dense)
+    ctx.run(1, 16)
+    obs = ctx.obs()
+    for r, d in enumerate(runs):
+        orc = oracle.OracleRun(d).run_all()
+        assert_obs_equal(obs[r, :orc.npop], orc.obs(), f"run {r}")
+        assert_state_equal(ctx, orc, r, f"run {r} final")
+    ctx.close()
