@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -246,6 +248,15 @@ def main():
     steps = max(1, min(args.steps, desc["K"] - 1))
     warmup = max(1, min(args.warmup, desc["K"] - 1))
     ensure_built()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 268435456-byte device-to-device copies")
+        del src, dst
     res = run_gpu(desc, steps, warmup, not args.no_plain)
 
     b = res["batched"]

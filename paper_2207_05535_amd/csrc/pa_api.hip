@@ -191,7 +191,7 @@ struct pa_ctx {
     hipGraph_t graph_def = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
     int lds_limit = 65536;
-    int sweep_threads = 256;
+    int sweep_threads = 512;
     int sweep_dense = 3;                // Philox calls every site makes in lockstep
     std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
     bool any_multinomial = false;
