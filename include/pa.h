@@ -190,11 +190,104 @@ pa_status pa_restore(pa_ctx *ctx, const void *host_buf, size_t bytes);
 pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_per_wg,
                         int32_t dense_calls);
 
+/* Persistent grid for the batched sweep: on = 1 launches as many
+ * workgroups as the device holds at once, each taking items (largest lattice
+ * block first) from a device ticket counter until none is left; on = 0
+ * launches one workgroup per item (the hardware dispatcher hands them out in
+ * the same largest-first order).  Results never depend on it. */
+pa_status pa_set_persistent(pa_ctx *ctx, int32_t on);
+
+/* Current launch shape of the batched sweep for lattice size L (any output
+ * pointer may be NULL). */
+pa_status pa_get_tuning(pa_ctx *ctx, int32_t L, int32_t *threads, int32_t *groups_per_wg,
+                        int32_t *dense_calls, int32_t *persistent);
+
+/* Autotuner of the batched sweep (no-op for the plain path).  From the
+ * current state (all steps so far measured) it runs `steps` (1..64, clipped
+ * to the remaining schedule) real temperature steps of this context for
+ * each candidate launch shape, timing the sweep launches with HIP events:
+ * first threads x dense_calls x persistent with the current groups per L,
+ * then groups per workgroup one L at a time (heaviest L first).  Every
+ * candidate's records and exact work counters must hash to the starting
+ * shape's value; one that differs is rejected (counted in *n_rejected, which
+ * is 0 unless a kernel is wrong).  The fastest accepted shape is applied and
+ * the context is returned to its starting state, so the tuned run continues
+ * exactly as an untuned one would.  Takes a pinned host snapshot of the
+ * workspace for the duration of the call.
+ * cache_path (host string, may be NULL): JSON file of shapes keyed by
+ * (device architecture, representation, L).  If it holds every L of the
+ * context, those shapes are applied without a search (*n_tried = 0); after a
+ * search the chosen shape is merged into it.  A cache that cannot be written
+ * gives PA_ERR_ARG after the shape has been applied. */
+pa_status pa_autotune(pa_ctx *ctx, int32_t steps, const char *cache_path, int32_t *n_tried,
+                      int32_t *n_rejected);
+
 /* Exact work counters of the sweep kernels since pa_create: host_out[3] =
  * {site updates of 64-replica words, Philox4x32-10 calls, attempted
  * single-spin flips}.  Used to express sweep throughput against the
  * integer-ALU roofline. */
 pa_status pa_read_stats(pa_ctx *ctx, uint64_t *host_out);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * Continuous batching of independent runs (a stream of requests, each one
+ * PA run of Sec. II B).  A server owns a caller-allocated device arena
+ * (256-byte aligned; borrowed until pa_server_destroy) and max_slots slots.
+ * Runs are admitted while a slot is free and their footprint fits in the
+ * free arena space; each server step advances every resident run that has
+ * not reached its last temperature by one temperature step (steps ii-v),
+ * whatever temperature it is at, in shared launches.  A run's records equal
+ * those of the same descriptor run alone in a pa_ctx, bit for bit.  All work
+ * goes to the caller's stream in order; a server is used from one host
+ * thread at a time. */
+typedef struct pa_server pa_server;
+
+/* Device bytes one run takes in a server arena: its own block (populations,
+ * records, work lists) plus its tables, which it shares with resident runs
+ * of the same L and schedule (so the bound is not always reached).
+ * PA_ERR_ARG for an invalid descriptor. */
+pa_status pa_server_footprint(const pa_run_desc *desc, pa_repr repr, size_t *bytes);
+
+/* tuning_cache (host string, may be NULL): autotuner cache file whose shapes
+ * the batched sweep uses (see pa_autotune).  PA_ERR_NOMEM if the arena
+ * cannot hold the slot table. */
+pa_status pa_server_create(pa_repr repr, void *dev_arena, size_t arena_bytes, int32_t max_slots,
+                           const char *tuning_cache, void *hip_stream, pa_server **out);
+
+/* Admits one run and enqueues its step (i) and the measurement at i = 0.
+ * *slot receives its slot.  PA_ERR_CAPACITY: no free slot; PA_ERR_NOMEM:
+ * its footprint does not fit in the free arena space now (nothing changed;
+ * retry after a release). */
+pa_status pa_server_admit(pa_server *srv, const pa_run_desc *desc, int32_t *slot);
+
+/* Enqueues one temperature step for every resident run that has not
+ * reached its last temperature.  finished (host, capacity max_slots)
+ * receives the slots whose run reached its last temperature in this step
+ * (*n_finished of them); their records are complete once the stream has
+ * passed this step. */
+pa_status pa_server_step(pa_server *srv, int32_t *finished, int32_t *n_finished);
+
+/* Temperature index a resident run has been advanced to (as enqueued). */
+pa_status pa_server_progress(pa_server *srv, int32_t slot, int32_t *i_done);
+
+/* Copies a resident run's records to host_out (host [K][n_pop]).  sync = 1
+ * waits for the copy; sync = 0 only enqueues it (host_out should then be
+ * pinned memory and must not be read before the stream has passed it). */
+pa_status pa_server_read_obs(pa_server *srv, int32_t slot, pa_obs *host_out, int32_t sync);
+
+/* Frees a slot and its arena space for later admissions.  Work already
+ * enqueued for it (including an unsynchronised pa_server_read_obs) still
+ * completes first. */
+pa_status pa_server_release(pa_server *srv, int32_t slot);
+
+/* Occupancy: resident runs, arena bytes in use, largest free extent (any
+ * pointer may be NULL). */
+pa_status pa_server_info(pa_server *srv, int32_t *resident, size_t *bytes_used, size_t *largest_free);
+
+const char *pa_server_last_error(pa_server *srv);
+
+/* Synchronises the stream and releases the server (not the arena). */
+pa_status pa_server_destroy(pa_server *srv);
 
 /* Text of the first HIP error that made the context fail ("none" if it has
  * not failed).  The string is static; do not free it. */

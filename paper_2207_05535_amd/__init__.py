@@ -79,8 +79,20 @@ def lib():
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
             "pa_set_tuning": [vp, i32, i32, i32, i32],
+            "pa_set_persistent": [vp, i32],
+            "pa_get_tuning": [vp, i32, vp, vp, vp, vp],
+            "pa_autotune": [vp, i32, C.c_char_p, vp, vp],
             "pa_read_stats": [vp, vp],
             "pa_destroy": [vp],
+            "pa_server_footprint": [vp, i32, vp],
+            "pa_server_create": [i32, vp, C.c_size_t, i32, C.c_char_p, vp, vp],
+            "pa_server_admit": [vp, vp, vp],
+            "pa_server_step": [vp, vp, vp],
+            "pa_server_progress": [vp, i32, vp],
+            "pa_server_read_obs": [vp, i32, vp, i32],
+            "pa_server_release": [vp, i32],
+            "pa_server_info": [vp, vp, vp, vp],
+            "pa_server_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -90,6 +102,8 @@ def lib():
         L.pa_status_str.restype = C.c_char_p
         L.pa_last_error.argtypes = [vp]
         L.pa_last_error.restype = C.c_char_p
+        L.pa_server_last_error.argtypes = [vp]
+        L.pa_server_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -143,11 +157,12 @@ def pa_create(runs, repr_, dev_ptr: int, nbytes: int, stream_ptr: int):
     return h
 
 
-def _chk(call, st, h=None):
+def _chk(call, st, h=None, server=False):
     if st:
         e = PAError(call, st)
         if st == PA_ERR_DEVICE and h is not None:
-            e.args = (e.args[0] + ": " + lib().pa_last_error(h).decode(),)
+            text = (lib().pa_server_last_error if server else lib().pa_last_error)(h)
+            e.args = (e.args[0] + ": " + text.decode(),)
         raise e
 
 
@@ -204,6 +219,23 @@ def pa_set_tuning(h, L, threads, groups_per_wg, dense_calls=3):
     _chk("pa_set_tuning", lib().pa_set_tuning(h, L, threads, groups_per_wg, dense_calls), h)
 
 
+def pa_set_persistent(h, on):
+    _chk("pa_set_persistent", lib().pa_set_persistent(h, int(on)), h)
+
+
+def pa_get_tuning(h, L):
+    v = [C.c_int32(0) for _ in range(4)]
+    _chk("pa_get_tuning", lib().pa_get_tuning(h, L, *[C.byref(x) for x in v]), h)
+    return dict(threads=v[0].value, groups=v[1].value, dense=v[2].value, persistent=v[3].value)
+
+
+def pa_autotune(h, steps, cache_path=None):
+    tried, rejected = C.c_int32(0), C.c_int32(0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _chk("pa_autotune", lib().pa_autotune(h, steps, path, C.byref(tried), C.byref(rejected)), h)
+    return dict(tried=tried.value, rejected=rejected.value)
+
+
 def pa_read_stats(h):
     out = np.zeros(3, np.uint64)
     _chk("pa_read_stats", lib().pa_read_stats(h, _p(out)), h)
@@ -212,6 +244,63 @@ def pa_read_stats(h):
 
 def pa_destroy(h):
     _chk("pa_destroy", lib().pa_destroy(h))
+
+
+def pa_server_footprint(desc, repr_) -> int:
+    arr, _keep = make_descs([desc])
+    n = C.c_size_t(0)
+    _chk("pa_server_footprint", lib().pa_server_footprint(arr, REPRS[repr_], C.byref(n)))
+    return n.value
+
+
+def pa_server_create(repr_, dev_ptr: int, nbytes: int, max_slots: int, tuning_cache, stream_ptr: int):
+    h = C.c_void_p()
+    path = None if tuning_cache is None else os.fsencode(tuning_cache)
+    _chk("pa_server_create", lib().pa_server_create(REPRS[repr_], C.c_void_p(dev_ptr), nbytes, max_slots,
+                                                    path, C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def pa_server_admit(h, desc):
+    """Slot of the admitted run, or None when it does not fit now
+    (PA_ERR_NOMEM) or no slot is free (PA_ERR_CAPACITY)."""
+    arr, _keep = make_descs([desc])
+    slot = C.c_int32(-1)
+    st = lib().pa_server_admit(h, arr, C.byref(slot))
+    if st in (PA_ERR_NOMEM, PA_ERR_CAPACITY):
+        return None
+    _chk("pa_server_admit", st, h, server=True)
+    return slot.value
+
+
+def pa_server_step(h, finished):
+    n = C.c_int32(0)
+    _chk("pa_server_step", lib().pa_server_step(h, _p(finished), C.byref(n)), h, server=True)
+    return [int(x) for x in finished[:n.value]]
+
+
+def pa_server_progress(h, slot):
+    i = C.c_int32(0)
+    _chk("pa_server_progress", lib().pa_server_progress(h, slot, C.byref(i)), h, server=True)
+    return i.value
+
+
+def pa_server_read_obs(h, slot, out, sync=True):
+    _chk("pa_server_read_obs", lib().pa_server_read_obs(h, slot, C.c_void_p(out), int(sync)), h, server=True)
+
+
+def pa_server_release(h, slot):
+    _chk("pa_server_release", lib().pa_server_release(h, slot), h, server=True)
+
+
+def pa_server_info(h):
+    n, used, free = C.c_int32(0), C.c_size_t(0), C.c_size_t(0)
+    _chk("pa_server_info", lib().pa_server_info(h, C.byref(n), C.byref(used), C.byref(free)), h, server=True)
+    return dict(resident=n.value, bytes_used=used.value, largest_free=free.value)
+
+
+def pa_server_destroy(h):
+    _chk("pa_server_destroy", lib().pa_server_destroy(h))
 
 
 # ------------------------------------------------------------ convenience
@@ -304,6 +393,17 @@ class Context:
 
     def set_tuning(self, L, threads, groups_per_wg, dense_calls=3):
         pa_set_tuning(self.h, L, threads, groups_per_wg, dense_calls)
+
+    def set_persistent(self, on):
+        pa_set_persistent(self.h, on)
+
+    def tuning(self, L):
+        return pa_get_tuning(self.h, L)
+
+    def autotune(self, steps=3, cache_path=None):
+        """Search launch shapes on this context's own next steps (its state
+        is left unchanged); returns {'tried': n, 'rejected': n}."""
+        return pa_autotune(self.h, steps, cache_path)
 
     def stats(self):
         """(word-site updates, Philox calls, attempted flips) of the sweeps."""

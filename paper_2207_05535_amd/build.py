@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpa.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "pa_api.hip"]
+SOURCES = ["kernels.hip", "pa_api.hip", "pa_autotune.hip", "pa_serve.hip"]
 ARCH = os.environ.get("PA_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -210,7 +210,7 @@ __global__ void k_init_spins(const Item *items, const RunInfo *runs)
     }
 }
 
-__global__ void k_init_fam(const RunInfo *runs, int npop_ctx)
+__global__ void k_init_fam(const RunInfo *runs)
 {
     const RunInfo &R = runs[blockIdx.x];
     for (int p = 0; p < R.npop; ++p)
@@ -227,7 +227,7 @@ __global__ void k_init_fam(const RunInfo *runs, int npop_ctx)
 // (exact); for multinomial resampling also the chunk-local exclusive prefix
 // of X_j.  The temperature index is i = (index of the population) + 1.
 __global__ void __launch_bounds__(CH_THREADS) k_rw_chunk(const ChunkItem *items, const RunInfo *runs,
-                                                          const PopState *st, int npop_ctx)
+                                                          const PopState *st)
 {
     __shared__ uint64_t lds64[CH_THREADS / 64 + 1];
     __shared__ double ldsd[CH_THREADS / 64];
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(CH_THREADS) k_rw_chunk(const ChunkItem *items,
 
 // ln Q_i = ln S - ln R_{i-1} - dbeta E_min and A_i = A_{i-1} + ln Q_i,
 // Eqs. (QBoltz), (F); chunk bases of the X prefix for multinomial draws.
-__global__ void k_rw_finish(const RunInfo *runs, PopState *st, int npop_ctx)
+__global__ void k_rw_finish(const RunInfo *runs, PopState *st)
 {
     __shared__ uint64_t lds64[257];
     const int run = blockIdx.x, pop = blockIdx.y;
@@ -447,13 +447,17 @@ __global__ void __launch_bounds__(CH_THREADS) k_cnt_scan_chunk(const ChunkItem *
     if (threadIdx.x == 0) R.tot32[it.pop][it.chunk] = tot;
 }
 
-__device__ void freeze_run(const RunInfo &R, PopState &S, int pop, int i, int32_t status,
-                           int n_runs, int npop_ctx)
+__device__ __forceinline__ pa_obs &obs_at(const RunInfo &R, int i, int pop)
+{
+    return R.obs[(size_t)i * R.obs_stride + R.obs_off + pop];
+}
+
+__device__ void freeze_run(const RunInfo &R, PopState &S, int pop, int i, int32_t status)
 {
     for (int k = i + threadIdx.x; k < R.K; k += blockDim.x) {
         pa_obs o = {};
         o.status = status;
-        R.obs[((size_t)k * n_runs + R.run) * npop_ctx + pop] = o;
+        obs_at(R, k, pop) = o;
     }
     if (threadIdx.x == 0) {
         S.status = status;
@@ -464,7 +468,7 @@ __device__ void freeze_run(const RunInfo &R, PopState &S, int pop, int i, int32_
 // Chunk bases of the count prefix, R_i = sum r_j; capacity and empty-
 // population checks (the run is frozen with that status); otherwise the
 // new population becomes current: the copy reads buffer src, writes cur.
-__global__ void k_cnt_finish(const RunInfo *runs, PopState *st, int n_runs, int npop_ctx)
+__global__ void k_cnt_finish(const RunInfo *runs, PopState *st)
 {
     __shared__ int64_t lds64[257];
     const int run = blockIdx.x, pop = blockIdx.y;
@@ -485,11 +489,11 @@ __global__ void k_cnt_finish(const RunInfo *runs, PopState *st, int n_runs, int 
     }
     __syncthreads();
     if (carry > R.R_cap) {
-        freeze_run(R, S, pop, S.i, PA_ERR_CAPACITY, n_runs, npop_ctx);
+        freeze_run(R, S, pop, S.i, PA_ERR_CAPACITY);
         return;
     }
     if (carry == 0) {
-        freeze_run(R, S, pop, S.i, PA_ERR_NUMERIC, n_runs, npop_ctx);
+        freeze_run(R, S, pop, S.i, PA_ERR_NUMERIC);
         return;
     }
     if (threadIdx.x == 0) {
@@ -876,16 +880,47 @@ __device__ __forceinline__ void sweep_dispatch(const SweepItem &it, const RunInf
     }
 }
 
-__global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, const RunInfo *runs,
-                                                    const PopState *st, int dense, unsigned long long *stats)
+__device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *runs, const PopState *st,
+                                          uint64_t *lds, int dense, unsigned long long *stats)
 {
-    extern __shared__ uint64_t lds[];
-    const SweepItem it = items[blockIdx.x];
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S) || R.theta == 0) return;
     if (R.model == PA_EA_PMJ) sweep_dispatch<true>(it, R, S, lds, dense, stats);
     else sweep_dispatch<false>(it, R, S, lds, dense, stats);
+}
+
+// One workgroup per item, or (queue != nullptr) a persistent grid whose
+// workgroups take items in list order from a ticket counter.  The items are
+// listed largest first, so the last tickets are the cheapest.  queue[0] is
+// the next ticket, queue[1] counts workgroups that found the list empty; the
+// last of them resets both, so the next launch (or graph replay) starts
+// from zero without a separate clear.
+__global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int n_items, const RunInfo *runs,
+                                                    const PopState *st, int dense, unsigned long long *stats,
+                                                    unsigned int *queue)
+{
+    extern __shared__ uint64_t lds[];
+    if (queue == nullptr) {
+        sweep_one(items[blockIdx.x], runs, st, lds, dense, stats);
+        return;
+    }
+    __shared__ unsigned int ticket;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) ticket = atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const unsigned int t = ticket;
+        if (t >= (unsigned int)n_items) break;
+        sweep_one(items[t], runs, st, lds, dense, stats);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
+            atomicExch(&queue[0], 0u);
+            atomicExch(&queue[1], 0u);
+        }
+    }
 }
 
 // -------------------------------------------------------------- step (v)
@@ -1135,7 +1170,7 @@ __global__ void __launch_bounds__(CH_THREADS) k_fam_chunk(const ChunkItem *items
 // Per run: the record of temperature i for each population, and the
 // accumulators reset.  With two populations both records carry the pair
 // sums.
-__global__ void k_finalize(const RunInfo *runs, PopState *st, int n_runs, int npop_ctx)
+__global__ void k_finalize(const RunInfo *runs, PopState *st, int n_runs)
 {
     const int run = blockIdx.x * blockDim.x + threadIdx.x;
     if (run >= n_runs) return;
@@ -1166,7 +1201,7 @@ __global__ void k_finalize(const RunInfo *runs, PopState *st, int n_runs, int np
         o.nFam = S.acc[A_NFAM];
         o.Emin = S.EminAcc;
         o.status = PA_OK;
-        R.obs[((size_t)i * n_runs + run) * npop_ctx + p] = o;
+        obs_at(R, i, p) = o;
         S.Emin = S.EminAcc;
         for (int k = 0; k < NACC; ++k) S.acc[k] = 0;
         S.EminAcc = INT32_MAX;
@@ -1347,9 +1382,9 @@ hipError_t launch_fill_u32(void *p, uint32_t v, size_t n, hipStream_t s)
 
 hipError_t launch_init(const LaunchCtx &c, const uint64_t *dseed)
 {
-    k_init_couplings<<<c.n_runs, 256, 0, c.stream>>>(c.runs, dseed);
+    k_init_couplings<<<c.n_runs, 256, 0, c.stream>>>(c.runs + c.run0, dseed);
     PA_CHECK_LAUNCH();
-    k_init_fam<<<c.n_runs, 256, 0, c.stream>>>(c.runs, c.npop_ctx);
+    k_init_fam<<<c.n_runs, 256, 0, c.stream>>>(c.runs + c.run0);
     PA_CHECK_LAUNCH();
     if (c.repr == PA_MSC64) k_init_spins<PA_MSC64><<<c.n_items, 256, 0, c.stream>>>(c.items, c.runs);
     else k_init_spins<PA_INT8><<<c.n_items, 256, 0, c.stream>>>(c.items, c.runs);
@@ -1358,9 +1393,10 @@ hipError_t launch_init(const LaunchCtx &c, const uint64_t *dseed)
 
 hipError_t launch_anneal(const LaunchCtx &c)
 {
-    k_rw_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st, c.npop_ctx);
+    k_rw_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
-    k_rw_finish<<<dim3(c.n_runs, c.npop_ctx), 256, 0, c.stream>>>(c.runs, c.st, c.npop_ctx);
+    k_rw_finish<<<dim3(c.n_runs, c.npop_ctx), 256, 0, c.stream>>>(c.runs + c.run0,
+                                                                 c.st + (size_t)c.run0 * MAX_POP);
     return hipGetLastError();
 }
 
@@ -1374,7 +1410,8 @@ hipError_t launch_resample(const LaunchCtx &c)
         k_cnt_scan_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
         PA_CHECK_LAUNCH();
     }
-    k_cnt_finish<<<dim3(c.n_runs, c.npop_ctx), 256, 0, c.stream>>>(c.runs, c.st, c.n_runs, c.npop_ctx);
+    k_cnt_finish<<<dim3(c.n_runs, c.npop_ctx), 256, 0, c.stream>>>(c.runs + c.run0,
+                                                                  c.st + (size_t)c.run0 * MAX_POP);
     PA_CHECK_LAUNCH();
     k_parent<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
@@ -1428,9 +1465,24 @@ hipError_t prepare_msc_lds(size_t bytes)
 
 hipError_t launch_sweep_msc(const LaunchCtx &c)
 {
-    k_sweep_msc<<<c.n_sweep_items, c.sweep_threads, c.sweep_lds, c.stream>>>(c.sweep_items, c.runs, c.st,
-                                                                            c.sweep_dense, c.stats);
+    if (c.n_sweep_items == 0) return hipSuccess;
+    const bool persistent = c.sweep_grid > 0 && c.sweep_grid < c.n_sweep_items;
+    const int grid = persistent ? c.sweep_grid : c.n_sweep_items;
+    k_sweep_msc<<<grid, c.sweep_threads, c.sweep_lds, c.stream>>>(c.sweep_items, c.n_sweep_items, c.runs, c.st,
+                                                                 c.sweep_dense, c.stats,
+                                                                 persistent ? c.sweep_queue : nullptr);
     return hipGetLastError();
+}
+
+int sweep_msc_resident(int threads, size_t lds)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_msc, threads, lds) != hipSuccess) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
 }
 
 hipError_t launch_measure(const LaunchCtx &c)
@@ -1440,7 +1492,8 @@ hipError_t launch_measure(const LaunchCtx &c)
     PA_CHECK_LAUNCH();
     k_fam_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
-    k_finalize<<<(c.n_runs + 63) / 64, 64, 0, c.stream>>>(c.runs, c.st, c.n_runs, c.npop_ctx);
+    k_finalize<<<(c.n_runs + 63) / 64, 64, 0, c.stream>>>(c.runs + c.run0, c.st + (size_t)c.run0 * MAX_POP,
+                                                          c.n_runs);
     return hipGetLastError();
 }
 

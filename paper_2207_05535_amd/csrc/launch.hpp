@@ -14,12 +14,14 @@ struct LaunchCtx {
     int n_items;
     const ChunkItem *chunk_items;  // device: every (run, pop, chunk < chunks_cap)
     int n_chunk_items;
-    int n_runs, npop_ctx;
+    int run0, n_runs, npop_ctx;    // per-run launches cover runs [run0, run0 + n_runs)
     int repr;
     bool any_multinomial;
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
     const SweepItem *sweep_items;  // device [n_sweep_items]
     int n_sweep_items, sweep_threads, sweep_dense;
+    int sweep_grid;                // > 0: persistent grid of this many workgroups
+    unsigned int *sweep_queue;     // device [2] ticket counters of the persistent grid
     size_t sweep_lds;
     hipStream_t stream;
 };
@@ -36,5 +38,6 @@ hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, i
 int int8_tile_rows(int L);
 size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);
+int sweep_msc_resident(int threads, size_t lds);   // workgroups resident on the whole device, 0 on error
 
 }  // namespace pa

@@ -14,15 +14,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pa.h"
-#include "launch.hpp"
-#include "pa_internal.hpp"
+#include "ctx.hpp"
 
 using namespace pa;
 
 namespace {
-
-enum Phase { PH_MEASURED = 0, PH_ANNEALED = 1, PH_RESAMPLED = 2, PH_SWEPT = 3 };
 
 constexpr uint64_t CKPT_MAGIC = 0x50414d4933353558ull;  // "PAMI355X"
 constexpr uint32_t CKPT_VERSION = 1;
@@ -34,37 +30,14 @@ struct CkptHeader {
     int32_t n_runs, i, phase, npop_ctx;
 };
 
-// Offsets of every buffer inside the workspace (256-byte aligned).
-struct Planner {
-    size_t off = 0;
-    size_t take(size_t bytes)
-    {
-        const size_t o = off;
-        off += (bytes + 255) & ~(size_t)255;
-        return o;
-    }
-};
+bool same_table(const TableOff &t, int N, const pa_run_desc &d)
+{
+    return t.N == N && t.K == d.K && std::memcmp(t.beta_src, d.beta, sizeof(double) * d.K) == 0;
+}
 
-struct RunOff {
-    size_t spins[MAX_POP][2], E[MAX_POP][2], fam[MAX_POP][2], r[MAX_POP], C[MAX_POP], parent[MAX_POP],
-        P[MAX_POP], famcnt[MAX_POP], partS[MAX_POP], tot64[MAX_POP], base64[MAX_POP], tot32[MAX_POP],
-        base32[MAX_POP], qh, jbits;
-    int table;
-};
+}  // namespace
 
-struct TableOff {
-    size_t X, x, T, beta;
-    int N, K;
-    const double *beta_src;
-};
-
-struct Layout {
-    std::vector<RunOff> runs;
-    std::vector<TableOff> tables;
-    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items;
-    int n_items, n_chunk_items, npop_ctx, Kmax, maxN;
-    size_t total;
-};
+namespace pa {
 
 bool desc_ok(const pa_run_desc &d, pa_repr repr)
 {
@@ -86,13 +59,44 @@ bool desc_ok(const pa_run_desc &d, pa_repr repr)
     return true;
 }
 
-bool same_table(const TableOff &t, int N, const pa_run_desc &d)
+void plan_run_buffers(Planner &P, const pa_run_desc &d, pa_repr repr, RunOff &o)
 {
-    return t.N == N && t.K == d.K && std::memcmp(t.beta_src, d.beta, sizeof(double) * d.K) == 0;
+    std::memset(&o, 0, sizeof(o));
+    const int N = d.L * d.L;
+    const int npop = n_pop_of(d.overlap);
+    const size_t site_bytes = repr == PA_MSC64 ? 8 : 64;
+    const size_t nch = chunks_cap_of(d);
+    for (int p = 0; p < npop; ++p) {
+        for (int b = 0; b < 2; ++b) {
+            o.spins[p][b] = P.take((size_t)groups_cap_of(d) * N * site_bytes);
+            o.E[p][b] = P.take(sizeof(int32_t) * d.R_cap);
+            o.fam[p][b] = P.take(sizeof(int32_t) * d.R_cap);
+        }
+        o.r[p] = P.take(sizeof(int32_t) * d.R_cap);
+        o.C[p] = P.take(sizeof(int32_t) * (d.R_cap + 1));
+        o.parent[p] = P.take(sizeof(int32_t) * d.R_cap);
+        o.P[p] = d.resampling == PA_MULTINOMIAL ? P.take(sizeof(uint64_t) * (d.R_cap + 1)) : 0;
+        o.famcnt[p] = P.take(sizeof(int32_t) * d.R);
+        o.partS[p] = P.take(sizeof(double) * nch);
+        o.tot64[p] = P.take(sizeof(uint64_t) * nch);
+        o.base64[p] = P.take(sizeof(uint64_t) * nch);
+        o.tot32[p] = P.take(sizeof(int32_t) * nch);
+        o.base32[p] = P.take(sizeof(int32_t) * nch);
+    }
+    o.qh = d.qhist ? P.take(sizeof(int32_t) * (size_t)npop * d.K * (N + 1)) : 0;
+    o.jbits = P.take(N);
 }
 
-int groups_cap_of(const pa_run_desc &d) { return (d.R_cap + 63) / 64; }
-int chunks_cap_of(const pa_run_desc &d) { return (d.R_cap + CH - 1) / CH; }
+void plan_table(Planner &P, int N, const pa_run_desc &d, TableOff &T)
+{
+    T.N = N;
+    T.K = d.K;
+    T.beta_src = d.beta;
+    T.X = P.take(sizeof(uint64_t) * (size_t)d.K * (N + 1));
+    T.x = P.take(sizeof(double) * (size_t)d.K * (N + 1));
+    T.T = P.take(sizeof(uint64_t) * 2 * d.K);
+    T.beta = P.take(sizeof(double) * d.K);
+}
 
 Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
 {
@@ -110,6 +114,7 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     Lo.popstate = P.take(sizeof(PopState) * n_runs * MAX_POP);
     Lo.dseed = P.take(sizeof(uint64_t) * n_runs);
     Lo.stats = P.take(sizeof(uint64_t) * NSTAT);
+    Lo.queue = P.take(sizeof(uint32_t) * 2);
     Lo.n_items = 0;
     Lo.n_chunk_items = 0;
     for (int r = 0; r < n_runs; ++r) {
@@ -132,93 +137,16 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
             if (same_table(Lo.tables[k], N, d)) t = (int)k;
         if (t < 0) {
             TableOff T;
-            T.N = N;
-            T.K = d.K;
-            T.beta_src = d.beta;
-            T.X = P.take(sizeof(uint64_t) * (size_t)d.K * (N + 1));
-            T.x = P.take(sizeof(double) * (size_t)d.K * (N + 1));
-            T.T = P.take(sizeof(uint64_t) * 2 * d.K);
-            T.beta = P.take(sizeof(double) * d.K);
+            plan_table(P, N, d, T);
             Lo.tables.push_back(T);
             t = (int)Lo.tables.size() - 1;
         }
-        RunOff &o = Lo.runs[r];
-        std::memset(&o, 0, sizeof(o));
-        o.table = t;
-        const int npop = n_pop_of(d.overlap);
-        const size_t site_bytes = repr == PA_MSC64 ? 8 : 64;
-        const size_t nch = chunks_cap_of(d);
-        for (int p = 0; p < npop; ++p) {
-            for (int b = 0; b < 2; ++b) {
-                o.spins[p][b] = P.take((size_t)groups_cap_of(d) * N * site_bytes);
-                o.E[p][b] = P.take(sizeof(int32_t) * d.R_cap);
-                o.fam[p][b] = P.take(sizeof(int32_t) * d.R_cap);
-            }
-            o.r[p] = P.take(sizeof(int32_t) * d.R_cap);
-            o.C[p] = P.take(sizeof(int32_t) * (d.R_cap + 1));
-            o.parent[p] = P.take(sizeof(int32_t) * d.R_cap);
-            o.P[p] = d.resampling == PA_MULTINOMIAL ? P.take(sizeof(uint64_t) * (d.R_cap + 1)) : 0;
-            o.famcnt[p] = P.take(sizeof(int32_t) * d.R);
-            o.partS[p] = P.take(sizeof(double) * nch);
-            o.tot64[p] = P.take(sizeof(uint64_t) * nch);
-            o.base64[p] = P.take(sizeof(uint64_t) * nch);
-            o.tot32[p] = P.take(sizeof(int32_t) * nch);
-            o.base32[p] = P.take(sizeof(int32_t) * nch);
-        }
-        o.qh = d.qhist ? P.take(sizeof(int32_t) * (size_t)npop * d.K * (N + 1)) : 0;
-        o.jbits = P.take(N);
+        plan_run_buffers(P, d, repr, Lo.runs[r]);
+        Lo.runs[r].table = t;
     }
     Lo.total = P.off;
     return Lo;
 }
-
-}  // namespace
-
-struct pa_ctx {
-    int n_runs = 0;
-    pa_repr repr = PA_INT8;
-    hipStream_t stream = nullptr;
-    uint8_t *ws = nullptr;
-    Layout lo;
-    std::vector<pa_run_desc> descs;
-    std::vector<std::vector<double>> betas;
-    std::vector<RunInfo> hinfo;
-    LaunchCtx lc;
-    int i = 0;
-    int phase = PH_MEASURED;
-    bool failed = false;
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_def = nullptr;
-    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
-    int lds_limit = 65536;
-    int sweep_threads = 512;
-    int sweep_dense = 3;                // Philox calls every site makes in lockstep
-    std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
-    bool any_multinomial = false;
-    hipError_t last = hipSuccess;
-};
-
-namespace {
-
-template <typename T>
-T *at(pa_ctx *c, size_t off)
-{
-    return (T *)(c->ws + off);
-}
-
-pa_status dev_fail(pa_ctx *c, hipError_t e = hipSuccess)
-{
-    c->failed = true;
-    if (e == hipSuccess) e = hipGetLastError();
-    if (c->last == hipSuccess) c->last = e;
-    return PA_ERR_DEVICE;
-}
-
-#define PA_HIP(ctx, expr)                                  \
-    do {                                                   \
-        const hipError_t e_ = (expr);                      \
-        if (e_ != hipSuccess) return dev_fail(ctx, e_);    \
-    } while (0)
 
 void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::vector<double> &x,
                     std::vector<uint64_t> &T)
@@ -243,11 +171,83 @@ void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::
     }
 }
 
+RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8_t *tbase, const TableOff &T,
+                     pa_obs *obs, int obs_stride, int obs_off)
+{
+    RunInfo I;
+    std::memset(&I, 0, sizeof(I));
+    I.L = d.L;
+    I.N = d.L * d.L;
+    I.npop = n_pop_of(d.overlap);
+    I.R = d.R;
+    I.R_cap = d.R_cap;
+    I.theta = d.theta;
+    I.K = d.K;
+    I.model = d.model;
+    I.resampling = d.resampling;
+    I.overlap = d.overlap;
+    I.qhist = d.qhist;
+    I.groups_cap = groups_cap_of(d);
+    I.key0 = (uint32_t)(d.seed & 0xffffffffu);
+    I.key1 = (uint32_t)(d.seed >> 32);
+    I.obs_stride = obs_stride;
+    I.obs_off = obs_off;
+    for (int p = 0; p < I.npop; ++p) {
+        for (int b = 0; b < 2; ++b) {
+            I.spins[p][b] = base + o.spins[p][b];
+            I.E[p][b] = (int32_t *)(base + o.E[p][b]);
+            I.fam[p][b] = (int32_t *)(base + o.fam[p][b]);
+        }
+        I.r[p] = (int32_t *)(base + o.r[p]);
+        I.C[p] = (int32_t *)(base + o.C[p]);
+        I.parent[p] = (int32_t *)(base + o.parent[p]);
+        I.P[p] = d.resampling == PA_MULTINOMIAL ? (uint64_t *)(base + o.P[p]) : nullptr;
+        I.famcnt[p] = (int32_t *)(base + o.famcnt[p]);
+        I.partS[p] = (double *)(base + o.partS[p]);
+        I.tot64[p] = (uint64_t *)(base + o.tot64[p]);
+        I.base64[p] = (uint64_t *)(base + o.base64[p]);
+        I.tot32[p] = (int32_t *)(base + o.tot32[p]);
+        I.base32[p] = (int32_t *)(base + o.base32[p]);
+    }
+    I.obs = obs;
+    I.qh = d.qhist ? (int32_t *)(base + o.qh) : nullptr;
+    I.jbits = base + o.jbits;
+    I.tabX = (const uint64_t *)(tbase + T.X);
+    I.tabx = (const double *)(tbase + T.x);
+    I.tabT = (const uint64_t *)(tbase + T.T);
+    I.beta = (const double *)(tbase + T.beta);
+    return I;
+}
+
+PopState initial_popstate(const pa_run_desc &d)
+{
+    PopState S;
+    std::memset(&S, 0, sizeof(S));
+    S.i = 0;
+    S.cur = 0;
+    S.src = 0;
+    S.Rprev = d.R;
+    S.Rcur = d.R;
+    S.status = PA_OK;
+    S.moved = 1;
+    S.A = (double)d.L * d.L * std::log(2.0);   // ln Z(0) = N ln 2
+    S.EminAcc = INT32_MAX;
+    return S;
+}
+
 int default_groups(int L)
 {
     const int nh = L * L / 2;
     int G = (2048 + nh / 2) / nh;
     return G < 1 ? 1 : (G > 64 ? 64 : G);
+}
+
+pa_status dev_fail(pa_ctx *c, hipError_t e)
+{
+    c->failed = true;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (c->last == hipSuccess) c->last = e;
+    return PA_ERR_DEVICE;
 }
 
 int groups_for(const pa_ctx *c, int L)
@@ -276,6 +276,13 @@ bool plan_sweep(const pa_ctx *c, std::vector<SweepItem> &items, size_t &lds)
             for (int g = 0; g < groups_cap_of(d); g += G)
                 items.push_back({r, p, g, std::min(G, groups_cap_of(d) - g)});
     }
+    // largest items first (words of lattice per item), so the cheapest ones
+    // fill the tail of the launch; ties keep run order
+    std::stable_sort(items.begin(), items.end(), [c](const SweepItem &a, const SweepItem &b) {
+        const long wa = (long)a.ngroups * c->descs[a.run].L * c->descs[a.run].L;
+        const long wb = (long)b.ngroups * c->descs[b.run].L * c->descs[b.run].L;
+        return wa > wb;
+    });
     return true;
 }
 
@@ -293,6 +300,12 @@ pa_status upload_sweep_plan(pa_ctx *c)
     c->lc.sweep_threads = c->sweep_threads;
     c->lc.sweep_dense = c->sweep_dense;
     c->lc.sweep_lds = lds;
+    c->lc.sweep_grid = 0;
+    if (c->sweep_persistent) {
+        const int resident = sweep_msc_resident(c->sweep_threads, lds);
+        if (resident <= 0) return dev_fail(c);
+        c->lc.sweep_grid = resident;
+    }
     return PA_OK;
 }
 
@@ -314,7 +327,20 @@ pa_status enqueue_step(pa_ctx *c)
     return PA_OK;
 }
 
-}  // namespace
+// A captured step graph holds the launch shapes it was captured with.
+void drop_graph(pa_ctx *c)
+{
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    if (c->graph_def) {
+        (void)hipGraphDestroy(c->graph_def);
+        c->graph_def = nullptr;
+    }
+}
+
+}  // namespace pa
 
 extern "C" {
 
@@ -385,60 +411,13 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         const pa_run_desc &d = c->descs[r];
         const RunOff &o = Lo.runs[r];
         const TableOff &T = Lo.tables[o.table];
-        RunInfo &I = c->hinfo[r];
-        std::memset(&I, 0, sizeof(I));
-        I.L = d.L;
-        I.N = d.L * d.L;
-        I.npop = n_pop_of(d.overlap);
-        I.R = d.R;
-        I.R_cap = d.R_cap;
-        I.theta = d.theta;
-        I.K = d.K;
-        I.model = d.model;
-        I.resampling = d.resampling;
-        I.overlap = d.overlap;
-        I.qhist = d.qhist;
-        I.groups_cap = groups_cap_of(d);
-        I.key0 = (uint32_t)(d.seed & 0xffffffffu);
-        I.key1 = (uint32_t)(d.seed >> 32);
-        I.run = r;
-        for (int p = 0; p < I.npop; ++p) {
-            for (int b = 0; b < 2; ++b) {
-                I.spins[p][b] = at<uint8_t>(c, o.spins[p][b]);
-                I.E[p][b] = at<int32_t>(c, o.E[p][b]);
-                I.fam[p][b] = at<int32_t>(c, o.fam[p][b]);
-            }
-            I.r[p] = at<int32_t>(c, o.r[p]);
-            I.C[p] = at<int32_t>(c, o.C[p]);
-            I.parent[p] = at<int32_t>(c, o.parent[p]);
-            I.P[p] = d.resampling == PA_MULTINOMIAL ? at<uint64_t>(c, o.P[p]) : nullptr;
-            I.famcnt[p] = at<int32_t>(c, o.famcnt[p]);
-            I.partS[p] = at<double>(c, o.partS[p]);
-            I.tot64[p] = at<uint64_t>(c, o.tot64[p]);
-            I.base64[p] = at<uint64_t>(c, o.base64[p]);
-            I.tot32[p] = at<int32_t>(c, o.tot32[p]);
-            I.base32[p] = at<int32_t>(c, o.base32[p]);
-            PopState &S = hst[(size_t)r * MAX_POP + p];
-            std::memset(&S, 0, sizeof(S));
-            S.i = 0;
-            S.cur = 0;
-            S.src = 0;
-            S.Rprev = d.R;
-            S.Rcur = d.R;
-            S.status = PA_OK;
-            S.moved = 1;
-            S.A = (double)I.N * std::log(2.0);   // ln Z(0) = N ln 2
-            S.EminAcc = INT32_MAX;
-            for (int g = 0; g < I.groups_cap; ++g) items.push_back({r, p, g, 0});
+        c->hinfo[r] = make_runinfo(d, c->ws, o, c->ws, T, at<pa_obs>(c, Lo.obs), n_runs * Lo.npop_ctx,
+                                   r * Lo.npop_ctx);
+        for (int p = 0; p < n_pop_of(d.overlap); ++p) {
+            hst[(size_t)r * MAX_POP + p] = initial_popstate(d);
+            for (int g = 0; g < groups_cap_of(d); ++g) items.push_back({r, p, g, 0});
             for (int k = 0; k < chunks_cap_of(d); ++k) chunks.push_back({r, p, k, 0});
         }
-        I.obs = at<pa_obs>(c, Lo.obs);
-        I.qh = d.qhist ? at<int32_t>(c, o.qh) : nullptr;
-        I.jbits = at<uint8_t>(c, o.jbits);
-        I.tabX = at<uint64_t>(c, T.X);
-        I.tabx = at<double>(c, T.x);
-        I.tabT = at<uint64_t>(c, T.T);
-        I.beta = at<double>(c, T.beta);
         dseed[r] = d.disorder_seed;
     }
 
@@ -448,11 +427,14 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.n_items = Lo.n_items;
     c->lc.chunk_items = at<ChunkItem>(c, Lo.chunk_items);
     c->lc.n_chunk_items = Lo.n_chunk_items;
+    c->lc.run0 = 0;
     c->lc.n_runs = n_runs;
     c->lc.npop_ctx = Lo.npop_ctx;
     c->lc.repr = repr;
     c->lc.any_multinomial = c->any_multinomial;
     c->lc.stats = at<unsigned long long>(c, Lo.stats);
+    c->lc.sweep_queue = at<unsigned int>(c, Lo.queue);
+    c->lc.sweep_grid = 0;
     c->lc.stream = c->stream;
 
     auto fail = [&](pa_status s) {
@@ -513,6 +495,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
                  hipSuccess;
     }
     ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, 2 * NSTAT, s) == hipSuccess;
+    ok = ok && launch_fill_u32(at<void>(c, Lo.queue), 0, 2, s) == hipSuccess;
     ok = ok && launch_fill_u32(at<void>(c, Lo.obs), 0,
                                sizeof(pa_obs) / 4 * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx, s) == hipSuccess;
     ok = ok && (repr != PA_MSC64 || upload_sweep_plan(c) == PA_OK);
@@ -777,16 +760,30 @@ pa_status pa_set_tuning(pa_ctx *c, int32_t L, int32_t threads, int32_t groups_pe
         c->groups_per_wg = old_groups;
         return PA_ERR_ARG;
     }
-    // a captured step graph holds the old launch shape
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
-    }
-    if (c->graph_def) {
-        (void)hipGraphDestroy(c->graph_def);
-        c->graph_def = nullptr;
-    }
+    drop_graph(c);
     return upload_sweep_plan(c);
+}
+
+pa_status pa_set_persistent(pa_ctx *c, int32_t on)
+{
+    if (!c || (on != 0 && on != 1)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED) return PA_ERR_STATE;
+    c->sweep_persistent = on != 0;
+    if (c->repr != PA_MSC64) return PA_OK;
+    drop_graph(c);
+    return upload_sweep_plan(c);
+}
+
+pa_status pa_get_tuning(pa_ctx *c, int32_t L, int32_t *threads, int32_t *groups_per_wg, int32_t *dense_calls,
+                        int32_t *persistent)
+{
+    if (!c || L < 4 || (L & 1)) return PA_ERR_ARG;
+    if (threads) *threads = c->sweep_threads;
+    if (groups_per_wg) *groups_per_wg = groups_for(c, L);
+    if (dense_calls) *dense_calls = c->sweep_dense;
+    if (persistent) *persistent = c->sweep_persistent ? 1 : 0;
+    return PA_OK;
 }
 
 pa_status pa_read_stats(pa_ctx *c, uint64_t *host_out)

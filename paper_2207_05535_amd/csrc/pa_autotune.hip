@@ -1,0 +1,350 @@
+// pa_autotune.hip -- launch-shape search for the batched sweep.
+//
+// The batched sweep has four knobs that change its speed and never its
+// results: threads per workgroup, replica groups per workgroup (per lattice
+// size L), Philox calls made in lockstep before the undecided sites are
+// compacted, and one-workgroup-per-item versus a persistent ticket-queue
+// grid.  The tuner runs a few real temperature steps of the caller's own
+// context from a snapshot for each candidate, times the sweep launches with
+// HIP events, and keeps the fastest candidate whose records and exact work
+// counters hash to the same value as the starting shape's; a candidate with
+// a different hash is rejected and counted.  The context is left in its
+// starting state with the chosen shape applied.
+//
+// Results are cached in a small JSON file keyed by (device architecture,
+// representation, L), one entry per line.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+
+using namespace pa;
+
+namespace {
+
+struct Shape {
+    int threads, dense, persistent;
+    std::map<int, int> groups;   // L -> groups per workgroup
+};
+
+struct CacheEntry {
+    std::string arch, repr;
+    int L, threads, groups, dense, persistent;
+    double sweep_us;
+};
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::vector<CacheEntry> read_cache(const char *path)
+{
+    std::vector<CacheEntry> out;
+    FILE *f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return out;
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char arch[64] = {0}, repr[16] = {0};
+        CacheEntry e;
+        e.sweep_us = 0.0;
+        const int n = std::sscanf(line,
+                                  " {\"arch\": \"%63[^\"]\", \"repr\": \"%15[^\"]\", \"L\": %d, \"threads\": %d, "
+                                  "\"groups\": %d, \"dense\": %d, \"persistent\": %d, \"sweep_us\": %lf",
+                                  arch, repr, &e.L, &e.threads, &e.groups, &e.dense, &e.persistent, &e.sweep_us);
+        if (n >= 7) {
+            e.arch = arch;
+            e.repr = repr;
+            out.push_back(e);
+        }
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool write_cache(const char *path, const std::vector<CacheEntry> &entries)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"pa_tuning_cache\": 1, \"entries\": [\n");
+    for (size_t k = 0; k < entries.size(); ++k) {
+        const CacheEntry &e = entries[k];
+        std::fprintf(f,
+                     "  {\"arch\": \"%s\", \"repr\": \"%s\", \"L\": %d, \"threads\": %d, \"groups\": %d, "
+                     "\"dense\": %d, \"persistent\": %d, \"sweep_us\": %.3f}%s\n",
+                     e.arch.c_str(), e.repr.c_str(), e.L, e.threads, e.groups, e.dense, e.persistent, e.sweep_us,
+                     k + 1 < entries.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const uint8_t *b = (const uint8_t *)p;
+    for (size_t k = 0; k < n; ++k) {
+        h ^= b[k];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+// Applies a shape; false if it does not fit the device (nothing changed).
+bool apply_shape(pa_ctx *c, const Shape &s)
+{
+    const int t0 = c->sweep_threads, d0 = c->sweep_dense;
+    const bool p0 = c->sweep_persistent;
+    const auto g0 = c->groups_per_wg;
+    c->sweep_threads = s.threads;
+    c->sweep_dense = s.dense;
+    c->sweep_persistent = s.persistent != 0;
+    for (const auto &kv : s.groups) c->groups_per_wg[kv.first] = kv.second;
+    std::vector<SweepItem> probe;
+    size_t lds = 0;
+    if (!plan_sweep(c, probe, lds)) {
+        c->sweep_threads = t0;
+        c->sweep_dense = d0;
+        c->sweep_persistent = p0;
+        c->groups_per_wg = g0;
+        return false;
+    }
+    return true;
+}
+
+struct Tuner {
+    pa_ctx *c;
+    int steps;
+    uint8_t *snap = nullptr;    // pinned host copy of the whole workspace
+    int i0 = 0;
+    bool have_ref = false;
+    uint64_t ref_hash = 0;
+    std::vector<uint8_t> rec;   // host staging of the records
+
+    pa_status restore()
+    {
+        PA_HIP(c, hipMemcpyAsync(c->ws, snap, c->lo.total, hipMemcpyHostToDevice, c->stream));
+        PA_HIP(c, hipStreamSynchronize(c->stream));
+        return PA_OK;
+    }
+
+    // Runs the steps for the applied shape; *ms = summed sweep time,
+    // *match = records and work counters equal the reference's.
+    pa_status evaluate(double *ms, bool *match)
+    {
+        pa_status st = restore();
+        if (st != PA_OK) return st;
+        drop_graph(c);
+        st = upload_sweep_plan(c);
+        if (st != PA_OK) return st;
+        std::vector<hipEvent_t> ev(2 * steps);
+        for (auto &e : ev) PA_HIP(c, hipEventCreate(&e));
+        pa_status out = PA_OK;
+        for (int k = 0; k < steps && out == PA_OK; ++k) {
+            if (launch_anneal(c->lc) != hipSuccess || launch_resample(c->lc) != hipSuccess ||
+                hipEventRecord(ev[2 * k], c->stream) != hipSuccess || launch_sweep_msc(c->lc) != hipSuccess ||
+                hipEventRecord(ev[2 * k + 1], c->stream) != hipSuccess || launch_measure(c->lc) != hipSuccess)
+                out = dev_fail(c);
+        }
+        if (out == PA_OK && hipStreamSynchronize(c->stream) != hipSuccess) out = dev_fail(c);
+        double total = 0.0;
+        for (int k = 0; k < steps && out == PA_OK; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) != hipSuccess) out = dev_fail(c);
+            total += t;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        if (out != PA_OK) return out;
+        // records of temperatures i0+1 .. i0+steps and the work counters
+        const size_t per_i = sizeof(pa_obs) * (size_t)c->n_runs * c->lo.npop_ctx;
+        rec.resize(per_i * steps + sizeof(uint64_t) * 3);
+        PA_HIP(c, hipMemcpyAsync(rec.data(), at<uint8_t>(c, c->lo.obs) + per_i * (i0 + 1), per_i * steps,
+                                 hipMemcpyDeviceToHost, c->stream));
+        PA_HIP(c, hipMemcpyAsync(rec.data() + per_i * steps, c->lc.stats, sizeof(uint64_t) * 3,
+                                 hipMemcpyDeviceToHost, c->stream));
+        PA_HIP(c, hipStreamSynchronize(c->stream));
+        const uint64_t h = fnv1a(0xcbf29ce484222325ull, rec.data(), rec.size());
+        if (!have_ref) {
+            have_ref = true;
+            ref_hash = h;
+        }
+        *ms = total;
+        *match = h == ref_hash;
+        return PA_OK;
+    }
+};
+
+Shape current_shape(const pa_ctx *c, const std::vector<int> &Ls)
+{
+    Shape s;
+    s.threads = c->sweep_threads;
+    s.dense = c->sweep_dense;
+    s.persistent = c->sweep_persistent ? 1 : 0;
+    for (int L : Ls) s.groups[L] = groups_for(c, L);
+    return s;
+}
+
+}  // namespace
+
+namespace pa {
+
+bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *dense, int *persistent)
+{
+    const std::string arch = device_arch();
+    for (const auto &e : read_cache(path))
+        if (e.arch == arch && e.repr == "msc" && e.L == L) {
+            *threads = e.threads;
+            *groups = e.groups;
+            *dense = e.dense;
+            *persistent = e.persistent;
+            return true;
+        }
+    return false;
+}
+
+}  // namespace pa
+
+extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_path, int32_t *n_tried,
+                                 int32_t *n_rejected)
+{
+    if (!c || steps < 1 || steps > 64) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED) return PA_ERR_STATE;
+    if (n_tried) *n_tried = 0;
+    if (n_rejected) *n_rejected = 0;
+    if (c->repr != PA_MSC64) return PA_OK;   // the plain path has no launch-shape knobs
+    steps = std::min(steps, c->lo.Kmax - 1 - c->i);
+    if (steps < 1) return PA_ERR_STATE;
+
+    // distinct L, heaviest (total lattice words) first
+    std::map<int, double> work;
+    for (const auto &d : c->descs) work[d.L] += (double)d.L * d.L * d.R_cap * n_pop_of(d.overlap);
+    std::vector<int> Ls;
+    for (const auto &kv : work) Ls.push_back(kv.first);
+    std::sort(Ls.begin(), Ls.end(), [&](int a, int b) { return work[a] > work[b]; });
+    const std::string arch = device_arch();
+
+    std::vector<CacheEntry> cache = read_cache(cache_path);
+    {
+        Shape s = current_shape(c, Ls);
+        size_t found = 0;
+        for (size_t k = 0; k < Ls.size(); ++k)
+            for (const auto &e : cache)
+                if (e.arch == arch && e.repr == "msc" && e.L == Ls[k]) {
+                    ++found;
+                    s.groups[e.L] = e.groups;
+                    if (k == 0) {   // context-wide knobs from the heaviest L
+                        s.threads = e.threads;
+                        s.dense = e.dense;
+                        s.persistent = e.persistent;
+                    }
+                    break;
+                }
+        if (found == Ls.size() && apply_shape(c, s)) {
+            drop_graph(c);
+            return upload_sweep_plan(c);
+        }
+    }
+
+    Tuner T;
+    T.c = c;
+    T.steps = steps;
+    T.i0 = c->i;
+    PA_HIP(c, hipHostMalloc((void **)&T.snap, c->lo.total, hipHostMallocDefault));
+    struct Free {
+        uint8_t *p;
+        ~Free() { (void)hipHostFree(p); }
+    } guard{T.snap};
+    PA_HIP(c, hipMemcpyAsync(T.snap, c->ws, c->lo.total, hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+
+    int tried = 0, rejected = 0;
+    Shape best = current_shape(c, Ls);
+    double best_ms = 0.0;
+    pa_status st;
+    {
+        bool match = false;
+        st = T.evaluate(&best_ms, &match);   // the starting shape sets the reference hash
+        if (st != PA_OK) return st;
+        ++tried;
+    }
+    auto consider = [&](const Shape &s) -> pa_status {
+        if (!apply_shape(c, s)) return PA_OK;   // does not fit: not a candidate
+        double ms = 0.0;
+        bool match = false;
+        const pa_status e = T.evaluate(&ms, &match);
+        if (e != PA_OK) return e;
+        ++tried;
+        if (!match) {
+            ++rejected;
+            return PA_OK;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+        return PA_OK;
+    };
+    // context-wide knobs with the current groups per L
+    for (int threads : {256, 512, 1024})
+        for (int dense : {2, 3, 4})
+            for (int pers : {0, 1}) {
+                Shape s = best;
+                s.threads = threads;
+                s.dense = dense;
+                s.persistent = pers;
+                if ((st = consider(s)) != PA_OK) return st;
+            }
+    // groups per workgroup, one L at a time
+    for (int L : Ls) {
+        int cap = 1;
+        for (const auto &d : c->descs)
+            if (d.L == L) cap = std::max(cap, groups_cap_of(d));
+        const int g0 = best.groups[L];
+        std::set<int> cand;
+        for (int g : {g0 / 2, (3 * g0) / 4, g0 - 1, g0 + 1, (3 * g0 + 1) / 2, 2 * g0})
+            if (g >= 1 && g <= cap && g != g0) cand.insert(g);
+        for (int g : cand) {
+            Shape s = best;
+            s.groups[L] = g;
+            if ((st = consider(s)) != PA_OK) return st;
+        }
+    }
+
+    // leave the context where it started, with the chosen shape
+    (void)apply_shape(c, best);
+    if ((st = T.restore()) != PA_OK) return st;
+    drop_graph(c);
+    if ((st = upload_sweep_plan(c)) != PA_OK) return st;
+    if (n_tried) *n_tried = tried;
+    if (n_rejected) *n_rejected = rejected;
+
+    if (cache_path) {
+        for (int L : Ls) {
+            CacheEntry e{arch, "msc", L, best.threads, best.groups[L], best.dense, best.persistent,
+                         1e3 * best_ms / steps};
+            bool replaced = false;
+            for (auto &x : cache)
+                if (x.arch == arch && x.repr == "msc" && x.L == L) {
+                    x = e;
+                    replaced = true;
+                }
+            if (!replaced) cache.push_back(e);
+        }
+        if (!write_cache(cache_path, cache)) return PA_ERR_ARG;
+    }
+    return PA_OK;
+}

@@ -40,8 +40,8 @@ enum Acc { A_SUME = 0, A_SUME2, A_SUMABSM, A_SUMM2, A_NPAIRS, A_SUMQ, A_SUMABSQ,
 struct RunInfo {
     int32_t L, N, npop, R, R_cap, theta, K, model, resampling, overlap, qhist, groups_cap;
     uint32_t key0, key1;
-    int32_t run;            // index of this run in the context
-    int32_t pad0;
+    // record of (population p, temperature i): obs[i * obs_stride + obs_off + p]
+    int32_t obs_stride, obs_off;
     // device pointers into the caller's workspace
     uint8_t *spins[MAX_POP][2];   // int8: [group][site][64] bytes; MSC: [group][site] u64
     int32_t *E[MAX_POP][2];       // energies [R_cap]
@@ -56,7 +56,7 @@ struct RunInfo {
     uint64_t *base64[MAX_POP];    // per chunk: exclusive prefix of tot64
     int32_t *tot32[MAX_POP];      // per chunk: sum of r_j
     int32_t *base32[MAX_POP];     // per chunk: exclusive prefix of tot32
-    pa_obs *obs;                  // records, [K][n_runs][n_pop] (context-wide array)
+    pa_obs *obs;                  // records, indexed through obs_stride and obs_off
     int32_t *qh;                  // [n_pop][K][N+1] or nullptr
     uint8_t *jbits;               // [N]: bit0 = J_R(n) < 0, bit1 = J_D(n) < 0
     const uint64_t *tabX;         // [K][N+1]  floor(exp(-dbeta_i 4k) 2^40)

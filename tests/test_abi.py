@@ -101,3 +101,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pa, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         pa.lib()
+
+
+def test_server_footprint_and_validation():
+    d = W.run_desc(16, W.EA_PMJ, R=5000, K=21, overlap=W.Q_INDEX_SHIFT)
+    fm = pa.pa_server_footprint(d, "msc")
+    f8 = pa.pa_server_footprint(d, "int8")
+    assert 0 < fm < f8
+    # the block grows with R and with a second population
+    assert pa.pa_server_footprint(W.with_(d, R=10000, R_cap=10000), "msc") > fm
+    assert pa.pa_server_footprint(W.with_(d, overlap=W.Q_TWO_POP), "msc") > fm
+    with pytest.raises(pa.PAError):
+        pa.pa_server_footprint(W.with_(d, L=7), "msc")
+    lib = pa.lib()
+    h = C.c_void_p()
+    # rejected before any device call: no arena, misaligned arena, no slots
+    assert lib.pa_server_create(pa.PA_MSC64, None, 1 << 20, 4, None, None, C.byref(h)) == pa.PA_ERR_ARG
+    assert lib.pa_server_create(pa.PA_MSC64, C.c_void_p(4096 + 8), 1 << 20, 4, None, None,
+                                C.byref(h)) == pa.PA_ERR_ARG
+    assert lib.pa_server_create(pa.PA_MSC64, C.c_void_p(4096), 1 << 20, 0, None, None,
+                                C.byref(h)) == pa.PA_ERR_ARG
+    assert lib.pa_server_create(pa.PA_MSC64, C.c_void_p(4096), 1024, 4, None, None,
+                                C.byref(h)) == pa.PA_ERR_NOMEM
+    assert lib.pa_server_step(None, None, None) == pa.PA_ERR_ARG
+    assert lib.pa_server_release(None, 0) == pa.PA_ERR_ARG
+
+
+def test_tuning_calls_validate_before_device():
+    lib = pa.lib()
+    assert lib.pa_autotune(None, 3, None, None, None) == pa.PA_ERR_ARG
+    assert lib.pa_set_persistent(None, 1) == pa.PA_ERR_ARG
+    assert lib.pa_get_tuning(None, 16, None, None, None, None) == pa.PA_ERR_ARG
