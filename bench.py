@@ -14,10 +14,25 @@ updates, sum over steps of theta * R_i * N.
 
 Headline value: the batched path (64 replicas bit-packed per word, lattice
 held in LDS for all theta sweeps, every kernel of a step captured in one HIP
-graph and replayed).  Reported beside it: the plain path (int8 spins, one
-colour of one run per launch, host-driven steps) on the same workload, whose
-records must equal the batched path's bit for bit; the dominant kernel's
-ALU roofline; and the CPU oracle on a bounded sample.
+graph and replayed; launch shapes from the autotuner).  Reported beside it:
+the plain path (int8 spins, one colour of one run per launch, host-driven
+steps) on the same workload, whose records must equal the batched path's bit
+for bit; the dominant kernel's ALU roofline; and the CPU oracle on a bounded
+sample.
+
+Further workloads in the same JSON line (skipped with --quick):
+  two_pop_ea   EA +-J, L = 32, two populations of R = 200000 on one
+               disorder sample, beta 0 -> 3 in 301 points, theta = 10,
+               overlaps q and link overlaps between the populations;
+  batched_4096 4096 independent FM runs, L in {8, 16, 24, 32} (1024 each),
+               R = 2000, beta 0 -> 0.6 in 150 points, theta = 10, all in
+               one context (one sweep launch per step), weighted averages
+               over the 1024 runs of each L in FP64 inside the timed region;
+  serving      500 EA +-J requests arriving at Poisson rate 20/s, L uniform
+               in {16, 24, 32, 48, 64}, R = 50000, beta 0 -> 3 in 201
+               points, theta = 10, served by continuous batching with
+               admission by device-memory footprint: p50/p99 latency and
+               flips/ns.
 """
 import argparse
 import hashlib
@@ -79,8 +94,8 @@ def measured_traffic(kernel, launches_units):
 
 
 def flips_of(obs_rows, desc, i0, i1):
-    N = desc["L"] ** 2
-    return sum(int(obs_rows[i]["R_i"]) * desc["theta"] * N for i in range(i0, i1))
+    """Attempted flips of steps i0 .. i1-1 of one population: theta R_i N each."""
+    return int(obs_rows["R_i"][i0:i1].sum()) * desc["theta"] * desc["L"] ** 2
 
 
 def percentile(xs, q):
@@ -93,117 +108,190 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def run_gpu(desc, steps, warmup, do_plain):
-    import numpy as np
+TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache.json")
+
+
+def tune(ctx, mode):
+    """Applies autotuned launch shapes: from the committed cache if it holds
+    every L of the context, else by a search on the context's own next
+    steps (its state is left unchanged)."""
+    if mode == "off":
+        return None
+    if mode == "search":
+        out = os.path.join(ROOT, "gpurun_out")
+        os.makedirs(out, exist_ok=True)
+        return ctx.autotune(steps=3, cache_path=os.path.join(out, "tuning_cache.json"))
+    return ctx.autotune(steps=3, cache_path=TUNING_CACHE)
+
+
+def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True):
+    """Graph-replayed batched path over `steps` temperature steps (plus the
+    weighted average over groups of M runs when M is given), timed with HIP
+    events and the host clock; then the same steps eagerly with events
+    around every sweep launch (records must be identical)."""
     import torch
 
     import paper_2207_05535_amd as pa
 
-    torch.cuda.set_device(0)
     K1 = 1 + steps
-    res = {}
-
-    # ---------------- batched path: bit-packed words, graph-replayed steps
-    log(f"batched path: create L={desc['L']} R={desc['R']}")
-    ctx = pa.Context([desc], "msc")
+    ctx = pa.Context(descs, "msc")
+    tuned = tune(ctx, tune_mode)
+    L0 = descs[0]["L"]
     ck = ctx.checkpoint()
     ctx.run(1, 1 + warmup)                       # instantiates the step graph
     torch.cuda.synchronize()
     ctx.restore(ck)
     torch.cuda.synchronize()
-    log(f"batched path: timing {steps} steps")
+    log(f"batched path: timing {steps} steps of {len(descs)} run(s)")
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
     ctx.run(1, K1)
-    wavg = ctx.weighted_average(1, pa.PA_W_FULL, 0)   # Sec. IV, FP64 on the device
+    wavg = ctx.weighted_average(M if M else 1, pa.PA_W_FULL, 0)   # Sec. IV, FP64 on the device
     ev1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    wall_s = t1 - t0
-    dev_s = ev0.elapsed_time(ev1) / 1e3
-    obs_graph = ctx.obs()[0, 0].copy()
-    flips = flips_of(obs_graph, desc, 1, K1)
-    res["batched"] = dict(wall_s=wall_s, dev_s=dev_s, flips=flips,
-                          free_energy=float(wavg[0]["minus_beta_WF"][steps]))
-
-    # ---------------- same path, eager, with events around every sweep launch
-    log("batched path: per-kernel timing pass")
-    ctx.restore(ck)
-    torch.cuda.synchronize()
-    st0 = ctx.stats()
-    sweep_ms, step_ms = [], []
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    for k, i in enumerate(range(1, K1)):
-        a, b, c = evs[k]
-        a.record()
-        ctx.anneal_step(i)
-        ctx.resample(i)
-        b.record()
-        ctx.sweep(i)
-        c.record()
-        ctx.measure(i)
-    done = torch.cuda.Event(enable_timing=True)
-    done.record()
-    torch.cuda.synchronize()
-    for k in range(steps):
-        a, b, c = evs[k]
-        nxt = evs[k + 1][0] if k + 1 < steps else done
-        sweep_ms.append(b.elapsed_time(c))
-        step_ms.append(a.elapsed_time(nxt))
-    st1 = ctx.stats()
-    obs_eager = ctx.obs()[0, 0].copy()
-    assert obs_eager.tobytes() == obs_graph.tobytes(), "graph replay differs from eager steps"
-    words = st1["words"] - st0["words"]
-    calls = st1["calls"] - st0["calls"]
-    res["batched"].update(sweep_ms=sweep_ms, step_ms=step_ms, words=words, calls=calls,
-                          sweep_flips=st1["flips"] - st0["flips"])
-    ctx.close()
-    del ck
-
-    # ---------------- plain path: int8 spins, one colour of one run per launch
-    if do_plain:
-        log("plain path: create")
-        pctx = pa.Context([desc], "int8")
-        pck = pctx.checkpoint()
-        for i in range(1, 1 + warmup):
-            pctx.step(i)
+    obs_graph = ctx.obs()
+    flips = sum(flips_of(obs_graph[r, p], descs[r], 1, K1)
+                for r in range(len(descs)) for p in range(obs_graph.shape[1])
+                if p == 0 or descs[r]["overlap"] == pa.PA_Q_TWO_POP)
+    res = dict(wall_s=t1 - t0, dev_s=ev0.elapsed_time(ev1) / 1e3, flips=flips, wavg=wavg,
+               tuning=ctx.tuning(L0), tuned=tuned, obs=obs_graph)
+    if per_kernel:
+        log("batched path: per-kernel timing pass")
+        ctx.restore(ck)
         torch.cuda.synchronize()
-        pctx.restore(pck)
-        del pck
-        torch.cuda.synchronize()
-        log(f"plain path: timing {steps} steps")
-        sw = []
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record()
+        st0 = ctx.stats()
+        sweep_ms, step_ms = [], []
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+                torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         for k, i in enumerate(range(1, K1)):
-            pctx.anneal_step(i)
-            pctx.resample(i)
-            sev[k][0].record()
-            pctx.sweep(i)
-            sev[k][1].record()
-            pctx.measure(i)
-        pw = pctx.weighted_average(1, pa.PA_W_FULL, 0)
-        e1.record()
+            a, b, c = evs[k]
+            a.record()
+            ctx.anneal_step(i)
+            ctx.resample(i)
+            b.record()
+            ctx.sweep(i)
+            c.record()
+            ctx.measure(i)
+        done = torch.cuda.Event(enable_timing=True)
+        done.record()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for a, b in sev:
-            sw.append(a.elapsed_time(b))
-        obs_plain = pctx.obs()[0, 0].copy()
-        ints = [f for f in pa.PA_OBS_DTYPE.names if f not in ("lnQ", "A")]
-        same = all(np.array_equal(obs_plain[f][:K1], obs_graph[f][:K1]) for f in ints)
-        same_fp = bool(np.allclose(obs_plain["A"][:K1], obs_graph["A"][:K1], rtol=1e-12, atol=0))
-        res["plain"] = dict(wall_s=t1 - t0, dev_s=e0.elapsed_time(e1) / 1e3, sweep_ms=sw,
-                            bit_exact=bool(same and same_fp),
-                            free_energy=float(pw[0]["minus_beta_WF"][steps]))
-        pctx.close()
+        for k in range(steps):
+            a, b, c = evs[k]
+            nxt = evs[k + 1][0] if k + 1 < steps else done
+            sweep_ms.append(b.elapsed_time(c))
+            step_ms.append(a.elapsed_time(nxt))
+        st1 = ctx.stats()
+        assert ctx.obs().tobytes() == obs_graph.tobytes(), "graph replay differs from eager steps"
+        res.update(sweep_ms=sweep_ms, step_ms=step_ms, words=st1["words"] - st0["words"],
+                   calls=st1["calls"] - st0["calls"], sweep_flips=st1["flips"] - st0["flips"])
+    ctx.close()
     return res
+
+
+def roofline_of(b, steps):
+    sweep_avg_s = sum(b["sweep_ms"]) / len(b["sweep_ms"]) / 1e3
+    ops_per_launch = (OPS_PER_CALL * b["calls"] + OPS_PER_WORD * b["words"]) / steps
+    achieved = ops_per_launch / sweep_avg_s
+    return sweep_avg_s, achieved
+
+
+def run_plain(desc, steps, warmup, obs_ref):
+    import numpy as np
+    import torch
+
+    import paper_2207_05535_amd as pa
+    K1 = 1 + steps
+    log("plain path: create")
+    pctx = pa.Context([desc], "int8")
+    pck = pctx.checkpoint()
+    for i in range(1, 1 + warmup):
+        pctx.step(i)
+    torch.cuda.synchronize()
+    pctx.restore(pck)
+    del pck
+    torch.cuda.synchronize()
+    log(f"plain path: timing {steps} steps")
+    sw = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for k, i in enumerate(range(1, K1)):
+        pctx.anneal_step(i)
+        pctx.resample(i)
+        sev[k][0].record()
+        pctx.sweep(i)
+        sev[k][1].record()
+        pctx.measure(i)
+    pw = pctx.weighted_average(1, pa.PA_W_FULL, 0)
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for a, b in sev:
+        sw.append(a.elapsed_time(b))
+    obs_plain = pctx.obs()[0, 0].copy()
+    ints = [f for f in pa.PA_OBS_DTYPE.names if f not in ("lnQ", "A")]
+    same = all(np.array_equal(obs_plain[f][:K1], obs_ref[f][:K1]) for f in ints)
+    same_fp = bool(np.allclose(obs_plain["A"][:K1], obs_ref["A"][:K1], rtol=1e-12, atol=0))
+    pctx.close()
+    return dict(wall_s=t1 - t0, dev_s=e0.elapsed_time(e1) / 1e3, sweep_ms=sw,
+                bit_exact=bool(same and same_fp), free_energy=float(pw[0]["minus_beta_WF"][steps]))
+
+
+def workload_summary(b, steps, name):
+    sweep_avg_s, achieved = roofline_of(b, steps)
+    return {
+        "workload": name,
+        "flips_per_ns": round(b["flips"] / b["wall_s"] / 1e9, 3),
+        "flips": b["flips"], "wall_s": round(b["wall_s"], 4), "device_s": round(b["dev_s"], 6),
+        "ms_per_step": round(b["wall_s"] * 1e3 / steps, 4),
+        "latency_ms_per_step": {"p50": round(percentile(b["step_ms"], 0.5), 4),
+                                "p99": round(percentile(b["step_ms"], 0.99), 4)},
+        "sweep_kernel": {"name": "k_sweep_msc", "avg_ms": round(sweep_avg_s * 1e3, 4),
+                         "flips_per_ns": round(b["sweep_flips"] / steps / sweep_avg_s / 1e9, 3),
+                         "alu_frac": round(achieved / PEAK_LANE_OPS, 4),
+                         "philox_calls_per_word": round(b["calls"] / max(1, b["words"]), 4)},
+        "tuning": b["tuning"],
+    }
+
+
+def run_serving(trace, arena_bytes, max_slots):
+    import paper_2207_05535_amd as pa
+    from paper_2207_05535_amd.serve import Server, replay
+    srv = Server(arena_bytes, max_slots=max_slots, tuning_cache=TUNING_CACHE)
+    last = [0.0]
+
+    def progress(done, n, t):
+        if t - last[0] >= 5.0 or done == n:
+            last[0] = t
+            log(f"serving: {done}/{n} requests done at t = {t:.1f} s, {srv.info()['resident']} resident")
+
+    rec, summary = replay(srv, trace, time_scale=1.0, progress=progress)
+    srv.close()
+    ok = all(int(r["obs"]["status"].max()) == pa.PA_OK for r in rec)
+    rate = len(trace) / trace[-1][0]
+    mean_flips = summary["flips"] / len(trace)
+    offered = rate * mean_flips / 1e9
+    cap = summary["busy_flips_per_ns"]
+    return {
+        "workload": "EA +-J requests at Poisson rate 20/s (500 arrivals, trace seed 0xA110000), "
+                    "L uniform in {16,24,32,48,64}, R=50000, beta 0->3 in 201 points, theta=10, "
+                    "index-shift overlaps; continuous batching, admission by device-memory footprint",
+        "requests": len(trace), "max_slots": max_slots, "arena_GiB": round(arena_bytes / 2**30, 2),
+        "p50_latency_s": round(summary["p50_s"], 4), "p99_latency_s": round(summary["p99_s"], 4),
+        "mean_latency_s": round(summary["mean_s"], 4), "max_latency_s": round(summary["max_s"], 4),
+        "flips_per_ns": round(summary["flips_per_ns"], 3),
+        "busy_flips_per_ns": round(cap, 3) if cap else None,
+        "offered_flips_per_ns": round(offered, 3),
+        "utilisation": round(offered / cap, 3) if cap else None,
+        "span_s": round(summary["span_s"], 3), "peak_resident": summary["peak_resident"],
+        "all_status_ok": ok,
+    }
 
 
 def cpu_baseline(desc, max_seconds=20.0):
@@ -234,6 +322,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving",
+                    help="comma-separated subset of headline,plain,two_pop,batched,serving "
+                         "(for profiling runs; the headline value is null when it is left out)")
+    ap.add_argument("--extra-steps", type=int, default=0,
+                    help="temperature steps of the two_pop and batched workloads (0: whole schedule)")
+    ap.add_argument("--tune", choices=("cache", "search", "off"), default="cache",
+                    help="launch shapes: committed autotuner cache (search for missing L), "
+                         "a fresh search, or the built-in defaults")
+    ap.add_argument("--serving-slots", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -248,8 +346,9 @@ def main():
     steps = max(1, min(args.steps, desc["K"] - 1))
     warmup = max(1, min(args.warmup, desc["K"] - 1))
     ensure_built()
+    import torch
+    torch.cuda.set_device(0)
     if args.calibrate_copy:
-        import torch
         src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -257,13 +356,51 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 268435456-byte device-to-device copies")
         del src, dst
-    res = run_gpu(desc, steps, warmup, not args.no_plain)
 
-    b = res["batched"]
+    only = set(args.only.split(","))
+    if args.quick:
+        only &= {"headline", "plain"}
+    line = {}
+    if "headline" in only:
+        line = headline(desc, steps, warmup, args, only)
+    else:
+        line = {"metric": "spin flips/ns on 1 MI355X (batched vs plain), % of roofline, p99 latency",
+                "value": None, "unit": "spin flips/ns", "n_gpus": 1, "steps": steps, "warmup": warmup}
+    xs = lambda K: K - 1 if args.extra_steps <= 0 else min(args.extra_steps, K - 1)   # noqa: E731
+    if "two_pop" in only:
+        d3 = W.ea_L32_two_pop()
+        log("two-population EA: L=32, 2 x 200000 replicas")
+        b3 = time_batched([d3], xs(d3["K"]), warmup, args.tune)
+        line["two_pop_ea"] = workload_summary(
+            b3, xs(d3["K"]), "EA +-J L=32, two populations of R=200000 on one disorder sample, "
+                             "beta 0->3 in 301 points, theta=10, q and link overlap between populations")
+        del b3
+    if "batched" in only:
+        runs = W.batched_fm_uneven()
+        log("batched weighted averaging: 4096 runs, L in {8,16,24,32}")
+        b4 = time_batched(runs, xs(runs[0]["K"]), warmup, args.tune, M=1024)
+        line["batched_4096"] = workload_summary(
+            b4, xs(runs[0]["K"]), "4096 FM runs in one context, L in {8,16,24,32} (1024 each), R=2000, "
+                                  "beta 0->0.6 in 150 points, theta=10, FP64 weighted averages over "
+                                  "the 1024 runs of each L inside the timed region")
+        line["batched_4096"]["free_energy_per_L"] = [
+            float(b4["wavg"][g]["minus_beta_WF"][xs(runs[0]["K"])]) for g in range(4)]
+        del b4
+    if "serving" in only:
+        trace = W.serving_trace()
+        log(f"serving: {len(trace)} requests")
+        line["serving"] = run_serving(trace, 4 << 30, args.serving_slots)
+    if not args.no_cpu_baseline and "headline" in only:
+        log("cpu baseline: oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(desc)
+    print(json.dumps(line), flush=True)
+
+
+def headline(desc, steps, warmup, args, only):
+    log(f"headline: L={desc['L']} R={desc['R']}")
+    b = time_batched([desc], steps, warmup, args.tune)
     value = b["flips"] / b["wall_s"] / 1e9
-    sweep_avg_s = sum(b["sweep_ms"]) / len(b["sweep_ms"]) / 1e3
-    ops_per_launch = (OPS_PER_CALL * b["calls"] + OPS_PER_WORD * b["words"]) / steps
-    achieved = ops_per_launch / sweep_avg_s
+    sweep_avg_s, achieved = roofline_of(b, steps)
     traffic = measured_traffic("k_sweep_msc", steps)
     line = {
         "metric": "spin flips/ns on 1 MI355X (batched vs plain), % of roofline, p99 latency",
@@ -292,12 +429,13 @@ def main():
         "sweep_kernel": {"name": "k_sweep_msc", "avg_ms": round(sweep_avg_s * 1e3, 4),
                          "flips_per_ns": round(b["sweep_flips"] / steps / sweep_avg_s / 1e9, 3),
                          "philox_calls_per_word": round(b["calls"] / max(1, b["words"]), 4)},
+        "tuning": b["tuning"],
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4),
                      "peak": round(PEAK_LANE_OPS / 1e12, 4), "unit": "Tlane-op/s",
                      "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic},
     }
-    if "plain" in res:
-        p = res["plain"]
+    if not args.no_plain and "plain" in only:
+        p = run_plain(desc, steps, warmup, b["obs"][0, 0])
         N = desc["L"] ** 2
         plain_sweep_avg = sum(p["sweep_ms"]) / len(p["sweep_ms"]) / 1e3 / (2 * desc["theta"])
         # algorithmic bytes per int8 colour launch: read every site of the
@@ -312,10 +450,7 @@ def main():
             "bit_exact_vs_batched": p["bit_exact"],
         }
         line["batched_over_plain"] = round(p["wall_s"] / b["wall_s"], 3)
-    if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(desc)
-    print(json.dumps(line), flush=True)
+    return line
 
 
 if __name__ == "__main__":
