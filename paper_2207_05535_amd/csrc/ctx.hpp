@@ -30,7 +30,7 @@ struct Planner {
 // Per-run buffers, as offsets from the start of the region they live in.
 struct RunOff {
     size_t spins[MAX_POP][2], E[MAX_POP][2], fam[MAX_POP][2], r[MAX_POP], C[MAX_POP], parent[MAX_POP],
-        P[MAX_POP], famcnt[MAX_POP], partS[MAX_POP], tot64[MAX_POP], base64[MAX_POP], tot32[MAX_POP],
+        P[MAX_POP], part[MAX_POP], partS[MAX_POP], tot64[MAX_POP], base64[MAX_POP], tot32[MAX_POP],
         base32[MAX_POP], qh, jbits;
     int table;
 };
@@ -46,8 +46,8 @@ struct TableOff {
 struct Layout {
     std::vector<RunOff> runs;
     std::vector<TableOff> tables;
-    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items, queue;
-    int n_items, n_chunk_items, npop_ctx, Kmax, maxN;
+    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items, queue, meas_items;
+    int n_items, n_chunk_items, n_meas_items, npop_ctx, Kmax, maxN;
     size_t total;
 };
 
@@ -64,6 +64,13 @@ void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::
 RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8_t *tbase, const TableOff &T,
                      pa_obs *obs, int obs_stride, int obs_off);
 PopState initial_popstate(const pa_run_desc &d);
+// Measure items of one (run, pop): 4 / waves-per-group consecutive groups each.
+void meas_items_of(const pa_run_desc &d, int run, int pop, std::vector<SweepItem> &out);
+inline int n_meas_items_of(const pa_run_desc &d)
+{
+    const int gpw = MEAS_WAVES / meas_waves_per_group(d.L * d.L);
+    return (groups_cap_of(d) + gpw - 1) / gpw;
+}
 int default_groups(int L);
 // Batched-sweep shape for lattice size L from an autotuner cache file.
 bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *dense, int *persistent);

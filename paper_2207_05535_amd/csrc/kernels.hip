@@ -935,35 +935,36 @@ __device__ __forceinline__ uint64_t load_word(const uint8_t *buf, int g, int n, 
     return pack64(v);
 }
 
-// Measurement of one replica group (64 replicas) per workgroup.  The group's
-// lattice (and its overlap partners' lattice) is staged in LDS in bands of
-// rows; each thread takes sites and accumulates, in bit-sliced counters,
-// the per-replica numbers of unsatisfied bonds (E = 2 #unsat - 2N), down
-// spins (M = N - 2 #down), and for overlap pairs the Hamming distance
-// (Q = N - 2 d) and the number of bonds whose product differs
-// (Q_l = 2N - 2 d_l).  The counters are turned into per-replica integers by
-// transposes, summed over the wavefronts, and reduced into the population's
-// integer sums, minimum energy, overlap histogram and family histogram.
-constexpr int MEAS_BAND_WORDS = 4096;
-
-constexpr int MEAS_THREADS = 256;   // a band gives each thread at most 16 sites
-
+// Measurement of replica groups (64 replicas each).  A workgroup of
+// MEAS_WAVES wavefronts takes a measure item of consecutive groups of one
+// (run, pop); each group gets meas_waves_per_group(N) wavefronts, which
+// split its sites 64 at a time.  A lane accumulates, in bit-sliced
+// counters over its sites, the per-replica numbers of unsatisfied bonds
+// (E = 2 #unsat - 2N), down spins (M = N - 2 #down), and for overlap pairs
+// the Hamming distance (Q = N - 2 d) and the number of bonds whose product
+// differs (Q_l = 2N - 2 d_l); neighbour words are read straight from
+// memory (the lattice block of a group is contiguous, so they hit the
+// caches).  The counters are turned into per-replica integers by
+// transposes, the wavefronts of a group are summed in LDS, the energies are
+// stored, and the group's integer sums go to its slot of the partial-sum
+// array; k_meas_chunk reduces those per chunk.
 template <int REPR, int LT>
-__device__ __forceinline__ void measure_group(const Item &it, const RunInfo &R, PopState &S, const PopState *st,
-                                              uint64_t *lat, uint64_t *plat, uint32_t (*red)[4][64])
+__device__ __forceinline__ void measure_group(const SweepItem &it, int g, int sub, int wpg, bool live,
+                                              const RunInfo &R, const PopState &S, const PopState *st,
+                                              uint32_t (*red)[MEAS_WAVES][64])
 {
     const int L = LT ? LT : R.L;
     const int N = L * L;
     const int Rc = S.Rcur;
-    const int g = it.group;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint8_t *buf = R.spins[it.pop][S.cur];
     // overlap partners of this group's replicas
     int mode = 0;                      // 0 none, 1 index shift, 2 two populations
     uint64_t pairmask = 0;
     const uint8_t *pbuf = buf;
-    int pg = 0, sh = 0, pgroups = R.groups_cap;
-    if (R.overlap == PA_Q_INDEX_SHIFT) {
+    int pg = 0, sh = 0;
+    const int pgroups = R.groups_cap;
+    if (live && R.overlap == PA_Q_INDEX_SHIFT) {
         const int h = Rc >> 1;
         const int lo = g * 64;
         if (lo < h) {
@@ -973,7 +974,7 @@ __device__ __forceinline__ void measure_group(const Item &it, const RunInfo &R, 
             pg = (lo + h) >> 6;
             sh = (lo + h) & 63;
         }
-    } else if (R.overlap == PA_Q_TWO_POP && it.pop == 0) {
+    } else if (live && R.overlap == PA_Q_TWO_POP && it.pop == 0) {
         const PopState &S1 = st[it.run * MAX_POP + 1];
         if (pop_active(S1)) {
             const int m = min(Rc, S1.Rcur);
@@ -987,183 +988,261 @@ __device__ __forceinline__ void measure_group(const Item &it, const RunInfo &R, 
             }
         }
     }
-    const int B = N <= MEAS_BAND_WORDS ? L : MEAS_BAND_WORDS / L - 1;   // rows per band
-    const bool whole = B == L;
     uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
     uint32_t totU = 0, totD = 0, totH = 0, totK = 0;
-    for (int y0 = 0; y0 < L; y0 += B) {
-        const int rows = min(B, L - y0);
-        const int srows = whole ? rows : rows + 1;
-        __syncthreads();
-        for (int idx = tid; idx < srows * L; idx += blockDim.x) {
-            const int r = idx / L, x = idx - r * L;
-            const int n = ((y0 + r) % L) * L + x;
-            lat[idx] = load_word<REPR>(buf, g, n, N);
-            if (mode == 1) {
-                const uint64_t a = load_word<REPR>(buf, pg, n, N);
-                const uint64_t b = (sh && pg + 1 < pgroups) ? load_word<REPR>(buf, pg + 1, n, N) : 0ull;
-                plat[idx] = sh ? ((a >> sh) | (b << (64 - sh))) : a;
-            } else if (mode == 2) {
-                plat[idx] = load_word<REPR>(pbuf, pg, n, N);
-            }
-        }
-        __syncthreads();
-        for (int idx = tid; idx < rows * L; idx += blockDim.x) {
-            const int r = idx / L, x = idx - r * L;
-            const int n = (y0 + r) * L + x;
-            const int ir = r * L + (x + 1 == L ? 0 : x + 1);
-            const int id = (whole && r + 1 == L) ? x : (r + 1) * L + x;
+    int since = 0;
+    // every lane of the wavefront runs the same iterations (flushes are
+    // wave-wide); lanes past the last site only skip the work
+    for (int base = 64 * sub; base < N; base += 64 * wpg) {
+        const int n = base + lane;
+        if (live && n < N) {
+            const int y = n / L, x = n - y * L;
+            const int nr = y * L + (x + 1 == L ? 0 : x + 1);
+            const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
             const uint8_t jn = R.jbits[n];
-            const uint64_t w = lat[idx], wr = lat[ir], wd = lat[id];
+            const uint64_t w = load_word<REPR>(buf, g, n, N);
+            const uint64_t wr = load_word<REPR>(buf, g, nr, N);
+            const uint64_t wd = load_word<REPR>(buf, g, nd, N);
             const uint64_t br = w ^ wr, bd = w ^ wd;
             vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
             vinc(cD, w);
             if (mode) {
-                const uint64_t q = plat[idx], qr = plat[ir], qd = plat[id];
+                uint64_t q, qr, qd;
+                if (mode == 1 && sh) {
+                    const bool two = pg + 1 < pgroups;
+                    q = (load_word<REPR>(buf, pg, n, N) >> sh) |
+                        (two ? load_word<REPR>(buf, pg + 1, n, N) << (64 - sh) : 0ull);
+                    qr = (load_word<REPR>(buf, pg, nr, N) >> sh) |
+                         (two ? load_word<REPR>(buf, pg + 1, nr, N) << (64 - sh) : 0ull);
+                    qd = (load_word<REPR>(buf, pg, nd, N) >> sh) |
+                         (two ? load_word<REPR>(buf, pg + 1, nd, N) << (64 - sh) : 0ull);
+                } else {
+                    q = load_word<REPR>(pbuf, pg, n, N);
+                    qr = load_word<REPR>(pbuf, pg, nr, N);
+                    qd = load_word<REPR>(pbuf, pg, nd, N);
+                }
                 vinc(cH, w ^ q);
                 vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
             }
         }
-        // wave-uniform point: every lane of the wavefront reaches it
-        totU += vflush(cU);
-        totD += vflush(cD);
-        if (mode) {
+        if (++since == 16) {   // at most 2 per site: 32 < 2^VB
+            since = 0;
+            totU += vflush(cU);
+            totD += vflush(cD);
             totH += vflush(cH);
             totK += vflush(cK);
         }
     }
-    red[0][wv][lane] = totU;
-    red[1][wv][lane] = totD;
-    red[2][wv][lane] = totH;
-    red[3][wv][lane] = totK;
+    totU += vflush(cU);
+    totD += vflush(cD);
+    totH += vflush(cH);
+    totK += vflush(cK);
+    if (wpg > 1) {
+        red[0][wv][lane] = totU;
+        red[1][wv][lane] = totD;
+        red[2][wv][lane] = totH;
+        red[3][wv][lane] = totK;
+    }
     __syncthreads();
-    if (wv != 0) return;
-    const int nwv = blockDim.x >> 6;
-    uint32_t U = 0, D = 0, H = 0, Kc = 0;
-    for (int k = 0; k < nwv; ++k) {
-        U += red[0][k][lane];
-        D += red[1][k][lane];
-        H += red[2][k][lane];
-        Kc += red[3][k][lane];
+    if (!live || sub != 0) return;
+    uint32_t U = totU, D = totD, H = totH, Kc = totK;
+    for (int k = 1; k < wpg; ++k) {
+        U += red[0][wv + k][lane];
+        D += red[1][wv + k][lane];
+        H += red[2][wv + k][lane];
+        Kc += red[3][wv + k][lane];
     }
     const int j = g * 64 + lane;
     const bool valid = j < Rc;
     const int64_t E = 2 * (int64_t)U - 2 * (int64_t)N;
     const int64_t M = (int64_t)N - 2 * (int64_t)D;
-    if (valid) {
-        R.E[it.pop][S.cur][j] = (int32_t)E;
-        atomicAdd(&R.famcnt[it.pop][R.fam[it.pop][S.cur][j]], 1);
-    }
+    if (valid) R.E[it.pop][S.cur][j] = (int32_t)E;
     const int64_t v = valid ? 1 : 0;
-    const int64_t sE = wave_sum<int64_t>(v * E);
-    const int64_t sE2 = wave_sum<int64_t>(v * E * E);
-    const int64_t sM = wave_sum<int64_t>(v * (M < 0 ? -M : M));
-    const int64_t sM2 = wave_sum<int64_t>(v * M * M);
-    const int emin = wave_min(valid ? (int)E : INT32_MAX);
     const bool pair = mode && ((pairmask >> lane) & 1u);
     const int64_t pv = pair ? 1 : 0;
     const int64_t Q = (int64_t)N - 2 * (int64_t)H, Ql = 2 * (int64_t)N - 2 * (int64_t)Kc;
-    const int64_t np = wave_sum<int64_t>(pv);
-    const int64_t sQ = wave_sum<int64_t>(pv * Q);
-    const int64_t sAQ = wave_sum<int64_t>(pv * (Q < 0 ? -Q : Q));
-    const int64_t sQ2 = wave_sum<int64_t>(pv * Q * Q);
-    const int64_t sQl = wave_sum<int64_t>(pv * Ql);
-    const int64_t sQl2 = wave_sum<int64_t>(pv * Ql * Ql);
+    int64_t part[MEAS_PART];
+    part[0] = wave_sum<int64_t>(v * E);
+    part[1] = wave_sum<int64_t>(v * E * E);
+    part[2] = wave_sum<int64_t>(v * (M < 0 ? -M : M));
+    part[3] = wave_sum<int64_t>(v * M * M);
+    part[4] = wave_sum<int64_t>(pv);
+    part[5] = wave_sum<int64_t>(pv * Q);
+    part[6] = wave_sum<int64_t>(pv * (Q < 0 ? -Q : Q));
+    part[7] = wave_sum<int64_t>(pv * Q * Q);
+    part[8] = wave_sum<int64_t>(pv * Ql);
+    part[9] = wave_sum<int64_t>(pv * Ql * Ql);
+    part[10] = wave_min(valid ? (int)E : INT32_MAX);
     if (pair && R.qhist) {
         const size_t Np1 = (size_t)N + 1;
         atomicAdd(&R.qh[((size_t)it.pop * R.K + S.i) * Np1 + H], 1);
         if (R.overlap == PA_Q_TWO_POP) atomicAdd(&R.qh[((size_t)1 * R.K + S.i) * Np1 + H], 1);
     }
-    if (lane == 0) {
-        unsigned long long *acc = (unsigned long long *)S.acc;
-        atomicAdd(&acc[A_SUME], (unsigned long long)sE);
-        atomicAdd(&acc[A_SUME2], (unsigned long long)sE2);
-        atomicAdd(&acc[A_SUMABSM], (unsigned long long)sM);
-        atomicAdd(&acc[A_SUMM2], (unsigned long long)sM2);
-        if (np) {
-            atomicAdd(&acc[A_NPAIRS], (unsigned long long)np);
-            atomicAdd(&acc[A_SUMQ], (unsigned long long)sQ);
-            atomicAdd(&acc[A_SUMABSQ], (unsigned long long)sAQ);
-            atomicAdd(&acc[A_SUMQ2], (unsigned long long)sQ2);
-            atomicAdd(&acc[A_SUMQL], (unsigned long long)sQl);
-            atomicAdd(&acc[A_SUMQL2], (unsigned long long)sQl2);
-        }
-        atomicMin(&S.EminAcc, emin);
+    if (lane < MEAS_PART) {
+        int64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < MEAS_PART; ++k)
+            if (lane == k) mine = part[k];
+        R.part[it.pop][(size_t)g * MEAS_PART + lane] = mine;
     }
 }
 
 template <int REPR>
-__global__ void __launch_bounds__(MEAS_THREADS) k_measure(const Item *items, const RunInfo *runs, PopState *st)
+__global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items, const RunInfo *runs,
+                                                          const PopState *st)
 {
-    __shared__ uint64_t lat[MEAS_BAND_WORDS];
-    __shared__ uint64_t plat[MEAS_BAND_WORDS];
-    __shared__ uint32_t red[4][MEAS_THREADS / 64][64];
-    const Item it = items[blockIdx.x];
+    __shared__ uint32_t red[4][MEAS_WAVES][64];
+    const SweepItem it = items[blockIdx.x];
     const RunInfo &R = runs[it.run];
-    PopState &S = st[it.run * MAX_POP + it.pop];
+    const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
-    if (it.group * 64 >= S.Rcur) return;
+    const int wpg = meas_waves_per_group(R.N);
+    const int wv = threadIdx.x >> 6;
+    const int k = wv / wpg, sub = wv - k * wpg;
+    const int g = it.group0 + k;
+    const bool live = k < it.ngroups && g * 64 < S.Rcur;
     switch (R.L) {
-    case 8: measure_group<REPR, 8>(it, R, S, st, lat, plat, red); break;
-    case 16: measure_group<REPR, 16>(it, R, S, st, lat, plat, red); break;
-    case 24: measure_group<REPR, 24>(it, R, S, st, lat, plat, red); break;
-    case 32: measure_group<REPR, 32>(it, R, S, st, lat, plat, red); break;
-    case 48: measure_group<REPR, 48>(it, R, S, st, lat, plat, red); break;
-    case 64: measure_group<REPR, 64>(it, R, S, st, lat, plat, red); break;
-    default: measure_group<REPR, 0>(it, R, S, st, lat, plat, red); break;
+    case 8: measure_group<REPR, 8>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 16: measure_group<REPR, 16>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 24: measure_group<REPR, 24>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 32: measure_group<REPR, 32>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 48: measure_group<REPR, 48>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 64: measure_group<REPR, 64>(it, g, sub, wpg, live, R, S, st, red); break;
+    default: measure_group<REPR, 0>(it, g, sub, wpg, live, R, S, st, red); break;
     }
 }
 
-// Family sizes: per chunk of family labels, sum of c_f^2, max c_f and the
-// number of non-empty families, accumulated per population; the histogram
-// is cleared for the next temperature.
-__global__ void __launch_bounds__(CH_THREADS) k_fam_chunk(const ChunkItem *items, const RunInfo *runs,
+// Per chunk of CH replicas (CH / 64 groups): the groups' partial sums, and
+// the family statistics.  Family labels are non-decreasing in the replica
+// index (they start as f_j = j and every resampling copies parents in
+// order), so each family is one run of equal labels.  A replica at rank r
+// inside its family contributes 2r + 1 to sum_f c_f^2 (the ranks of a
+// family of size c give c^2), r + 1 to max_f c_f, and 1 to the number of
+// families if r = 0.  The rank needs the family's first index: the last
+// start at or before the replica inside the chunk, else (a family that
+// began in an earlier chunk) found by binary search for the first label
+// equal to the chunk's first.
+__global__ void __launch_bounds__(CH_THREADS) k_meas_chunk(const ChunkItem *items, const RunInfo *runs,
                                                            PopState *st)
 {
     __shared__ int64_t red[3][CH_THREADS / 64];
+    __shared__ int lds_scan[CH_THREADS / 64 + 1];
+    __shared__ int first_start;
     const ChunkItem it = items[blockIdx.x];
     const RunInfo &R = runs[it.run];
     PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
-    const int f0 = it.chunk * CH;
-    if (f0 >= R.R) return;
-    int32_t *fc = R.famcnt[it.pop];
-    int64_t sq = 0, mx = 0, nz = 0;
+    const int Rc = S.Rcur;
+    const int j0 = it.chunk * CH;
+    if (j0 >= Rc) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // group partials: groups [j0/64, j0/64 + CH/64), one per lane of wave 0
+    int64_t part[MEAS_PART];
+#pragma unroll
+    for (int k = 0; k < MEAS_PART; ++k) part[k] = 0;
+    part[10] = INT32_MAX;
+    const int g = j0 / 64 + lane;
+    if (wv == 0 && lane < CH / 64 && g * 64 < Rc) {
+#pragma unroll
+        for (int k = 0; k < MEAS_PART; ++k) part[k] = R.part[it.pop][(size_t)g * MEAS_PART + k];
+    }
+    // families
+    const int32_t *fam = R.fam[it.pop][S.cur];
+    if (threadIdx.x == 0) {
+        int fs = j0;
+        if (j0 > 0 && fam[j0 - 1] == fam[j0]) {
+            const int32_t f = fam[j0];
+            int lo = 0, hi = j0;   // first index with label f
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (fam[mid] < f) lo = mid + 1;
+                else hi = mid;
+            }
+            fs = lo;
+        }
+        first_start = fs;
+    }
+    const int jb = j0 + threadIdx.x * CH_PER;
+    int32_t lab[CH_PER];
+    int last = -1;
+#pragma unroll
     for (int q = 0; q < CH_PER; ++q) {
-        const int f = f0 + threadIdx.x + q * CH_THREADS;
-        if (f < R.R) {
-            const int64_t cnt = fc[f];
-            sq += cnt * cnt;
-            mx = cnt > mx ? cnt : mx;
-            nz += cnt > 0;
-            fc[f] = 0;
+        const int j = jb + q;
+        lab[q] = j < Rc ? fam[j] : 0;
+        if (j < Rc && j > j0 && fam[j - 1] != lab[q]) last = j;
+        if (j == j0 && j < Rc && j0 == 0) last = 0;
+    }
+    // exclusive max-scan of the threads' last starts
+    int incl = last;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl = max(incl, t);
+    }
+    if (lane == 63) lds_scan[wv] = incl;
+    __syncthreads();
+    int before = first_start;   // start of the family of replica j0
+    for (int k = 0; k < wv; ++k) before = max(before, lds_scan[k]);
+    {
+        const int t = __shfl_up(incl, 1, 64);
+        if (lane >= 1) before = max(before, t);
+    }
+    int64_t sq = 0, mx = 0, nf = 0;
+    int s = before;
+#pragma unroll
+    for (int q = 0; q < CH_PER; ++q) {
+        const int j = jb + q;
+        if (j < Rc) {
+            const bool start = j == 0 || fam[j - 1] != lab[q];
+            if (start) s = j;
+            const int64_t r = j - s;
+            sq += 2 * r + 1;
+            mx = r + 1 > mx ? r + 1 : mx;
+            nf += start ? 1 : 0;
         }
     }
     sq = wave_sum<int64_t>(sq);
-    nz = wave_sum<int64_t>(nz);
+    nf = wave_sum<int64_t>(nf);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const int64_t t = __shfl_xor(mx, o, 64);
         mx = t > mx ? t : mx;
     }
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) part[k] = wave_sum<int64_t>(part[k]);
+        part[10] = wave_min((int)part[10]);
+    }
+    if (lane == 0) {
         red[0][wv] = sq;
         red[1][wv] = mx;
-        red[2][wv] = nz;
+        red[2][wv] = nf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t a = 0, b = 0, cnz = 0;
+        int64_t a = 0, b = 0, c = 0;
         for (int k = 0; k < CH_THREADS / 64; ++k) {
             a += red[0][k];
             b = red[1][k] > b ? red[1][k] : b;
-            cnz += red[2][k];
+            c += red[2][k];
         }
         unsigned long long *acc = (unsigned long long *)S.acc;
         atomicAdd(&acc[A_FAMSQ], (unsigned long long)a);
         atomicMax(&acc[A_FAMMAX], (unsigned long long)b);
-        atomicAdd(&acc[A_NFAM], (unsigned long long)cnz);
+        atomicAdd(&acc[A_NFAM], (unsigned long long)c);
+        atomicAdd(&acc[A_SUME], (unsigned long long)part[0]);
+        atomicAdd(&acc[A_SUME2], (unsigned long long)part[1]);
+        atomicAdd(&acc[A_SUMABSM], (unsigned long long)part[2]);
+        atomicAdd(&acc[A_SUMM2], (unsigned long long)part[3]);
+        if (part[4]) {
+            atomicAdd(&acc[A_NPAIRS], (unsigned long long)part[4]);
+            atomicAdd(&acc[A_SUMQ], (unsigned long long)part[5]);
+            atomicAdd(&acc[A_SUMABSQ], (unsigned long long)part[6]);
+            atomicAdd(&acc[A_SUMQ2], (unsigned long long)part[7]);
+            atomicAdd(&acc[A_SUMQL], (unsigned long long)part[8]);
+            atomicAdd(&acc[A_SUMQL2], (unsigned long long)part[9]);
+        }
+        atomicMin(&S.EminAcc, (int)part[10]);
     }
 }
 
@@ -1487,10 +1566,14 @@ int sweep_msc_resident(int threads, size_t lds)
 
 hipError_t launch_measure(const LaunchCtx &c)
 {
-    if (c.repr == PA_MSC64) k_measure<PA_MSC64><<<c.n_items, MEAS_THREADS, 0, c.stream>>>(c.items, c.runs, c.st);
-    else k_measure<PA_INT8><<<c.n_items, MEAS_THREADS, 0, c.stream>>>(c.items, c.runs, c.st);
-    PA_CHECK_LAUNCH();
-    k_fam_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
+    if (c.n_meas_items > 0) {
+        if (c.repr == PA_MSC64)
+            k_measure<PA_MSC64><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+        else
+            k_measure<PA_INT8><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+        PA_CHECK_LAUNCH();
+    }
+    k_meas_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
     k_finalize<<<(c.n_runs + 63) / 64, 64, 0, c.stream>>>(c.runs + c.run0, c.st + (size_t)c.run0 * MAX_POP,
                                                           c.n_runs);

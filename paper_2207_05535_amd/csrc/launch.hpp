@@ -18,6 +18,8 @@ struct LaunchCtx {
     int repr;
     bool any_multinomial;
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
+    const SweepItem *meas_items;   // device [n_meas_items]: groups per measure workgroup
+    int n_meas_items;
     const SweepItem *sweep_items;  // device [n_sweep_items]
     int n_sweep_items, sweep_threads, sweep_dense;
     int sweep_grid;                // > 0: persistent grid of this many workgroups

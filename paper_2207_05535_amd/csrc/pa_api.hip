@@ -76,7 +76,7 @@ void plan_run_buffers(Planner &P, const pa_run_desc &d, pa_repr repr, RunOff &o)
         o.C[p] = P.take(sizeof(int32_t) * (d.R_cap + 1));
         o.parent[p] = P.take(sizeof(int32_t) * d.R_cap);
         o.P[p] = d.resampling == PA_MULTINOMIAL ? P.take(sizeof(uint64_t) * (d.R_cap + 1)) : 0;
-        o.famcnt[p] = P.take(sizeof(int32_t) * d.R);
+        o.part[p] = P.take(sizeof(int64_t) * MEAS_PART * groups_cap_of(d));
         o.partS[p] = P.take(sizeof(double) * nch);
         o.tot64[p] = P.take(sizeof(uint64_t) * nch);
         o.base64[p] = P.take(sizeof(uint64_t) * nch);
@@ -117,12 +117,15 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     Lo.queue = P.take(sizeof(uint32_t) * 2);
     Lo.n_items = 0;
     Lo.n_chunk_items = 0;
+    Lo.n_meas_items = 0;
     for (int r = 0; r < n_runs; ++r) {
         const int npop = n_pop_of(runs[r].overlap);
         Lo.n_items += npop * groups_cap_of(runs[r]);
         Lo.n_chunk_items += npop * chunks_cap_of(runs[r]);
+        Lo.n_meas_items += npop * n_meas_items_of(runs[r]);
     }
     Lo.items = P.take(sizeof(Item) * Lo.n_items);
+    Lo.meas_items = P.take(sizeof(SweepItem) * Lo.n_meas_items);
     Lo.sweep_items = P.take(sizeof(SweepItem) * Lo.n_items);
     Lo.chunk_items = P.take(sizeof(ChunkItem) * Lo.n_chunk_items);
     Lo.obs = P.take(sizeof(pa_obs) * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx);
@@ -202,7 +205,7 @@ RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8
         I.C[p] = (int32_t *)(base + o.C[p]);
         I.parent[p] = (int32_t *)(base + o.parent[p]);
         I.P[p] = d.resampling == PA_MULTINOMIAL ? (uint64_t *)(base + o.P[p]) : nullptr;
-        I.famcnt[p] = (int32_t *)(base + o.famcnt[p]);
+        I.part[p] = (int64_t *)(base + o.part[p]);
         I.partS[p] = (double *)(base + o.partS[p]);
         I.tot64[p] = (uint64_t *)(base + o.tot64[p]);
         I.base64[p] = (uint64_t *)(base + o.base64[p]);
@@ -233,6 +236,12 @@ PopState initial_popstate(const pa_run_desc &d)
     S.A = (double)d.L * d.L * std::log(2.0);   // ln Z(0) = N ln 2
     S.EminAcc = INT32_MAX;
     return S;
+}
+
+void meas_items_of(const pa_run_desc &d, int run, int pop, std::vector<SweepItem> &out)
+{
+    const int gpw = MEAS_WAVES / meas_waves_per_group(d.L * d.L);
+    for (int g = 0; g < groups_cap_of(d); g += gpw) out.push_back({run, pop, g, std::min(gpw, groups_cap_of(d) - g)});
 }
 
 int default_groups(int L)
@@ -406,6 +415,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     std::vector<PopState> hst((size_t)n_runs * MAX_POP);
     std::vector<Item> items;
     std::vector<ChunkItem> chunks;
+    std::vector<SweepItem> meas;
     std::vector<uint64_t> dseed(n_runs);
     for (int r = 0; r < n_runs; ++r) {
         const pa_run_desc &d = c->descs[r];
@@ -417,6 +427,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
             hst[(size_t)r * MAX_POP + p] = initial_popstate(d);
             for (int g = 0; g < groups_cap_of(d); ++g) items.push_back({r, p, g, 0});
             for (int k = 0; k < chunks_cap_of(d); ++k) chunks.push_back({r, p, k, 0});
+            meas_items_of(d, r, p, meas);
         }
         dseed[r] = d.disorder_seed;
     }
@@ -427,6 +438,8 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.n_items = Lo.n_items;
     c->lc.chunk_items = at<ChunkItem>(c, Lo.chunk_items);
     c->lc.n_chunk_items = Lo.n_chunk_items;
+    c->lc.meas_items = at<SweepItem>(c, Lo.meas_items);
+    c->lc.n_meas_items = Lo.n_meas_items;
     c->lc.run0 = 0;
     c->lc.n_runs = n_runs;
     c->lc.npop_ctx = Lo.npop_ctx;
@@ -463,6 +476,8 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
                               hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(at<ChunkItem>(c, Lo.chunk_items), chunks.data(), sizeof(ChunkItem) * chunks.size(),
                               hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(at<SweepItem>(c, Lo.meas_items), meas.data(), sizeof(SweepItem) * meas.size(),
+                              hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(at<uint64_t>(c, Lo.dseed), dseed.data(), sizeof(uint64_t) * n_runs,
                               hipMemcpyHostToDevice, s) == hipSuccess;
     std::vector<std::vector<uint64_t>> hX(Lo.tables.size()), hT(Lo.tables.size());
@@ -487,8 +502,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         const pa_run_desc &d = c->descs[r];
         const RunOff &o = Lo.runs[r];
         for (int p = 0; p < n_pop_of(d.overlap) && ok; ++p) {
-            ok = launch_fill_u32(at<void>(c, o.famcnt[p]), 0, d.R, s) == hipSuccess;
-            ok = ok && launch_fill_u32(at<void>(c, o.r[p]), 0, d.R_cap, s) == hipSuccess;
+            ok = launch_fill_u32(at<void>(c, o.r[p]), 0, d.R_cap, s) == hipSuccess;
         }
         if (d.qhist && ok)
             ok = launch_fill_u32(at<void>(c, o.qh), 0, (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1), s) ==

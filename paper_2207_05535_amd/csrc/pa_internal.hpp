@@ -34,6 +34,16 @@ constexpr int CH_PER = 8;
 constexpr int CH = CH_THREADS * CH_PER;
 constexpr int NACC = 13;  // measure accumulators, see Acc
 
+// Measurement: workgroups of MEAS_WAVES wavefronts; a lattice of N sites
+// gets one wavefront per group up to 1024 sites, two up to 2048, else four.
+constexpr int MEAS_WAVES = 4;
+constexpr int MEAS_THREADS = 64 * MEAS_WAVES;
+// per-group partial sums: E, E^2, |M|, M^2, pairs, Q, |Q|, Q^2, Q_l, Q_l^2,
+// minimum energy
+constexpr int MEAS_PART = 11;
+
+__host__ __device__ inline int meas_waves_per_group(int N) { return N <= 1024 ? 1 : (N <= 2048 ? 2 : 4); }
+
 enum Acc { A_SUME = 0, A_SUME2, A_SUMABSM, A_SUMM2, A_NPAIRS, A_SUMQ, A_SUMABSQ, A_SUMQ2,
            A_SUMQL, A_SUMQL2, A_FAMSQ, A_FAMMAX, A_NFAM };
 
@@ -50,7 +60,7 @@ struct RunInfo {
     int32_t *C[MAX_POP];          // exclusive prefix of r [R_cap + 1]
     int32_t *parent[MAX_POP];     // child -> parent [R_cap]
     uint64_t *P[MAX_POP];         // multinomial prefix of X [R_cap + 1]
-    int32_t *famcnt[MAX_POP];     // family histogram [R]
+    int64_t *part[MAX_POP];       // per group: MEAS_PART partial sums of the measurement
     double *partS[MAX_POP];       // per chunk: partial sum of x_j
     uint64_t *tot64[MAX_POP];     // per chunk: sum of X_j
     uint64_t *base64[MAX_POP];    // per chunk: exclusive prefix of tot64

@@ -96,7 +96,7 @@ private:
 // the disorder seed.
 struct BlockPlan {
     RunOff o;
-    size_t obs, items, chunks, dseed, bytes;
+    size_t obs, items, chunks, meas, dseed, bytes;
 };
 
 BlockPlan plan_block(const pa_run_desc &d, pa_repr repr)
@@ -108,6 +108,7 @@ BlockPlan plan_block(const pa_run_desc &d, pa_repr repr)
     b.obs = P.take(sizeof(pa_obs) * (size_t)d.K * npop);
     b.items = P.take(sizeof(Item) * (size_t)npop * groups_cap_of(d));
     b.chunks = P.take(sizeof(ChunkItem) * (size_t)npop * chunks_cap_of(d));
+    b.meas = P.take(sizeof(SweepItem) * (size_t)npop * n_meas_items_of(d));
     b.dseed = P.take(sizeof(uint64_t));
     b.bytes = P.off;
     return b;
@@ -157,6 +158,7 @@ struct pa_server {
     std::vector<Table> tables;
     // batch work lists in the arena (grown on demand)
     size_t items_off = 0, items_cap = 0, chunks_off = 0, chunks_cap = 0, sweep_off = 0, sweep_cap = 0;
+    size_t meas_off = 0, meas_cap = 0;
     bool dirty = true;
     LaunchCtx lc;
     std::deque<Upload> pending;
@@ -234,7 +236,7 @@ bool grow(pa_server *s, size_t &off, size_t &cap, size_t need)
 // block first) are built on the host.
 pa_status rebuild(pa_server *s)
 {
-    size_t n_items = 0, n_chunks = 0;
+    size_t n_items = 0, n_chunks = 0, n_meas = 0;
     int hi = 0, npop_ctx = 1;
     bool mn = false;
     std::vector<SweepItem> sweep;
@@ -245,6 +247,7 @@ pa_status rebuild(pa_server *s)
         const int npop = n_pop_of(sl.d.overlap);
         n_items += (size_t)npop * groups_cap_of(sl.d);
         n_chunks += (size_t)npop * chunks_cap_of(sl.d);
+        n_meas += (size_t)npop * n_meas_items_of(sl.d);
         hi = k + 1;
         npop_ctx = std::max(npop_ctx, npop);
         mn = mn || sl.d.resampling == PA_MULTINOMIAL;
@@ -266,21 +269,26 @@ pa_status rebuild(pa_server *s)
     });
     if (!grow(s, s->items_off, s->items_cap, sizeof(Item) * std::max<size_t>(n_items, 1)) ||
         !grow(s, s->chunks_off, s->chunks_cap, sizeof(ChunkItem) * std::max<size_t>(n_chunks, 1)) ||
-        !grow(s, s->sweep_off, s->sweep_cap, sizeof(SweepItem) * std::max<size_t>(sweep.size(), 1)))
+        !grow(s, s->sweep_off, s->sweep_cap, sizeof(SweepItem) * std::max<size_t>(sweep.size(), 1)) ||
+        !grow(s, s->meas_off, s->meas_cap, sizeof(SweepItem) * std::max<size_t>(n_meas, 1)))
         return PA_ERR_NOMEM;
-    size_t ai = 0, ac = 0;
+    size_t ai = 0, ac = 0, am = 0;
     for (int k = 0; k < s->max_slots; ++k) {
         const Slot &sl = s->slots[k];
         if (!sl.used) continue;
         const int npop = n_pop_of(sl.d.overlap);
         const size_t ni = (size_t)npop * groups_cap_of(sl.d), nc = (size_t)npop * chunks_cap_of(sl.d);
+        const size_t nm = (size_t)npop * n_meas_items_of(sl.d);
         uint8_t *blk = s->base + sl.off;
         PA_SHIP(s, hipMemcpyAsync(s->base + s->items_off + ai * sizeof(Item), blk + sl.b.items, ni * sizeof(Item),
                                   hipMemcpyDeviceToDevice, s->stream));
         PA_SHIP(s, hipMemcpyAsync(s->base + s->chunks_off + ac * sizeof(ChunkItem), blk + sl.b.chunks,
                                   nc * sizeof(ChunkItem), hipMemcpyDeviceToDevice, s->stream));
+        PA_SHIP(s, hipMemcpyAsync(s->base + s->meas_off + am * sizeof(SweepItem), blk + sl.b.meas,
+                                  nm * sizeof(SweepItem), hipMemcpyDeviceToDevice, s->stream));
         ai += ni;
         ac += nc;
+        am += nm;
     }
     pa_status st = upload(s, s->base + s->sweep_off, sweep.data(), sizeof(SweepItem) * sweep.size());
     if (st != PA_OK) return st;
@@ -289,6 +297,8 @@ pa_status rebuild(pa_server *s)
     c.n_items = (int)n_items;
     c.chunk_items = (const ChunkItem *)(s->base + s->chunks_off);
     c.n_chunk_items = (int)n_chunks;
+    c.meas_items = (const SweepItem *)(s->base + s->meas_off);
+    c.n_meas_items = (int)n_meas;
     c.run0 = 0;
     c.n_runs = hi;
     c.npop_ctx = npop_ctx;
@@ -476,22 +486,22 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     for (int p = 0; p < npop; ++p) hst[p] = initial_popstate(sl.d);
     std::vector<Item> items;
     std::vector<ChunkItem> chunks;
+    std::vector<SweepItem> meas;
     for (int p = 0; p < npop; ++p) {
         for (int g = 0; g < groups_cap_of(d); ++g) items.push_back({k, p, g, 0});
         for (int q = 0; q < chunks_cap_of(d); ++q) chunks.push_back({k, p, q, 0});
+        meas_items_of(d, k, p, meas);
     }
     const uint64_t ds = d.disorder_seed;
     if ((st = upload(s, s->base + s->runinfo + sizeof(RunInfo) * k, &I, sizeof(I))) != PA_OK ||
         (st = upload(s, s->base + s->popstate + sizeof(PopState) * MAX_POP * k, hst, sizeof(hst))) != PA_OK ||
         (st = upload(s, blk + b.items, items.data(), sizeof(Item) * items.size())) != PA_OK ||
         (st = upload(s, blk + b.chunks, chunks.data(), sizeof(ChunkItem) * chunks.size())) != PA_OK ||
+        (st = upload(s, blk + b.meas, meas.data(), sizeof(SweepItem) * meas.size())) != PA_OK ||
         (st = upload(s, blk + b.dseed, &ds, sizeof(ds))) != PA_OK)
         return st;
     bool ok = true;
-    for (int p = 0; p < npop && ok; ++p) {
-        ok = launch_fill_u32(blk + b.o.famcnt[p], 0, d.R, s->stream) == hipSuccess;
-        ok = ok && launch_fill_u32(blk + b.o.r[p], 0, d.R_cap, s->stream) == hipSuccess;
-    }
+    for (int p = 0; p < npop && ok; ++p) ok = launch_fill_u32(blk + b.o.r[p], 0, d.R_cap, s->stream) == hipSuccess;
     if (d.qhist && ok)
         ok = launch_fill_u32(blk + b.o.qh, 0, (size_t)npop * d.K * (N + 1), s->stream) == hipSuccess;
     ok = ok && launch_fill_u32(blk + b.obs, 0, sizeof(pa_obs) / 4 * (size_t)d.K * npop, s->stream) == hipSuccess;
@@ -502,6 +512,8 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     c.n_items = (int)items.size();
     c.chunk_items = (const ChunkItem *)(blk + b.chunks);
     c.n_chunk_items = (int)chunks.size();
+    c.meas_items = (const SweepItem *)(blk + b.meas);
+    c.n_meas_items = (int)meas.size();
     c.run0 = k;
     c.n_runs = 1;
     c.npop_ctx = npop;
