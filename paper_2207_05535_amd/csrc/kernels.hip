@@ -400,6 +400,34 @@ __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items,
     const uint64_t *B = R.base64[it.pop];
     const uint32_t c3 = (TAG_MN << 28) | ((uint32_t)it.pop << 24);
     int32_t *r = R.r[it.pop];
+    if (R.R <= CH && Rp <= CH) {
+        // the whole run in this workgroup: prefix and counts in LDS, the
+        // counts are written out once (no global atomics)
+        __shared__ uint64_t sP[CH];
+        __shared__ int32_t sr[CH];
+        for (int j = threadIdx.x; j < Rp; j += CH_THREADS) {
+            sP[j] = P[j];     // one chunk: base64[0] = 0
+            sr[j] = 0;
+        }
+        __syncthreads();
+        for (int q = 0; q < CH_PER; ++q) {
+            const int d = threadIdx.x + q * CH_THREADS;
+            if (d >= R.R) break;
+            const u32x4 o = philox10((uint32_t)d, 0, (uint32_t)S.i, c3, R.key0, R.key1);
+            const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
+            const uint64_t t = umul64hi(v, SX);
+            int lo = 0, hi = Rp - 1;
+            while (lo < hi) {
+                const int mid = lo + ((hi - lo + 1) >> 1);
+                if (sP[mid] <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            atomicAdd(&sr[lo], 1);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < Rp; j += CH_THREADS) r[j] = sr[j];
+        return;
+    }
     for (int q = 0; q < CH_PER; ++q) {
         const int d = d0 + threadIdx.x + q * CH_THREADS;
         if (d >= R.R) break;
@@ -518,6 +546,24 @@ __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, c
     const int32_t *C = R.C[it.pop];
     const int32_t *B = R.base32[it.pop];
     int32_t *par = R.parent[it.pop];
+    if (Rp <= CH) {
+        // one chunk of parents (base32[0] = 0): search the prefix in LDS
+        __shared__ int32_t sC[CH];
+        for (int j = threadIdx.x; j < Rp; j += CH_THREADS) sC[j] = C[j];
+        __syncthreads();
+        for (int q = 0; q < CH_PER; ++q) {
+            const int c = c0 + threadIdx.x + q * CH_THREADS;
+            if (c >= Rc) break;
+            int lo = 0, hi = Rp - 1;
+            while (lo < hi) {
+                const int mid = lo + ((hi - lo + 1) >> 1);
+                if (sC[mid] <= c) lo = mid;
+                else hi = mid - 1;
+            }
+            par[c] = lo;
+        }
+        return;
+    }
     for (int q = 0; q < CH_PER; ++q) {
         const int c = c0 + threadIdx.x + q * CH_THREADS;
         if (c >= Rc) break;
@@ -542,28 +588,22 @@ __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, c
 constexpr int COPY_MAX_SRC = 4;
 
 template <int REPR>
-__global__ void __launch_bounds__(256) k_copy(const Item *items, const RunInfo *runs, const PopState *st)
+__device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, int pop, int G, int sub, int wpg)
 {
-    const Item it = items[blockIdx.x];
-    const RunInfo &R = runs[it.run];
-    const PopState &S = st[it.run * MAX_POP + it.pop];
-    if (!pop_active(S)) return;
     const int Rc = S.Rcur;
-    const int G = it.group;
-    if (G * 64 >= Rc) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int c = G * 64 + lane;
     const bool valid = c < Rc;
     const int clast = min(Rc, G * 64 + 64) - 1;
-    const int p = R.parent[it.pop][valid ? c : clast];
+    const int p = R.parent[pop][valid ? c : clast];
     const int N = R.N;
     if (REPR == PA_MSC64) {
-        const uint64_t *src = (const uint64_t *)R.spins[it.pop][S.src];
-        uint64_t *dst = (uint64_t *)R.spins[it.pop][S.cur] + (size_t)G * N;
+        const uint64_t *src = (const uint64_t *)R.spins[pop][S.src];
+        uint64_t *dst = (uint64_t *)R.spins[pop][S.cur] + (size_t)G * N;
         const int g_lo = __shfl(p, 0, 64) >> 6;
         const int g_hi = __shfl(p, 63, 64) >> 6;
         if (g_hi - g_lo < COPY_MAX_SRC) {
-            for (int n0 = wv * 64; n0 < N; n0 += nw * 64) {
+            for (int n0 = sub * 64; n0 < N; n0 += wpg * 64) {
                 const int n = n0 + lane;
                 uint64_t row = 0;
                 for (int gs = g_lo; gs <= g_hi; ++gs) {
@@ -579,7 +619,7 @@ __global__ void __launch_bounds__(256) k_copy(const Item *items, const RunInfo *
         } else {
             const uint64_t *ps = src + (size_t)(p >> 6) * N;
             const int pb = p & 63;
-            for (int nb = wv * 64; nb < N; nb += nw * 64) {
+            for (int nb = sub * 64; nb < N; nb += wpg * 64) {
                 uint64_t mine = 0;
                 const int cnt = min(64, N - nb);
                 for (int k = 0; k < cnt; ++k) {
@@ -591,14 +631,32 @@ __global__ void __launch_bounds__(256) k_copy(const Item *items, const RunInfo *
             }
         }
     } else {
-        const uint8_t *src = R.spins[it.pop][S.src] + (size_t)(p >> 6) * N * 64 + (p & 63);
-        uint8_t *dst = R.spins[it.pop][S.cur] + (size_t)G * N * 64 + lane;
-        for (int n = wv; n < N; n += nw) dst[(size_t)n * 64] = valid ? src[(size_t)n * 64] : (uint8_t)1;
+        const uint8_t *src = R.spins[pop][S.src] + (size_t)(p >> 6) * N * 64 + (p & 63);
+        uint8_t *dst = R.spins[pop][S.cur] + (size_t)G * N * 64 + lane;
+        for (int n = sub; n < N; n += wpg) dst[(size_t)n * 64] = valid ? src[(size_t)n * 64] : (uint8_t)1;
     }
-    if (wv == 0 && valid) {
-        R.E[it.pop][S.cur][c] = R.E[it.pop][S.src][p];
-        R.fam[it.pop][S.cur][c] = R.fam[it.pop][S.src][p];
+    if (sub == 0 && valid) {
+        R.E[pop][S.cur][c] = R.E[pop][S.src][p];
+        R.fam[pop][S.cur][c] = R.fam[pop][S.src][p];
     }
+}
+
+// Workgroups of MEAS_WAVES wavefronts over the measure items: each group
+// gets meas_waves_per_group(N) wavefronts, which split its sites.
+template <int REPR>
+__global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, const RunInfo *runs,
+                                                       const PopState *st)
+{
+    const SweepItem it = items[blockIdx.x];
+    const RunInfo &R = runs[it.run];
+    const PopState &S = st[it.run * MAX_POP + it.pop];
+    if (!pop_active(S)) return;
+    const int wpg = meas_waves_per_group(R.N);
+    const int wv = threadIdx.x >> 6;
+    const int k = wv / wpg, sub = wv - k * wpg;
+    const int G = it.group0 + k;
+    if (k >= it.ngroups || G * 64 >= S.Rcur) return;
+    copy_group<REPR>(R, S, it.pop, G, sub, wpg);
 }
 
 // ------------------------------------------------------------- step (iv)
@@ -733,40 +791,63 @@ __global__ void __launch_bounds__(1024) k_sweep_int8(const RunInfo *runs, const 
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
 template <int LT, bool EA>
-__device__ __forceinline__ void sweep_item(const SweepItem &it, const RunInfo &R, const PopState &S,
+__device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo &R, const PopState &S,
                                            uint64_t *lds, int dense, unsigned long long *stats)
 {
-    const int L = LT ? LT : R.L;
+    // Everything the loops need is read into registers before the first
+    // barrier: a barrier orders memory, so values left in global memory
+    // would be loaded again after every one of them.
+    const int L = LT ? LT : __builtin_amdgcn_readfirstlane(R.L);
     const int N = L * L, half = L >> 1, nh = N >> 1;
     const int T = blockDim.x, tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6, nw = T >> 6;
-    const int Rc = S.Rcur;
-    const int G = min(it.ngroups, (Rc + 63) / 64 - it.group0);
+    const int Rc = __builtin_amdgcn_readfirstlane(S.Rcur);
+    const int group0 = __builtin_amdgcn_readfirstlane(item.group0);
+    const int pop = __builtin_amdgcn_readfirstlane(item.pop);
+    const int theta = __builtin_amdgcn_readfirstlane(R.theta);
+    const uint32_t key0 = __builtin_amdgcn_readfirstlane(R.key0), key1 = __builtin_amdgcn_readfirstlane(R.key1);
+    const int G = min(__builtin_amdgcn_readfirstlane(item.ngroups), (Rc + 63) / 64 - group0);
     if (G <= 0) return;
     const int units = G * nh;
     uint64_t *lat = lds;                                  // [G][2][nh]
-    uint64_t *eu = lds + (size_t)G * N;                   // [units] undecided lanes
-    uint64_t *eo = eu + units;                            // [units] lanes of class dE = +4
-    uint32_t *en = (uint32_t *)(eo + units);              // [units] (LDS word << 16) | site
-    uint8_t *jb = (uint8_t *)(en + units);                // [N] couplings (spin glass)
-    uint64_t *base = (uint64_t *)R.spins[it.pop][S.cur] + (size_t)it.group0 * N;
+    uint64_t *e4 = lds + (size_t)G * N;                   // [units] undecided lanes of class dE = +4
+    uint64_t *e8 = e4 + units;                            // [units] undecided lanes of class dE = +8
+    uint32_t *en = (uint32_t *)(e8 + units);              // [units] (LDS word << 16) | site
+    uint8_t *jb = (uint8_t *)(en + units);                // [2][nh] bond signs of each site (spin glass)
+    uint64_t *base = (uint64_t *)R.spins[pop][S.cur] + (size_t)group0 * N;
     for (int u = tid; u < G * N; u += T) {
         const int gs = u / N, n = u - gs * N;
         const int y = n / L, x = n - y * L;
         lat[(size_t)gs * N + ((x + y) & 1) * nh + y * half + (x >> 1)] = base[u];
     }
+    // Colour-split neighbours of site k = y half + m (x = 2m + p, p = (y +
+    // colour) & 1) in the other colour's array: k itself and kh = k - 1 or
+    // k + 1 within the row (the horizontal pair), k -+ half (up, down).
+    // jb holds the signs of the four bonds in that order (bit set: J = -1).
     if (EA)
-        for (int n = tid; n < N; n += T) jb[n] = R.jbits[n];
-    const int i = S.i;
+        for (int v = tid; v < N; v += T) {
+            const int colour = v / nh, k = v - colour * nh;
+            const int y = k / half, m = k - y * half;
+            const int p = (y + colour) & 1, x = 2 * m + p;
+            const int xl = x == 0 ? L - 1 : x - 1, yu = y == 0 ? L - 1 : y - 1;
+            const uint8_t jn = R.jbits[y * L + x];
+            const uint32_t jr = jn & 1u, jd = (jn >> 1) & 1u;
+            const uint32_t jl = R.jbits[y * L + xl] & 1u, ju = (R.jbits[yu * L + x] >> 1) & 1u;
+            // k is the right neighbour when p = 0 and the left one when p = 1
+            const uint32_t jk = p ? jl : jr, jh = p ? jr : jl;
+            jb[v] = (uint8_t)(jk | (jh << 1) | (ju << 2) | (jd << 3));
+        }
+    const int i = __builtin_amdgcn_readfirstlane(S.i);
     const Thresholds Th = thresholds_of(R.tabT, i);
-    const uint32_t c3p = (TAG_SWEEP << 28) | ((uint32_t)it.pop << 24);
-    const int lastg = it.group0 + G - 1;
+    const uint32_t c3p = (TAG_SWEEP << 28) | ((uint32_t)pop << 24);
+    const int lastg = group0 + G - 1;
     const uint64_t vlast = (Rc - lastg * 64 >= 64) ? ~0ull : ((1ull << (Rc - lastg * 64)) - 1);
     const int upw = (units + nw - 1) / nw;
     const int ub = min(units, wv * upw), ue = min(units, ub + upw);
     const uint64_t lt_mask = __lanemask_lt();
-    uint32_t nwords = 0, ncalls = 0, nflips = 0;
-    for (int s = 0; s < R.theta; ++s) {
+    uint32_t nwords = 0, nflips = 0;
+    uint32_t wcalls = 0;   // Philox calls of this wavefront (uniform)
+    for (int s = 0; s < theta; ++s) {
         const uint32_t c3 = c3p | (uint32_t)s;
         for (int colour = 0; colour < 2; ++colour) {
             __syncthreads();
@@ -774,52 +855,54 @@ __device__ __forceinline__ void sweep_item(const SweepItem &it, const RunInfo &R
             // dense rounds
             for (int u0 = ub; u0 < ue; u0 += 64) {
                 const int u = u0 + lane;
-                uint64_t und = 0, one = 0, acc = 0;
+                uint64_t und4 = 0, und8 = 0, acc = 0;
                 int addr = 0;
                 uint32_t n = 0, g = 0;
                 if (u < ue) {
                     const int gs = u / nh, k = u - gs * nh;
                     const int y = k / half, m = k - y * half;
-                    const int x = 2 * m + ((y + colour) & 1);
-                    const int xr = x + 1 == L ? 0 : x + 1, xl = x == 0 ? L - 1 : x - 1;
-                    const int yd = y + 1 == L ? 0 : y + 1, yu = y == 0 ? L - 1 : y - 1;
+                    const int p = (y + colour) & 1;
+                    int mh = p ? m + 1 : m - 1;                  // the other horizontal neighbour
+                    mh = mh < 0 ? half - 1 : (mh == half ? 0 : mh);
+                    const int kh = k - m + mh;
+                    const int ku = y == 0 ? k + nh - half : k - half;
+                    const int kd = y + 1 == L ? k - nh + half : k + half;
                     addr = gs * N + colour * nh + k;
                     const uint64_t *oth = lat + (size_t)gs * N + (colour ^ 1) * nh;
                     const uint64_t w = lat[addr];
-                    uint64_t jr = 0, jl = 0, jd = 0, ju = 0;
+                    uint64_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
                     if (EA) {
-                        const uint8_t jn = jb[y * L + x];
-                        jr = jmask(jn, 0);
-                        jd = jmask(jn, 1);
-                        jl = jmask(jb[y * L + xl], 0);
-                        ju = jmask(jb[yu * L + x], 1);
+                        const uint32_t jm = jb[colour * nh + k];
+                        j0 = jmask((uint8_t)jm, 0);
+                        j1 = jmask((uint8_t)jm, 1);
+                        j2 = jmask((uint8_t)jm, 2);
+                        j3 = jmask((uint8_t)jm, 3);
                     }
-                    SiteClass sc = classify<EA>(w, oth[y * half + (xr >> 1)], oth[y * half + (xl >> 1)],
-                                                oth[yd * half + m], oth[yu * half + m], jr, jl, jd, ju);
+                    SiteClass sc = classify<EA>(w, oth[k], oth[kh], oth[ku], oth[kd], j0, j1, j2, j3);
                     if (Th.all4) { sc.flip |= sc.one; sc.one = 0; }
                     if (Th.all8) { sc.flip |= sc.zero; sc.zero = 0; }
-                    const uint64_t valid = it.group0 + gs == lastg ? vlast : ~0ull;
+                    const uint64_t valid = group0 + gs == lastg ? vlast : ~0ull;
                     acc = sc.flip;
-                    und = bop3<LUT_OR_AND>(sc.one, sc.zero, valid);
-                    one = sc.one;
-                    n = (uint32_t)(y * L + x);
-                    g = (uint32_t)(it.group0 + gs);
+                    und4 = sc.one & valid;
+                    und8 = sc.zero & valid;
+                    n = (uint32_t)(y * L + 2 * m + p);
+                    g = (uint32_t)(group0 + gs);
                     nflips += (uint32_t)__popcll(valid);
                     ++nwords;
                 }
                 for (int c = 0; c < dense; ++c) {
-                    if (__ballot(und != 0) == 0) break;
-                    if (und != 0) {
-                        draw_step((uint32_t)c, Th, one, und, acc, n, g, (uint32_t)i, c3, R.key0, R.key1);
-                        ++ncalls;
-                    }
+                    const uint64_t live = __ballot((und4 | und8) != 0);
+                    if (live == 0) break;
+                    wcalls += (uint32_t)__popcll(live);
+                    if ((und4 | und8) != 0)
+                        draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, (uint32_t)i, c3, key0, key1);
                 }
                 if (acc) lat[addr] ^= acc;
-                const uint64_t need = __ballot(und != 0);
-                if (und != 0) {
+                const uint64_t need = __ballot((und4 | und8) != 0);
+                if ((und4 | und8) != 0) {
                     const int slot = ub + cnt + __popcll(need & lt_mask);
-                    eu[slot] = und;
-                    eo[slot] = one;
+                    e4[slot] = und4;
+                    e8[slot] = und8;
                     en[slot] = ((uint32_t)addr << 16) | n;
                 }
                 cnt += __popcll(need);
@@ -829,24 +912,24 @@ __device__ __forceinline__ void sweep_item(const SweepItem &it, const RunInfo &R
                 int wcnt = 0;
                 for (int e0 = 0; e0 < cnt; e0 += 64) {
                     const int e = e0 + lane;
-                    uint64_t und = 0, one = 0, acc = 0;
+                    uint64_t und4 = 0, und8 = 0, acc = 0;
                     uint32_t pk = 0;
+                    wcalls += (uint32_t)min(64, cnt - e0);
                     if (e < cnt) {
-                        und = eu[ub + e];
-                        one = eo[ub + e];
+                        und4 = e4[ub + e];
+                        und8 = e8[ub + e];
                         pk = en[ub + e];
                         const int addr = (int)(pk >> 16);
-                        const uint32_t g = (uint32_t)(it.group0 + addr / N);
-                        draw_step((uint32_t)c, Th, one, und, acc, pk & 0xFFFFu, g, (uint32_t)i, c3, R.key0,
-                                  R.key1);
-                        ++ncalls;
+                        const uint32_t g = (uint32_t)(group0 + addr / N);
+                        draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, (uint32_t)i, c3,
+                                  key0, key1);
                         if (acc) lat[addr] ^= acc;
                     }
-                    const uint64_t need = __ballot(und != 0);
-                    if (und != 0) {
+                    const uint64_t need = __ballot((und4 | und8) != 0);
+                    if ((und4 | und8) != 0) {
                         const int slot = ub + wcnt + __popcll(need & lt_mask);
-                        eu[slot] = und;
-                        eo[slot] = one;
+                        e4[slot] = und4;
+                        e8[slot] = und8;
                         en[slot] = pk;
                     }
                     wcnt += __popcll(need);
@@ -861,7 +944,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &it, const RunInfo &R
         const int y = n / L, x = n - y * L;
         base[u] = lat[(size_t)gs * N + ((x + y) & 1) * nh + y * half + (x >> 1)];
     }
-    flush_stats(stats, nwords, ncalls, nflips);
+    flush_stats(stats, nwords, lane == 0 ? wcalls : 0u, nflips);
 }
 
 template <bool EA>
@@ -1025,18 +1108,18 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
                 vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
             }
         }
-        if (++since == 16) {   // at most 2 per site: 32 < 2^VB
+        // flush every 16 sites per lane (at most 2 per site: 32 < 2^VB);
+        // mode is uniform over the wavefront, so are the overlap flushes
+        if (++since == 16 || base + 64 * wpg >= N) {
             since = 0;
             totU += vflush(cU);
             totD += vflush(cD);
-            totH += vflush(cH);
-            totK += vflush(cK);
+            if (mode) {
+                totH += vflush(cH);
+                totK += vflush(cK);
+            }
         }
     }
-    totU += vflush(cU);
-    totD += vflush(cD);
-    totH += vflush(cH);
-    totK += vflush(cK);
     if (wpg > 1) {
         red[0][wv][lane] = totU;
         red[1][wv][lane] = totD;
@@ -1494,8 +1577,12 @@ hipError_t launch_resample(const LaunchCtx &c)
     PA_CHECK_LAUNCH();
     k_parent<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
-    if (c.repr == PA_MSC64) k_copy<PA_MSC64><<<c.n_items, 256, 0, c.stream>>>(c.items, c.runs, c.st);
-    else k_copy<PA_INT8><<<c.n_items, 256, 0, c.stream>>>(c.items, c.runs, c.st);
+    if (c.n_meas_items > 0) {
+        if (c.repr == PA_MSC64)
+            k_copy<PA_MSC64><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+        else
+            k_copy<PA_INT8><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+    }
     return hipGetLastError();
 }
 

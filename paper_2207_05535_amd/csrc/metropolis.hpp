@@ -66,30 +66,49 @@ __device__ __forceinline__ SiteClass classify(uint64_t w, uint64_t nr, uint64_t 
     return c;
 }
 
+constexpr int LUT_ACCEPT = lut3(LUT_A & ~LUT_B & LUT_C);           // und & ~plane & m
+constexpr int LUT_KEEP = lut3(LUT_A & ~(LUT_B ^ LUT_C));             // und & ~(plane ^ m)
+constexpr int LUT_OR3 = lut3(LUT_A | LUT_B | LUT_C);
+
 // One bit plane of the most-significant-first comparison u < T for the
-// undecided lanes `und`: tb is T's bit for each lane's class (dE = +4 lanes
-// where `one` is set, dE = +8 lanes elsewhere); a lane whose draw bit is 0
-// where tb is 1 is accepted, a lane whose bits differ otherwise is rejected,
-// equal bits stay undecided.
-__device__ __forceinline__ void plane_step(uint64_t plane, uint64_t one, uint64_t m4, uint64_t m8,
-                                           uint64_t &und, uint64_t &acc)
+// undecided lanes of both classes (dE = +4 in und4, dE = +8 in und8).  m4
+// and m8 are all ones where T's bit at this plane is 1 for that class, and
+// the same for the whole wavefront.  A lane whose draw bit differs from T's
+// bit is decided (accepted iff T's bit is 1); equal bits stay undecided.
+// Five three-input operations per 32 bits, each with one scalar operand.
+__device__ __forceinline__ void plane_both(uint64_t plane, uint32_t m4, uint32_t m8, uint64_t &und4,
+                                           uint64_t &und8, uint64_t &acc)
 {
-    const uint64_t tb = bop3<LUT_SEL>(one, m4, m8);
-    acc |= bop3<LUT_WIN>(und, tb, plane);
-    und = bop3<LUT_TIE>(und, tb, plane);
+    const uint32_t p[2] = {(uint32_t)plane, (uint32_t)(plane >> 32)};
+    uint32_t u4[2] = {(uint32_t)und4, (uint32_t)(und4 >> 32)};
+    uint32_t u8[2] = {(uint32_t)und8, (uint32_t)(und8 >> 32)};
+    uint32_t a[2] = {(uint32_t)acc, (uint32_t)(acc >> 32)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t x4 = bop3<LUT_ACCEPT>(u4[h], p[h], m4);
+        const uint32_t x8 = bop3<LUT_ACCEPT>(u8[h], p[h], m8);
+        a[h] = bop3<LUT_OR3>(a[h], x4, x8);
+        u4[h] = bop3<LUT_KEEP>(u4[h], p[h], m4);
+        u8[h] = bop3<LUT_KEEP>(u8[h], p[h], m8);
+    }
+    und4 = (uint64_t)u4[0] | ((uint64_t)u4[1] << 32);
+    und8 = (uint64_t)u8[0] | ((uint64_t)u8[1] << 32);
+    acc = (uint64_t)a[0] | ((uint64_t)a[1] << 32);
 }
 
-// Philox call c of a site: planes 2c and 2c+1 compared against T.
-__device__ __forceinline__ void draw_step(uint32_t c, const Thresholds &T, uint64_t one, uint64_t &und,
+// Philox call c of a site: planes 2c and 2c+1 compared against the
+// thresholds t4 = T(beta, 4) and t8 = T(beta, 8) (low 32 bits; both
+// wavefront-uniform), for the undecided lanes of each class.
+__device__ __forceinline__ void draw_call(uint32_t c, uint32_t t4, uint32_t t8, uint64_t &und4, uint64_t &und8,
                                           uint64_t &acc, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1)
 {
     const u32x4 o = philox10(c0 | (c << 20), c1, c2, c3, k0, k1);
-    const int sh = 31 - 2 * (int)c;
-    const uint64_t m4a = (T.t4 >> sh) & 1u ? ~0ull : 0ull, m8a = (T.t8 >> sh) & 1u ? ~0ull : 0ull;
-    const uint64_t m4b = (T.t4 >> (sh - 1)) & 1u ? ~0ull : 0ull, m8b = (T.t8 >> (sh - 1)) & 1u ? ~0ull : 0ull;
-    plane_step((uint64_t)o.x | ((uint64_t)o.y << 32), one, m4a, m8a, und, acc);
-    plane_step((uint64_t)o.z | ((uint64_t)o.w << 32), one, m4b, m8b, und, acc);
+    const uint32_t sh = 31u - 2u * c;
+    const uint64_t pa = (uint64_t)o.x | ((uint64_t)o.y << 32);
+    const uint64_t pb = (uint64_t)o.z | ((uint64_t)o.w << 32);
+    plane_both(pa, 0u - ((t4 >> sh) & 1u), 0u - ((t8 >> sh) & 1u), und4, und8, acc);
+    plane_both(pb, 0u - ((t4 >> (sh - 1u)) & 1u), 0u - ((t8 >> (sh - 1u)) & 1u), und4, und8, acc);
 }
 
 // Flip mask of one site, all draws done here (used by the plain path).
@@ -102,23 +121,25 @@ __device__ __forceinline__ uint64_t flip_mask(uint64_t w, uint64_t nr, uint64_t 
     SiteClass sc = classify<true>(w, nr, nl, nd, nu, jr, jl, jd, ju);
     if (T.all4) { sc.flip |= sc.one; sc.one = 0; }
     if (T.all8) { sc.flip |= sc.zero; sc.zero = 0; }
-    uint64_t und = (sc.one | sc.zero) & valid;
-    uint64_t acc = 0;
-    for (uint32_t c = 0; und != 0 && c < 16; ++c) {
-        draw_step(c, T, sc.one, und, acc, c0, c1, c2, c3, k0, k1);
+    uint64_t und4 = sc.one & valid, und8 = sc.zero & valid;
+    uint64_t acc = sc.flip;
+    for (uint32_t c = 0; (und4 | und8) != 0 && c < 16; ++c) {
+        draw_call(c, T.t4, T.t8, und4, und8, acc, c0, c1, c2, c3, k0, k1);
         ++calls;
     }
-    return sc.flip | acc;
+    return acc;
 }
 
+// Thresholds of temperature i, read once per workgroup and kept in scalar
+// registers.
 __device__ __forceinline__ Thresholds thresholds_of(const uint64_t *tabT, int i)
 {
     Thresholds T;
     const uint64_t a = tabT[2 * i], b = tabT[2 * i + 1];
-    T.t4 = (uint32_t)a;
-    T.t8 = (uint32_t)b;
-    T.all4 = a >= (1ull << 32);
-    T.all8 = b >= (1ull << 32);
+    T.t4 = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    T.t8 = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    T.all4 = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) != 0;
+    T.all8 = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) != 0;
     return T;
 }
 
