@@ -907,8 +907,33 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                 }
                 cnt += __popcll(need);
             }
-            // sparse rounds over the compacted list
+            // sparse rounds over the compacted list; once one pass holds
+            // every remaining entry, it runs all their remaining calls
+            // without writing the list back
             for (int c = dense; c < 16 && cnt > 0; ++c) {
+                if (cnt <= 64) {
+                    const int e = lane;
+                    uint64_t und4 = 0, und8 = 0, acc = 0;
+                    int addr = 0;
+                    uint32_t n = 0, g = 0;
+                    if (e < cnt) {
+                        und4 = e4[ub + e];
+                        und8 = e8[ub + e];
+                        const uint32_t pk = en[ub + e];
+                        addr = (int)(pk >> 16);
+                        n = pk & 0xFFFFu;
+                        g = (uint32_t)(group0 + addr / N);
+                    }
+                    for (; c < 16; ++c) {
+                        const uint64_t live = __ballot((und4 | und8) != 0);
+                        if (live == 0) break;
+                        wcalls += (uint32_t)__popcll(live);
+                        if ((und4 | und8) != 0)
+                            draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, (uint32_t)i, c3, key0, key1);
+                    }
+                    if (acc) lat[addr] ^= acc;
+                    break;
+                }
                 int wcnt = 0;
                 for (int e0 = 0; e0 < cnt; e0 += 64) {
                     const int e = e0 + lane;
