@@ -123,5 +123,6 @@ bool plan_sweep(const pa_ctx *c, std::vector<SweepItem> &items, size_t &lds);
 pa_status upload_sweep_plan(pa_ctx *c);
 pa_status enqueue_step(pa_ctx *c);
 void drop_graph(pa_ctx *c);
+pa_status read_stats(pa_ctx *c, uint64_t out[3]);   // sums the counter slots; synchronises
 
 }  // namespace pa

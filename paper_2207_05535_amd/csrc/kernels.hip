@@ -661,7 +661,8 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, c
 
 // ------------------------------------------------------------- step (iv)
 
-// One atomic per wavefront: the sweep kernels' exact work counts.
+// The sweep kernels' exact work counters: one set of atomics per
+// wavefront, into a slot chosen by workgroup and wavefront.
 __device__ __forceinline__ void flush_stats(unsigned long long *stats, uint32_t words, uint32_t calls,
                                             uint32_t flips)
 {
@@ -669,9 +670,11 @@ __device__ __forceinline__ void flush_stats(unsigned long long *stats, uint32_t 
     const unsigned long long c = wave_sum<unsigned long long>(calls);
     const unsigned long long f = wave_sum<unsigned long long>(flips);
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&stats[ST_WORDS], w);
-        atomicAdd(&stats[ST_CALLS], c);
-        atomicAdd(&stats[ST_FLIPS], f);
+        const unsigned slot = (blockIdx.x * 16u + (threadIdx.x >> 6)) % STAT_SLOTS;
+        unsigned long long *p = stats + (size_t)slot * NSTAT;
+        atomicAdd(&p[ST_WORDS], w);
+        atomicAdd(&p[ST_CALLS], c);
+        atomicAdd(&p[ST_FLIPS], f);
     }
 }
 
@@ -679,16 +682,104 @@ __device__ __forceinline__ uint64_t jmask(uint8_t b, int bit) { return ((b >> bi
 
 // Plain path: one colour of one run per launch, int8 spins ([group][site][64
 // replicas] bytes).  A workgroup takes `rows` lattice rows of one replica
-// group (plus one halo row on each side unless it holds the whole lattice).
-// Consecutive lanes load consecutive 16-byte chunks (coalesced), pack their
-// sign bits into an LDS bit-lattice (one 64-bit word per site), and keep the
-// chunks in registers; the colour's sites are then updated from the packed
-// words, and each lane XORs the flips of its chunk back and stores it.
-constexpr int I8_CMAX = 16;   // 16-byte chunks held per thread
+// group, plus one halo row on each side unless it holds the whole lattice.
+// All of its 16-byte chunks are loaded first (consecutive lanes take
+// consecutive chunks, so the loads coalesce and are all in flight at once),
+// their sign bits are packed into an LDS bit-lattice (one 64-bit word per
+// site), the colour's sites are updated from the packed words, and each
+// lane XORs the flips of its chunks back and stores the chunks that change.
+constexpr int I8_CMAX = 12;   // 16-byte chunks held per thread
 
 __device__ __forceinline__ uint32_t signs16(const uint4 &v)
 {
     return signs4(v.x) | (signs4(v.y) << 4) | (signs4(v.z) << 8) | (signs4(v.w) << 12);
+}
+
+template <int LT>
+__device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState &S, int pop, int g, int tile,
+                                                int s, int colour, int T, uint64_t *sm, unsigned long long *stats)
+{
+    const int L = LT ? LT : R.L;
+    const int N = L * L, half = L >> 1;
+    const int Rc = S.Rcur;
+    const int y0 = tile * T;
+    const int rows = min(T, L - y0);
+    const int halo = rows == L ? 0 : 1;
+    const int nrow = rows + 2 * halo;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    uint64_t *packed = sm;                              // [nrow][L]
+    uint64_t *fm = sm + (size_t)nrow * L;               // [rows][half]
+    uint16_t *pk16 = (uint16_t *)packed;
+    uint8_t *base = R.spins[pop][S.cur] + (size_t)g * N * 64;
+    const int i = S.i;
+    const Thresholds Th = thresholds_of(R.tabT, i);
+    const uint32_t key0 = R.key0, key1 = R.key1;
+    const uint8_t *jbits = R.jbits;
+    const int chunks = nrow * L * 4;
+    uint4 reg[I8_CMAX];
+    size_t off[I8_CMAX];
+#pragma unroll
+    for (int q = 0; q < I8_CMAX; ++q) {
+        const int c = tid + q * nthr;
+        const int site = c >> 2, part = c & 3;
+        const int rr = site / L, x = site - rr * L;
+        int y = y0 - halo + rr;
+        y = y < 0 ? y + L : (y >= L ? y - L : y);
+        off[q] = (size_t)(y * L + x) * 64 + part * 16;
+    }
+#pragma unroll
+    for (int q = 0; q < I8_CMAX; ++q)
+        if (tid + q * nthr < chunks) reg[q] = *(const uint4 *)(base + off[q]);
+#pragma unroll
+    for (int q = 0; q < I8_CMAX; ++q) {
+        const int c = tid + q * nthr;
+        if (c < chunks) pk16[c] = (uint16_t)signs16(reg[q]);
+    }
+    __syncthreads();
+    const uint32_t c3 = (TAG_SWEEP << 28) | ((uint32_t)pop << 24) | (uint32_t)s;
+    const uint64_t valid = (Rc - g * 64 >= 64) ? ~0ull : ((1ull << (Rc - g * 64)) - 1);
+    const uint32_t lanes = (uint32_t)__popcll(valid);
+    uint32_t nwords = 0, ncalls = 0;
+    for (int idx = tid; idx < rows * half; idx += nthr) {
+        const int yy = idx / half, m = idx - yy * half;
+        const int y = y0 + yy;
+        const int x = 2 * m + ((y + colour) & 1);
+        const int n = y * L + x;
+        const int xr = x + 1 == L ? 0 : x + 1, xl = x == 0 ? L - 1 : x - 1;
+        const int yu = y == 0 ? L - 1 : y - 1;
+        const int rc = yy + halo;
+        const int rd = halo ? rc + 1 : (rc + 1 == L ? 0 : rc + 1);
+        const int ru = halo ? rc - 1 : (rc == 0 ? L - 1 : rc - 1);
+        const uint64_t w = packed[rc * L + x];
+        const uint8_t jn = jbits[n];
+        fm[idx] = flip_mask(w, packed[rc * L + xr], packed[rc * L + xl], packed[rd * L + x], packed[ru * L + x],
+                            jmask(jn, 0), jmask(jbits[y * L + xl], 0), jmask(jn, 1), jmask(jbits[yu * L + x], 1),
+                            Th, valid, (uint32_t)n, (uint32_t)g, (uint32_t)i, c3, key0, key1, ncalls);
+        ++nwords;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < I8_CMAX; ++q) {
+        const int c = tid + q * nthr;
+        if (c < chunks) {
+            const int site = c >> 2, part = c & 3;
+            const int rr = site / L, x = site - rr * L;
+            const int yy = rr - halo;
+            const int y = y0 + yy;
+            if (yy >= 0 && yy < rows && ((x + y) & 1) == colour) {
+                const uint32_t f = (uint32_t)(fm[yy * half + (x >> 1)] >> (16 * part)) & 0xFFFFu;
+                if (f) {
+                    uint4 v = reg[q];
+                    v.x ^= negmask4(f & 15u);
+                    v.y ^= negmask4((f >> 4) & 15u);
+                    v.z ^= negmask4((f >> 8) & 15u);
+                    v.w ^= negmask4((f >> 12) & 15u);
+                    *(uint4 *)(base + off[q]) = v;
+                }
+            }
+        }
+    }
+    flush_stats(stats, nwords, ncalls, nwords * lanes);
 }
 
 __global__ void __launch_bounds__(1024) k_sweep_int8(const RunInfo *runs, const PopState *st, int run, int pop,
@@ -700,78 +791,16 @@ __global__ void __launch_bounds__(1024) k_sweep_int8(const RunInfo *runs, const 
     const PopState &S = st[run * MAX_POP + pop];
     if (!pop_active(S)) return;
     const int g = blockIdx.x / ntiles, tile = blockIdx.x - g * ntiles;
-    const int Rc = S.Rcur;
-    if (g * 64 >= Rc) return;
-    const int L = R.L, N = R.N, half = L >> 1;
-    const int y0 = tile * T;
-    const int rows = min(T, L - y0);
-    const int halo = rows == L ? 0 : 1;
-    const int nrow = rows + 2 * halo;
-    uint64_t *packed = sm;                              // [nrow][L]
-    uint64_t *fm = sm + (size_t)nrow * L;               // [rows][half]
-    uint16_t *pk16 = (uint16_t *)packed;
-    uint8_t *base = R.spins[pop][S.cur] + (size_t)g * N * 64;
-    const int chunks = nrow * L * 4;
-    uint4 reg[I8_CMAX];
-#pragma unroll
-    for (int q = 0; q < I8_CMAX; ++q) {
-        const int c = threadIdx.x + q * blockDim.x;
-        if (c < chunks) {
-            const int site = c >> 2, part = c & 3;
-            const int rr = site / L, x = site - rr * L;
-            const int y = (y0 - halo + rr + L) % L;
-            reg[q] = *(const uint4 *)(base + (size_t)(y * L + x) * 64 + part * 16);
-            pk16[site * 4 + part] = (uint16_t)signs16(reg[q]);
-        }
+    if (g * 64 >= S.Rcur) return;
+    switch (R.L) {
+    case 8: sweep_int8_tile<8>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 16: sweep_int8_tile<16>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 24: sweep_int8_tile<24>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 32: sweep_int8_tile<32>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 48: sweep_int8_tile<48>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 64: sweep_int8_tile<64>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    default: sweep_int8_tile<0>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
     }
-    __syncthreads();
-    const int i = S.i;
-    const Thresholds Th = thresholds_of(R.tabT, i);
-    const uint32_t c3 = (TAG_SWEEP << 28) | ((uint32_t)pop << 24) | (uint32_t)s;
-    const uint64_t valid = (Rc - g * 64 >= 64) ? ~0ull : ((1ull << (Rc - g * 64)) - 1);
-    const uint32_t lanes = (uint32_t)__popcll(valid);
-    uint32_t nwords = 0, ncalls = 0;
-    for (int idx = threadIdx.x; idx < rows * half; idx += blockDim.x) {
-        const int yy = idx / half, m = idx - yy * half;
-        const int y = y0 + yy;
-        const int x = 2 * m + ((y + colour) & 1);
-        const int n = y * L + x;
-        const int xr = x + 1 == L ? 0 : x + 1, xl = x == 0 ? L - 1 : x - 1;
-        const int yu = y == 0 ? L - 1 : y - 1;
-        const int rc = yy + halo;
-        const int rd = halo ? rc + 1 : (rc + 1 == L ? 0 : rc + 1);
-        const int ru = halo ? rc - 1 : (rc == 0 ? L - 1 : rc - 1);
-        const uint64_t w = packed[rc * L + x];
-        const uint8_t jn = R.jbits[n];
-        fm[idx] = flip_mask(w, packed[rc * L + xr], packed[rc * L + xl], packed[rd * L + x], packed[ru * L + x],
-                            jmask(jn, 0), jmask(R.jbits[y * L + xl], 0), jmask(jn, 1),
-                            jmask(R.jbits[yu * L + x], 1), Th, valid, (uint32_t)n, (uint32_t)g, (uint32_t)i, c3,
-                            R.key0, R.key1, ncalls);
-        ++nwords;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < I8_CMAX; ++q) {
-        const int c = threadIdx.x + q * blockDim.x;
-        if (c < chunks) {
-            const int site = c >> 2, part = c & 3;
-            const int rr = site / L, x = site - rr * L;
-            const int yy = rr - halo;
-            const int y = (y0 - halo + rr + L) % L;
-            if (yy >= 0 && yy < rows && ((x + y) & 1) == colour) {
-                const uint32_t f = (uint32_t)(fm[yy * half + (x >> 1)] >> (16 * part)) & 0xFFFFu;
-                if (f) {
-                    uint4 v = reg[q];
-                    v.x ^= negmask4(f & 15u);
-                    v.y ^= negmask4((f >> 4) & 15u);
-                    v.z ^= negmask4((f >> 8) & 15u);
-                    v.w ^= negmask4((f >> 12) & 15u);
-                    *(uint4 *)(base + (size_t)(y * L + x) * 64 + part * 16) = v;
-                }
-            }
-        }
-    }
-    flush_stats(stats, nwords, ncalls, nwords * lanes);
 }
 
 // Batched path: every (run, pop, block of G replica groups) item of the
@@ -1615,11 +1644,20 @@ hipError_t launch_resample(const LaunchCtx &c)
 // Rows per workgroup of the int8 sweep: the whole lattice when its chunks
 // fit in the registers of 1024 threads, else bands with a halo row on each
 // side.
+// Threads per workgroup of the plain sweep: 256, or 1024 when three rows of
+// a very large lattice would not fit in 256 threads' chunks.
+int int8_threads(int L) { return 3 * L * 4 <= 256 * I8_CMAX ? 256 : 1024; }
+
+// Rows per workgroup: the whole lattice if its chunks fit, else the largest
+// divisor T of L whose T + 2 rows (with halos) fit.
 int int8_tile_rows(int L)
 {
-    if (L * L * 4 <= I8_CMAX * 1024) return L;
-    int T = I8_CMAX * 1024 / (4 * L) - 2;
-    return T < 1 ? 1 : T;
+    const int cap = int8_threads(L) * I8_CMAX;
+    if (L * L * 4 <= cap) return L;
+    int best = 1;
+    for (int T = 1; T < L; ++T)
+        if (L % T == 0 && (T + 2) * L * 4 <= cap) best = T;
+    return best;
 }
 
 hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop, int theta)
@@ -1627,10 +1665,7 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
     const int T = int8_tile_rows(L);
     const int ntiles = (L + T - 1) / T;
     const int nrow = T == L ? L : T + 2;
-    const int chunks = nrow * L * 4;
-    int threads = (chunks + I8_CMAX - 1) / I8_CMAX;
-    threads = ((threads + 63) / 64) * 64;
-    threads = threads < 64 ? 64 : (threads > 1024 ? 1024 : threads);
+    const int threads = int8_threads(L);
     const size_t lds = (size_t)nrow * L * 8 + (size_t)T * (L / 2) * 8;
     for (int s = 0; s < theta; ++s)
         for (int colour = 0; colour < 2; ++colour)

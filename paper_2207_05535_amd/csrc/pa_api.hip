@@ -113,7 +113,7 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     Lo.runinfo = P.take(sizeof(RunInfo) * n_runs);
     Lo.popstate = P.take(sizeof(PopState) * n_runs * MAX_POP);
     Lo.dseed = P.take(sizeof(uint64_t) * n_runs);
-    Lo.stats = P.take(sizeof(uint64_t) * NSTAT);
+    Lo.stats = P.take(STAT_BYTES);
     Lo.queue = P.take(sizeof(uint32_t) * 2);
     Lo.n_items = 0;
     Lo.n_chunk_items = 0;
@@ -336,6 +336,18 @@ pa_status enqueue_step(pa_ctx *c)
     return PA_OK;
 }
 
+pa_status read_stats(pa_ctx *c, uint64_t out[3])
+{
+    std::vector<uint64_t> slots((size_t)NSTAT * STAT_SLOTS);
+    PA_HIP(c, hipMemcpyAsync(slots.data(), c->lc.stats, STAT_BYTES, hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < 3; ++k) {
+        out[k] = 0;
+        for (int q = 0; q < STAT_SLOTS; ++q) out[k] += slots[(size_t)q * NSTAT + k];
+    }
+    return PA_OK;
+}
+
 // A captured step graph holds the launch shapes it was captured with.
 void drop_graph(pa_ctx *c)
 {
@@ -508,7 +520,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
             ok = launch_fill_u32(at<void>(c, o.qh), 0, (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1), s) ==
                  hipSuccess;
     }
-    ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, 2 * NSTAT, s) == hipSuccess;
+    ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, STAT_BYTES / 4, s) == hipSuccess;
     ok = ok && launch_fill_u32(at<void>(c, Lo.queue), 0, 2, s) == hipSuccess;
     ok = ok && launch_fill_u32(at<void>(c, Lo.obs), 0,
                                sizeof(pa_obs) / 4 * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx, s) == hipSuccess;
@@ -804,9 +816,7 @@ pa_status pa_read_stats(pa_ctx *c, uint64_t *host_out)
 {
     if (!c || !host_out) return PA_ERR_ARG;
     if (c->failed) return PA_ERR_DEVICE;
-    PA_HIP(c, hipMemcpyAsync(host_out, c->lc.stats, sizeof(uint64_t) * 3, hipMemcpyDeviceToHost, c->stream));
-    PA_HIP(c, hipStreamSynchronize(c->stream));
-    return PA_OK;
+    return read_stats(c, host_out);
 }
 
 const char *pa_last_error(pa_ctx *c)

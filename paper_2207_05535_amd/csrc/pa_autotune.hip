@@ -173,9 +173,9 @@ struct Tuner {
         rec.resize(per_i * steps + sizeof(uint64_t) * 3);
         PA_HIP(c, hipMemcpyAsync(rec.data(), at<uint8_t>(c, c->lo.obs) + per_i * (i0 + 1), per_i * steps,
                                  hipMemcpyDeviceToHost, c->stream));
-        PA_HIP(c, hipMemcpyAsync(rec.data() + per_i * steps, c->lc.stats, sizeof(uint64_t) * 3,
-                                 hipMemcpyDeviceToHost, c->stream));
-        PA_HIP(c, hipStreamSynchronize(c->stream));
+        uint64_t counts[3];
+        if ((st = read_stats(c, counts)) != PA_OK) return st;
+        std::memcpy(rec.data() + per_i * steps, counts, sizeof(counts));
         const uint64_t h = fnv1a(0xcbf29ce484222325ull, rec.data(), rec.size());
         if (!have_ref) {
             have_ref = true;

@@ -93,7 +93,12 @@ struct PopState {
 
 // Work counters of the sweep kernels (exact, for the ALU roofline):
 // word-site updates (64 replicas of one site), Philox calls, attempted flips.
-enum Stat { ST_WORDS = 0, ST_CALLS = 1, ST_FLIPS = 2, NSTAT = 4 };
+// They are striped over STAT_SLOTS slots of 64 bytes (NSTAT counters each)
+// so that concurrent wavefronts add to different cache lines; a reader sums
+// the slots.
+enum Stat { ST_WORDS = 0, ST_CALLS = 1, ST_FLIPS = 2, NSTAT = 8 };
+constexpr int STAT_SLOTS = 256;
+constexpr size_t STAT_BYTES = sizeof(uint64_t) * NSTAT * STAT_SLOTS;
 
 struct Item {         // one replica group (64 replicas) of one (run, pop)
     int32_t run, pop, group, pad;
