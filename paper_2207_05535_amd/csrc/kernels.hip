@@ -633,7 +633,22 @@ __device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, 
     } else {
         const uint8_t *src = R.spins[pop][S.src] + (size_t)(p >> 6) * N * 64 + (p & 63);
         uint8_t *dst = R.spins[pop][S.cur] + (size_t)G * N * 64 + lane;
-        for (int n = sub; n < N; n += wpg) dst[(size_t)n * 64] = valid ? src[(size_t)n * 64] : (uint8_t)1;
+        // eight sites per step, all loads issued before the stores (the
+        // buffers differ, but the compiler cannot know it)
+        constexpr int U = 8;
+        for (int n0 = sub; n0 < N; n0 += U * wpg) {
+            uint8_t v[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int n = n0 + q * wpg;
+                v[q] = (valid && n < N) ? src[(size_t)n * 64] : (uint8_t)1;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int n = n0 + q * wpg;
+                if (n < N) dst[(size_t)n * 64] = v[q];
+            }
+        }
     }
     if (sub == 0 && valid) {
         R.E[pop][S.cur][c] = R.E[pop][S.src][p];
