@@ -260,7 +260,7 @@ def workload_summary(b, steps, name):
     }
 
 
-def run_serving(trace, arena_bytes, max_slots):
+def run_serving(trace, arena_bytes, max_slots, rate=20.0):
     import paper_2207_05535_amd as pa
     from paper_2207_05535_amd.serve import Server, replay
     srv = Server(arena_bytes, max_slots=max_slots, tuning_cache=TUNING_CACHE)
@@ -271,18 +271,19 @@ def run_serving(trace, arena_bytes, max_slots):
             last[0] = t
             log(f"serving: {done}/{n} requests done at t = {t:.1f} s, {srv.info()['resident']} resident")
 
-    rec, summary = replay(srv, trace, time_scale=1.0, progress=progress)
+    rec, summary = replay(srv, trace, time_scale=20.0 / rate, progress=progress)
     srv.close()
     ok = all(int(r["obs"]["status"].max()) == pa.PA_OK for r in rec)
-    rate = len(trace) / trace[-1][0]
+    emp_rate = len(trace) / (trace[-1][0] * 20.0 / rate)
     mean_flips = summary["flips"] / len(trace)
-    offered = rate * mean_flips / 1e9
+    offered = emp_rate * mean_flips / 1e9
     cap = summary["busy_flips_per_ns"]
     return {
-        "workload": "EA +-J requests at Poisson rate 20/s (500 arrivals, trace seed 0xA110000), "
+        "workload": f"EA +-J requests at Poisson rate {rate:g}/s (500 arrivals, trace seed 0xA110000), "
                     "L uniform in {16,24,32,48,64}, R=50000, beta 0->3 in 201 points, theta=10, "
                     "index-shift overlaps; continuous batching, admission by device-memory footprint",
-        "requests": len(trace), "max_slots": max_slots, "arena_GiB": round(arena_bytes / 2**30, 2),
+        "requests": len(trace), "arrival_rate_per_s": round(emp_rate, 3), "max_slots": max_slots,
+        "arena_GiB": round(arena_bytes / 2**30, 2),
         "p50_latency_s": round(summary["p50_s"], 4), "p99_latency_s": round(summary["p99_s"], 4),
         "mean_latency_s": round(summary["mean_s"], 4), "max_latency_s": round(summary["max_s"], 4),
         "flips_per_ns": round(summary["flips_per_ns"], 3),
@@ -332,6 +333,9 @@ def main():
                     help="launch shapes: committed autotuner cache (search for missing L), "
                          "a fresh search, or the built-in defaults")
     ap.add_argument("--serving-slots", type=int, default=12)
+    ap.add_argument("--serving-rate", type=float, default=20.0,
+                    help="arrival rate of the serving trace in requests/s (the trace's arrival times "
+                         "are scaled from its 20/s draw, so the requests and their order are the same)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -389,7 +393,7 @@ def main():
     if "serving" in only:
         trace = W.serving_trace()
         log(f"serving: {len(trace)} requests")
-        line["serving"] = run_serving(trace, 4 << 30, args.serving_slots)
+        line["serving"] = run_serving(trace, 4 << 30, args.serving_slots, args.serving_rate)
     if not args.no_cpu_baseline and "headline" in only:
         log("cpu baseline: oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(desc)
