@@ -48,8 +48,16 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        if (round == 9) {
+            // Keep the last products whole: otherwise the compiler may split
+            // them into separate 32-bit low and high multiplies, which issue
+            // at a quarter of the rate of one v_mad_u64_u32.  (An empty
+            // statement that only pins the value in a register pair.)
+            asm volatile("" : "+v"(p0));
+            asm volatile("" : "+v"(p1));
+        }
         const uint32_t n0 = bop3<LUT_XOR3>((uint32_t)(p1 >> 32), c1, k0);
         const uint32_t n2 = bop3<LUT_XOR3>((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
