@@ -197,16 +197,23 @@ pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_
  * the same largest-first order).  Results never depend on it. */
 pa_status pa_set_persistent(pa_ctx *ctx, int32_t on);
 
+/* Sparse rounds of the batched sweep: on = 1 pools the sites still
+ * undecided after the lockstep calls into one list per workgroup, so the
+ * compacted rounds run on full wavefronts; on = 0 keeps one list per
+ * wavefront (no workgroup barriers in those rounds).  Results never depend
+ * on it. */
+pa_status pa_set_pooled(pa_ctx *ctx, int32_t on);
+
 /* Current launch shape of the batched sweep for lattice size L (any output
  * pointer may be NULL). */
 pa_status pa_get_tuning(pa_ctx *ctx, int32_t L, int32_t *threads, int32_t *groups_per_wg,
-                        int32_t *dense_calls, int32_t *persistent);
+                        int32_t *dense_calls, int32_t *persistent, int32_t *pooled);
 
 /* Autotuner of the batched sweep (no-op for the plain path).  From the
  * current state (all steps so far measured) it runs `steps` (1..64, clipped
  * to the remaining schedule) real temperature steps of this context for
  * each candidate launch shape, timing the sweep launches with HIP events:
- * first threads x dense_calls x persistent with the current groups per L,
+ * first threads x dense_calls x persistent x pooled with the current groups per L,
  * then groups per workgroup one L at a time (heaviest L first).  Every
  * candidate's records and exact work counters must hash to the starting
  * shape's value; one that differs is rejected (counted in *n_rejected, which

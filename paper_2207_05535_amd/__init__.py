@@ -80,7 +80,8 @@ def lib():
             "pa_restore": [vp, vp, C.c_size_t],
             "pa_set_tuning": [vp, i32, i32, i32, i32],
             "pa_set_persistent": [vp, i32],
-            "pa_get_tuning": [vp, i32, vp, vp, vp, vp],
+            "pa_get_tuning": [vp, i32, vp, vp, vp, vp, vp],
+            "pa_set_pooled": [vp, i32],
             "pa_autotune": [vp, i32, C.c_char_p, vp, vp],
             "pa_read_stats": [vp, vp],
             "pa_destroy": [vp],
@@ -223,10 +224,15 @@ def pa_set_persistent(h, on):
     _chk("pa_set_persistent", lib().pa_set_persistent(h, int(on)), h)
 
 
+def pa_set_pooled(h, on):
+    _chk("pa_set_pooled", lib().pa_set_pooled(h, int(on)), h)
+
+
 def pa_get_tuning(h, L):
-    v = [C.c_int32(0) for _ in range(4)]
+    v = [C.c_int32(0) for _ in range(5)]
     _chk("pa_get_tuning", lib().pa_get_tuning(h, L, *[C.byref(x) for x in v]), h)
-    return dict(threads=v[0].value, groups=v[1].value, dense=v[2].value, persistent=v[3].value)
+    return dict(threads=v[0].value, groups=v[1].value, dense=v[2].value, persistent=v[3].value,
+                pooled=v[4].value)
 
 
 def pa_autotune(h, steps, cache_path=None):
@@ -396,6 +402,9 @@ class Context:
 
     def set_persistent(self, on):
         pa_set_persistent(self.h, on)
+
+    def set_pooled(self, on):
+        pa_set_pooled(self.h, on)
 
     def tuning(self, L):
         return pa_get_tuning(self.h, L)

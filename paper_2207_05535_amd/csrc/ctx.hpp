@@ -73,7 +73,8 @@ inline int n_meas_items_of(const pa_run_desc &d)
 }
 int default_groups(int L);
 // Batched-sweep shape for lattice size L from an autotuner cache file.
-bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *dense, int *persistent);
+bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *dense, int *persistent,
+                       int *pooled);
 
 }  // namespace pa
 
@@ -97,6 +98,7 @@ struct pa_ctx {
     int sweep_threads = 512;
     int sweep_dense = 3;                // Philox calls every site makes in lockstep
     bool sweep_persistent = false;      // persistent grid with a ticket queue
+    bool sweep_pooled = false;          // sparse rounds over one list per workgroup
     std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
     bool any_multinomial = false;
     hipError_t last = hipSuccess;

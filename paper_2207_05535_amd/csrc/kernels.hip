@@ -834,9 +834,155 @@ __global__ void __launch_bounds__(1024) k_sweep_int8(const RunInfo *runs, const 
 //    run on full wavefronts.
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
+// Sparse rounds of one wavefront over its own compacted list of `cnt`
+// undecided sites (entries: lanes of each class, LDS word << 16 | site):
+// call c for every entry, survivors compacted in place; once one pass holds
+// every remaining entry it runs all their remaining calls without writing
+// the list back.
+__device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en, int cnt,
+                                                  int c_first, int N, int group0, const Thresholds &Th, uint32_t i,
+                                                  uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = __lanemask_lt();
+    for (int c = c_first; c < 16 && cnt > 0; ++c) {
+        if (cnt <= 64) {
+            uint64_t und4 = 0, und8 = 0, acc = 0;
+            int addr = 0;
+            uint32_t n = 0, g = 0;
+            if (lane < cnt) {
+                und4 = e4[lane];
+                und8 = e8[lane];
+                const uint32_t pk = en[lane];
+                addr = (int)(pk >> 16);
+                n = pk & 0xFFFFu;
+                g = (uint32_t)(group0 + addr / N);
+            }
+            for (; c < 16; ++c) {
+                const uint64_t live = __ballot((und4 | und8) != 0);
+                if (live == 0) break;
+                wcalls += (uint32_t)__popcll(live);
+                if ((und4 | und8) != 0) draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
+            }
+            if (acc) lat[addr] ^= acc;
+            return;
+        }
+        int wcnt = 0;
+        for (int e0 = 0; e0 < cnt; e0 += 64) {
+            const int e = e0 + lane;
+            uint64_t und4 = 0, und8 = 0, acc = 0;
+            uint32_t pk = 0;
+            wcalls += (uint32_t)min(64, cnt - e0);
+            if (e < cnt) {
+                und4 = e4[e];
+                und8 = e8[e];
+                pk = en[e];
+                const int addr = (int)(pk >> 16);
+                const uint32_t g = (uint32_t)(group0 + addr / N);
+                draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, i, c3, key0, key1);
+                if (acc) lat[addr] ^= acc;
+            }
+            const uint64_t need = __ballot((und4 | und8) != 0);
+            if ((und4 | und8) != 0) {
+                const int slot = wcnt + __popcll(need & lt_mask);
+                e4[slot] = und4;
+                e8[slot] = und8;
+                en[slot] = pk;
+            }
+            wcnt += __popcll(need);
+        }
+        cnt = wcnt;
+    }
+}
+
+// Sparse rounds over one list shared by the workgroup (ctl[h & 1] entries,
+// appended by every wavefront in the dense rounds): each round takes the
+// list in passes of one wavefront-load per wavefront; after a pass the
+// wavefronts' survivor counts (ctl[2 + 16 par + w], alternating buffers)
+// give every survivor its place in the compacted list, which always lies
+// before the entries of later passes, so the list is compacted in place.
+// When at most two wavefront-loads remain, two wavefronts (one if the
+// workgroup has only one) run all their remaining calls without writing the
+// list back.
+__device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en,
+                                                    int *ctl, int h, int c_first, int N, int group0,
+                                                    const Thresholds &Th, uint32_t i, uint32_t c3, uint32_t key0,
+                                                    uint32_t key1, uint32_t &wcalls)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t lt_mask = __lanemask_lt();
+    const int tailw = min(2, nw);   // wavefronts that finish the last entries
+    __syncthreads();   // every wavefront's appends are in the list
+    int cnt = ctl[h & 1];
+    int par = 0;
+    for (int c = c_first; c < 16 && cnt > 0; ++c) {
+        if (cnt <= 64 * tailw) {
+            if (wv < tailw) {
+                const int e = wv * 64 + lane;
+                uint64_t und4 = 0, und8 = 0, acc = 0;
+                int addr = 0;
+                uint32_t n = 0, g = 0;
+                if (e < cnt) {
+                    und4 = e4[e];
+                    und8 = e8[e];
+                    const uint32_t pk = en[e];
+                    addr = (int)(pk >> 16);
+                    n = pk & 0xFFFFu;
+                    g = (uint32_t)(group0 + addr / N);
+                }
+                for (; c < 16; ++c) {
+                    const uint64_t live = __ballot((und4 | und8) != 0);
+                    if (live == 0) break;
+                    wcalls += (uint32_t)__popcll(live);
+                    if ((und4 | und8) != 0)
+                        draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
+                }
+                if (acc) lat[addr] ^= acc;
+            }
+            return;
+        }
+        int out = 0;
+        for (int s0 = 0; s0 < cnt; s0 += 64 * nw) {
+            const int e = s0 + wv * 64 + lane;
+            uint64_t und4 = 0, und8 = 0, acc = 0;
+            uint32_t pk = 0;
+            wcalls += (uint32_t)max(0, min(64, cnt - (s0 + wv * 64)));
+            if (e < cnt) {
+                und4 = e4[e];
+                und8 = e8[e];
+                pk = en[e];
+                const int addr = (int)(pk >> 16);
+                const uint32_t g = (uint32_t)(group0 + addr / N);
+                draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, i, c3, key0, key1);
+                if (acc) lat[addr] ^= acc;
+            }
+            const uint64_t need = __ballot((und4 | und8) != 0);
+            int *cw = ctl + 2 + 16 * par;
+            if (lane == 0) cw[wv] = __popcll(need);
+            __syncthreads();
+            int off = out, tot = 0;
+            for (int w = 0; w < nw; ++w) {
+                const int v = cw[w];
+                off += w < wv ? v : 0;
+                tot += v;
+            }
+            if ((und4 | und8) != 0) {
+                const int slot = off + __popcll(need & lt_mask);
+                e4[slot] = und4;
+                e8[slot] = und8;
+                en[slot] = pk;
+            }
+            out += tot;
+            par ^= 1;
+        }
+        __syncthreads();   // the compacted list is complete
+        cnt = out;
+    }
+}
+
 template <int LT, bool EA>
 __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo &R, const PopState &S,
-                                           uint64_t *lds, int dense, unsigned long long *stats)
+                                           uint64_t *lds, int mode, unsigned long long *stats)
 {
     // Everything the loops need is read into registers before the first
     // barrier: a barrier orders memory, so values left in global memory
@@ -858,6 +1004,9 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     uint64_t *e8 = e4 + units;                            // [units] undecided lanes of class dE = +8
     uint32_t *en = (uint32_t *)(e8 + units);              // [units] (LDS word << 16) | site
     uint8_t *jb = (uint8_t *)(en + units);                // [2][nh] bond signs of each site (spin glass)
+    int *ctl = (int *)(jb + N);                           // pooled list counts [2], pass counts [2][16]
+    const bool pool = (mode >> 8) & 1;
+    const int dense = mode & 0xFF;
     uint64_t *base = (uint64_t *)R.spins[pop][S.cur] + (size_t)group0 * N;
     for (int u = tid; u < G * N; u += T) {
         const int gs = u / N, n = u - gs * N;
@@ -891,10 +1040,13 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const uint64_t lt_mask = __lanemask_lt();
     uint32_t nwords = 0, nflips = 0;
     uint32_t wcalls = 0;   // Philox calls of this wavefront (uniform)
+    if (tid == 0) ctl[0] = ctl[1] = 0;
     for (int s = 0; s < theta; ++s) {
         const uint32_t c3 = c3p | (uint32_t)s;
         for (int colour = 0; colour < 2; ++colour) {
+            const int h = 2 * s + colour;   // half-sweep index: its list count is ctl[h & 1]
             __syncthreads();
+            if (tid == 0) ctl[(h + 1) & 1] = 0;   // the next half-sweep's count; last read before this barrier
             int cnt = 0;
             // dense rounds
             for (int u0 = ub; u0 < ue; u0 += 64) {
@@ -943,68 +1095,26 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                 }
                 if (acc) lat[addr] ^= acc;
                 const uint64_t need = __ballot((und4 | und8) != 0);
+                int base_slot = ub + cnt;
+                if (pool && need) {
+                    int b0 = 0;
+                    if (lane == 0) b0 = atomicAdd(&ctl[h & 1], __popcll(need));
+                    base_slot = __shfl(b0, 0, 64);
+                }
                 if ((und4 | und8) != 0) {
-                    const int slot = ub + cnt + __popcll(need & lt_mask);
+                    const int slot = base_slot + __popcll(need & lt_mask);
                     e4[slot] = und4;
                     e8[slot] = und8;
                     en[slot] = ((uint32_t)addr << 16) | n;
                 }
                 cnt += __popcll(need);
             }
-            // sparse rounds over the compacted list; once one pass holds
-            // every remaining entry, it runs all their remaining calls
-            // without writing the list back
-            for (int c = dense; c < 16 && cnt > 0; ++c) {
-                if (cnt <= 64) {
-                    const int e = lane;
-                    uint64_t und4 = 0, und8 = 0, acc = 0;
-                    int addr = 0;
-                    uint32_t n = 0, g = 0;
-                    if (e < cnt) {
-                        und4 = e4[ub + e];
-                        und8 = e8[ub + e];
-                        const uint32_t pk = en[ub + e];
-                        addr = (int)(pk >> 16);
-                        n = pk & 0xFFFFu;
-                        g = (uint32_t)(group0 + addr / N);
-                    }
-                    for (; c < 16; ++c) {
-                        const uint64_t live = __ballot((und4 | und8) != 0);
-                        if (live == 0) break;
-                        wcalls += (uint32_t)__popcll(live);
-                        if ((und4 | und8) != 0)
-                            draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, (uint32_t)i, c3, key0, key1);
-                    }
-                    if (acc) lat[addr] ^= acc;
-                    break;
-                }
-                int wcnt = 0;
-                for (int e0 = 0; e0 < cnt; e0 += 64) {
-                    const int e = e0 + lane;
-                    uint64_t und4 = 0, und8 = 0, acc = 0;
-                    uint32_t pk = 0;
-                    wcalls += (uint32_t)min(64, cnt - e0);
-                    if (e < cnt) {
-                        und4 = e4[ub + e];
-                        und8 = e8[ub + e];
-                        pk = en[ub + e];
-                        const int addr = (int)(pk >> 16);
-                        const uint32_t g = (uint32_t)(group0 + addr / N);
-                        draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, (uint32_t)i, c3,
-                                  key0, key1);
-                        if (acc) lat[addr] ^= acc;
-                    }
-                    const uint64_t need = __ballot((und4 | und8) != 0);
-                    if ((und4 | und8) != 0) {
-                        const int slot = ub + wcnt + __popcll(need & lt_mask);
-                        e4[slot] = und4;
-                        e8[slot] = und8;
-                        en[slot] = pk;
-                    }
-                    wcnt += __popcll(need);
-                }
-                cnt = wcnt;
-            }
+            if (pool)
+                sweep_sparse_pooled(lat, e4, e8, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
+                                    wcalls);
+            else
+                sweep_sparse_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, dense, N, group0, Th, (uint32_t)i, c3, key0,
+                                  key1, wcalls);
         }
     }
     __syncthreads();
@@ -1695,7 +1805,7 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
 size_t msc_lds_bytes(int N, int groups)
 {
     const size_t units = (size_t)groups * (N / 2);
-    return (size_t)groups * N * 8 + units * 20 + (size_t)N;
+    return (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
 }
 
 hipError_t prepare_msc_lds(size_t bytes)
@@ -1710,7 +1820,7 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
     const bool persistent = c.sweep_grid > 0 && c.sweep_grid < c.n_sweep_items;
     const int grid = persistent ? c.sweep_grid : c.n_sweep_items;
     k_sweep_msc<<<grid, c.sweep_threads, c.sweep_lds, c.stream>>>(c.sweep_items, c.n_sweep_items, c.runs, c.st,
-                                                                 c.sweep_dense, c.stats,
+                                                                 c.sweep_dense | (c.sweep_pooled << 8), c.stats,
                                                                  persistent ? c.sweep_queue : nullptr);
     return hipGetLastError();
 }

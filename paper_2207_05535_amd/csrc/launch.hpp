@@ -23,6 +23,7 @@ struct LaunchCtx {
     const SweepItem *sweep_items;  // device [n_sweep_items]
     int n_sweep_items, sweep_threads, sweep_dense;
     int sweep_grid;                // > 0: persistent grid of this many workgroups
+    int sweep_pooled;              // 1: sparse rounds over one list per workgroup
     unsigned int *sweep_queue;     // device [2] ticket counters of the persistent grid
     size_t sweep_lds;
     hipStream_t stream;

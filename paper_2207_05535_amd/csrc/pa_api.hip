@@ -310,6 +310,7 @@ pa_status upload_sweep_plan(pa_ctx *c)
     c->lc.sweep_dense = c->sweep_dense;
     c->lc.sweep_lds = lds;
     c->lc.sweep_grid = 0;
+    c->lc.sweep_pooled = c->sweep_pooled ? 1 : 0;
     if (c->sweep_persistent) {
         const int resident = sweep_msc_resident(c->sweep_threads, lds);
         if (resident <= 0) return dev_fail(c);
@@ -801,14 +802,26 @@ pa_status pa_set_persistent(pa_ctx *c, int32_t on)
     return upload_sweep_plan(c);
 }
 
+pa_status pa_set_pooled(pa_ctx *c, int32_t on)
+{
+    if (!c || (on != 0 && on != 1)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED) return PA_ERR_STATE;
+    c->sweep_pooled = on != 0;
+    if (c->repr != PA_MSC64) return PA_OK;
+    drop_graph(c);
+    return upload_sweep_plan(c);
+}
+
 pa_status pa_get_tuning(pa_ctx *c, int32_t L, int32_t *threads, int32_t *groups_per_wg, int32_t *dense_calls,
-                        int32_t *persistent)
+                        int32_t *persistent, int32_t *pooled)
 {
     if (!c || L < 4 || (L & 1)) return PA_ERR_ARG;
     if (threads) *threads = c->sweep_threads;
     if (groups_per_wg) *groups_per_wg = groups_for(c, L);
     if (dense_calls) *dense_calls = c->sweep_dense;
     if (persistent) *persistent = c->sweep_persistent ? 1 : 0;
+    if (pooled) *pooled = c->sweep_pooled ? 1 : 0;
     return PA_OK;
 }
 

@@ -30,13 +30,13 @@ using namespace pa;
 namespace {
 
 struct Shape {
-    int threads, dense, persistent;
+    int threads, dense, persistent, pooled;
     std::map<int, int> groups;   // L -> groups per workgroup
 };
 
 struct CacheEntry {
     std::string arch, repr;
-    int L, threads, groups, dense, persistent;
+    int L, threads, groups, dense, persistent, pooled;
     double sweep_us;
 };
 
@@ -60,10 +60,13 @@ std::vector<CacheEntry> read_cache(const char *path)
         char arch[64] = {0}, repr[16] = {0};
         CacheEntry e;
         e.sweep_us = 0.0;
+        e.pooled = 0;
         const int n = std::sscanf(line,
                                   " {\"arch\": \"%63[^\"]\", \"repr\": \"%15[^\"]\", \"L\": %d, \"threads\": %d, "
-                                  "\"groups\": %d, \"dense\": %d, \"persistent\": %d, \"sweep_us\": %lf",
-                                  arch, repr, &e.L, &e.threads, &e.groups, &e.dense, &e.persistent, &e.sweep_us);
+                                  "\"groups\": %d, \"dense\": %d, \"persistent\": %d, \"pooled\": %d, "
+                                  "\"sweep_us\": %lf",
+                                  arch, repr, &e.L, &e.threads, &e.groups, &e.dense, &e.persistent, &e.pooled,
+                                  &e.sweep_us);
         if (n >= 7) {
             e.arch = arch;
             e.repr = repr;
@@ -84,9 +87,9 @@ bool write_cache(const char *path, const std::vector<CacheEntry> &entries)
         const CacheEntry &e = entries[k];
         std::fprintf(f,
                      "  {\"arch\": \"%s\", \"repr\": \"%s\", \"L\": %d, \"threads\": %d, \"groups\": %d, "
-                     "\"dense\": %d, \"persistent\": %d, \"sweep_us\": %.3f}%s\n",
-                     e.arch.c_str(), e.repr.c_str(), e.L, e.threads, e.groups, e.dense, e.persistent, e.sweep_us,
-                     k + 1 < entries.size() ? "," : "");
+                     "\"dense\": %d, \"persistent\": %d, \"pooled\": %d, \"sweep_us\": %.3f}%s\n",
+                     e.arch.c_str(), e.repr.c_str(), e.L, e.threads, e.groups, e.dense, e.persistent, e.pooled,
+                     e.sweep_us, k + 1 < entries.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
     const bool ok = std::fclose(f) == 0;
@@ -107,11 +110,12 @@ uint64_t fnv1a(uint64_t h, const void *p, size_t n)
 bool apply_shape(pa_ctx *c, const Shape &s)
 {
     const int t0 = c->sweep_threads, d0 = c->sweep_dense;
-    const bool p0 = c->sweep_persistent;
+    const bool p0 = c->sweep_persistent, q0 = c->sweep_pooled;
     const auto g0 = c->groups_per_wg;
     c->sweep_threads = s.threads;
     c->sweep_dense = s.dense;
     c->sweep_persistent = s.persistent != 0;
+    c->sweep_pooled = s.pooled != 0;
     for (const auto &kv : s.groups) c->groups_per_wg[kv.first] = kv.second;
     std::vector<SweepItem> probe;
     size_t lds = 0;
@@ -119,6 +123,7 @@ bool apply_shape(pa_ctx *c, const Shape &s)
         c->sweep_threads = t0;
         c->sweep_dense = d0;
         c->sweep_persistent = p0;
+        c->sweep_pooled = q0;
         c->groups_per_wg = g0;
         return false;
     }
@@ -193,6 +198,7 @@ Shape current_shape(const pa_ctx *c, const std::vector<int> &Ls)
     s.threads = c->sweep_threads;
     s.dense = c->sweep_dense;
     s.persistent = c->sweep_persistent ? 1 : 0;
+    s.pooled = c->sweep_pooled ? 1 : 0;
     for (int L : Ls) s.groups[L] = groups_for(c, L);
     return s;
 }
@@ -201,7 +207,8 @@ Shape current_shape(const pa_ctx *c, const std::vector<int> &Ls)
 
 namespace pa {
 
-bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *dense, int *persistent)
+bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *dense, int *persistent,
+                       int *pooled)
 {
     const std::string arch = device_arch();
     for (const auto &e : read_cache(path))
@@ -210,6 +217,7 @@ bool tuning_from_cache(const char *path, int L, int *threads, int *groups, int *
             *groups = e.groups;
             *dense = e.dense;
             *persistent = e.persistent;
+            *pooled = e.pooled;
             return true;
         }
     return false;
@@ -250,6 +258,7 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
                         s.threads = e.threads;
                         s.dense = e.dense;
                         s.persistent = e.persistent;
+                        s.pooled = e.pooled;
                     }
                     break;
                 }
@@ -301,13 +310,15 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
     // context-wide knobs with the current groups per L
     for (int threads : {256, 512, 1024})
         for (int dense : {2, 3, 4})
-            for (int pers : {0, 1}) {
-                Shape s = best;
-                s.threads = threads;
-                s.dense = dense;
-                s.persistent = pers;
-                if ((st = consider(s)) != PA_OK) return st;
-            }
+            for (int pers : {0, 1})
+                for (int pool : {0, 1}) {
+                    Shape s = best;
+                    s.threads = threads;
+                    s.dense = dense;
+                    s.persistent = pers;
+                    s.pooled = pool;
+                    if ((st = consider(s)) != PA_OK) return st;
+                }
     // groups per workgroup, one L at a time
     for (int L : Ls) {
         int cap = 1;
@@ -334,7 +345,7 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
 
     if (cache_path) {
         for (int L : Ls) {
-            CacheEntry e{arch, "msc", L, best.threads, best.groups[L], best.dense, best.persistent,
+            CacheEntry e{arch, "msc", L, best.threads, best.groups[L], best.dense, best.persistent, best.pooled,
                          1e3 * best_ms / steps};
             bool replaced = false;
             for (auto &x : cache)

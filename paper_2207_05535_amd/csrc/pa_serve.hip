@@ -164,7 +164,7 @@ struct pa_server {
     std::deque<Upload> pending;
     int lds_limit = 65536;
     int threads = 512, dense = 3;
-    bool persistent = false;
+    bool persistent = false, pooled = false;
     std::map<int, int> groups;
     bool failed = false;
     hipError_t last = hipSuccess;
@@ -309,6 +309,7 @@ pa_status rebuild(pa_server *s)
     c.sweep_dense = s->dense;
     c.sweep_lds = lds;
     c.sweep_grid = 0;
+    c.sweep_pooled = s->pooled ? 1 : 0;
     if (s->repr == PA_MSC64 && !sweep.empty()) {
         if (prepare_msc_lds(lds) != hipSuccess) return sfail(s);
         if (s->persistent) {
@@ -378,14 +379,15 @@ pa_status pa_server_create(pa_repr repr, void *dev_arena, size_t arena_bytes, in
         return PA_ERR_DEVICE;
     }
     if (tuning_cache) {
-        int th = 0, g = 0, dn = 0, pe = 0;
+        int th = 0, g = 0, dn = 0, pe = 0, po = 0;
         for (int L = 4; L <= 128; L += 2)
-            if (tuning_from_cache(tuning_cache, L, &th, &g, &dn, &pe)) {
+            if (tuning_from_cache(tuning_cache, L, &th, &g, &dn, &pe, &po)) {
                 s->groups[L] = g;
                 if (L == 64 || s->groups.size() == 1) {   // shared knobs: from L = 64 when present
                     s->threads = th;
                     s->dense = dn;
                     s->persistent = pe != 0;
+                    s->pooled = po != 0;
                 }
             }
     }

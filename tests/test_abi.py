@@ -131,4 +131,5 @@ def test_tuning_calls_validate_before_device():
     lib = pa.lib()
     assert lib.pa_autotune(None, 3, None, None, None) == pa.PA_ERR_ARG
     assert lib.pa_set_persistent(None, 1) == pa.PA_ERR_ARG
-    assert lib.pa_get_tuning(None, 16, None, None, None, None) == pa.PA_ERR_ARG
+    assert lib.pa_get_tuning(None, 16, None, None, None, None, None) == pa.PA_ERR_ARG
+    assert lib.pa_set_pooled(None, 1) == pa.PA_ERR_ARG

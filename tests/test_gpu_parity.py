@@ -351,14 +351,18 @@ def test_full_size_batched_uneven_sampled_runs(repr_):
 # ------------------------------------------------------------- tuning shapes
 
 
-@pytest.mark.parametrize("threads,groups,dense", [(64, 1, 0), (256, 2, 3), (1024, 1, 16), (128, 3, 1),
-                                                  (512, 5, 2)])
-def test_tuning_shapes_do_not_change_results(threads, groups, dense):
+@pytest.mark.parametrize("threads,groups,dense,pooled", [(64, 1, 0, 0), (256, 2, 3, 0), (1024, 1, 16, 0),
+                                                         (128, 3, 1, 0), (512, 5, 2, 0), (64, 1, 0, 1),
+                                                         (256, 2, 3, 1), (1024, 2, 1, 1), (512, 1, 4, 1)])
+def test_tuning_shapes_do_not_change_results(threads, groups, dense, pooled):
     """Every launch shape of the batched sweep (threads per workgroup, replica
-    groups per workgroup, lockstep calls before compaction) gives the
-    oracle's results bit for bit."""
+    groups per workgroup, lockstep calls before compaction, per-wavefront or
+    pooled lists for the compacted rounds) gives the oracle's results bit for
+    bit."""
+    say(f"tuning shape threads={threads} groups={groups} dense={dense} pooled={pooled}")
     runs = batch_runs()
     ctx = pa.Context(runs, "msc")
+    ctx.set_pooled(pooled)
     for d in runs:
         ctx.set_tuning(d["L"], threads, groups, dense)
     ctx.run(1, 16)

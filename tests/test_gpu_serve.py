@@ -162,8 +162,8 @@ def test_autotune_keeps_results_and_uses_cache(tmp_path):
     ctx2.close()
 
 
-def test_persistent_grid_same_results():
-    say("persistent sweep grid invariance")
+def test_persistent_grid_and_pooled_lists_same_results():
+    say("persistent sweep grid and pooled list invariance")
     runs = W.batched_fm_uneven(n_per_L=5, Ls=(8, 16, 24, 32), R=500, K=8)
     a = pa.Context(runs, "msc")
     a.run(1, 8)
@@ -172,6 +172,8 @@ def test_persistent_grid_same_results():
     assert b.tuning(16)["persistent"] == 1
     b.run(1, 4)
     b.set_persistent(0)
+    b.set_pooled(1)
+    assert b.tuning(16)["pooled"] == 1
     b.run(4, 6)
     b.set_persistent(1)
     for i in range(6, 8):
