@@ -400,11 +400,11 @@ __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items,
     const uint64_t *B = R.base64[it.pop];
     const uint32_t c3 = (TAG_MN << 28) | ((uint32_t)it.pop << 24);
     int32_t *r = R.r[it.pop];
+    __shared__ uint64_t sP[CH];   // one chunk's prefix, or the chunk bases
+    __shared__ int32_t sr[CH];
     if (R.R <= CH && Rp <= CH) {
         // the whole run in this workgroup: prefix and counts in LDS, the
         // counts are written out once (no global atomics)
-        __shared__ uint64_t sP[CH];
-        __shared__ int32_t sr[CH];
         for (int j = threadIdx.x; j < Rp; j += CH_THREADS) {
             sP[j] = P[j];     // one chunk: base64[0] = 0
             sr[j] = 0;
@@ -428,20 +428,35 @@ __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items,
         for (int j = threadIdx.x; j < Rp; j += CH_THREADS) r[j] = sr[j];
         return;
     }
+    // largest j with P_j <= t in two levels: the last chunk whose base is
+    // <= t (chunk bases staged in LDS), then inside that chunk
+    const int nch = (Rp + CH - 1) / CH;
+    uint64_t *sB = sP;
+    const bool staged = nch <= CH;
+    if (staged)
+        for (int k = threadIdx.x; k < nch; k += CH_THREADS) sB[k] = B[k];
+    __syncthreads();
     for (int q = 0; q < CH_PER; ++q) {
         const int d = d0 + threadIdx.x + q * CH_THREADS;
         if (d >= R.R) break;
         const u32x4 o = philox10((uint32_t)d, 0, (uint32_t)S.i, c3, R.key0, R.key1);
         const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
         const uint64_t t = umul64hi(v, SX);
-        int lo = 0, hi = Rp - 1;      // largest j with P_j <= t
+        int klo = 0, khi = nch - 1;
+        while (klo < khi) {
+            const int mid = klo + ((khi - klo + 1) >> 1);
+            if ((staged ? sB[mid] : B[mid]) <= t) klo = mid;
+            else khi = mid - 1;
+        }
+        const uint64_t tl = t - (staged ? sB[klo] : B[klo]);
+        const uint64_t *Pk = P + (size_t)klo * CH;
+        int lo = 0, hi = min(CH, Rp - klo * CH) - 1;
         while (lo < hi) {
             const int mid = lo + ((hi - lo + 1) >> 1);
-            const uint64_t pm = B[mid / CH] + P[mid];
-            if (pm <= t) lo = mid;
+            if (Pk[mid] <= tl) lo = mid;
             else hi = mid - 1;
         }
-        atomicAdd(&r[lo], 1);
+        atomicAdd(&r[klo * CH + lo], 1);
     }
 }
 
@@ -564,16 +579,31 @@ __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, c
         }
         return;
     }
+    // largest j with C_j <= c in two levels, as for the multinomial draws
+    const int nch = (Rp + CH - 1) / CH;
+    __shared__ int32_t sB[CH];
+    const bool staged = nch <= CH;
+    if (staged)
+        for (int k = threadIdx.x; k < nch; k += CH_THREADS) sB[k] = B[k];
+    __syncthreads();
     for (int q = 0; q < CH_PER; ++q) {
         const int c = c0 + threadIdx.x + q * CH_THREADS;
         if (c >= Rc) break;
-        int lo = 0, hi = Rp - 1;
+        int klo = 0, khi = nch - 1;
+        while (klo < khi) {
+            const int mid = klo + ((khi - klo + 1) >> 1);
+            if ((staged ? sB[mid] : B[mid]) <= c) klo = mid;
+            else khi = mid - 1;
+        }
+        const int cl = c - (staged ? sB[klo] : B[klo]);
+        const int32_t *Ck = C + (size_t)klo * CH;
+        int lo = 0, hi = min(CH, Rp - klo * CH) - 1;
         while (lo < hi) {
             const int mid = lo + ((hi - lo + 1) >> 1);
-            if (B[mid / CH] + C[mid] <= c) lo = mid;
+            if (Ck[mid] <= cl) lo = mid;
             else hi = mid - 1;
         }
-        par[c] = lo;
+        par[c] = klo * CH + lo;
     }
 }
 
@@ -603,18 +633,33 @@ __device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, 
         const int g_lo = __shfl(p, 0, 64) >> 6;
         const int g_hi = __shfl(p, 63, 64) >> 6;
         if (g_hi - g_lo < COPY_MAX_SRC) {
-            for (int n0 = sub * 64; n0 < N; n0 += wpg * 64) {
-                const int n = n0 + lane;
-                uint64_t row = 0;
-                for (int gs = g_lo; gs <= g_hi; ++gs) {
-                    const uint64_t x = n < N ? src[(size_t)gs * N + n] : 0ull;
-                    const uint64_t xt = transpose64(x);
-                    const uint64_t v = __shfl(xt, p & 63, 64);
-                    if ((p >> 6) == gs) row = v;
+            const int nsrc = g_hi - g_lo + 1;   // uniform over the wavefront
+            // two 64-site blocks per step: their source loads are issued together
+            for (int n0 = sub * 64; n0 < N; n0 += 2 * wpg * 64) {
+                const int na = n0 + lane, nb = n0 + wpg * 64 + lane;
+                uint64_t xa[COPY_MAX_SRC], xb[COPY_MAX_SRC];
+#pragma unroll
+                for (int q = 0; q < COPY_MAX_SRC; ++q) {
+                    const size_t gofs = (size_t)(g_lo + q) * N;
+                    xa[q] = (q < nsrc && na < N) ? src[gofs + na] : 0ull;
+                    xb[q] = (q < nsrc && nb < N) ? src[gofs + nb] : 0ull;
                 }
-                if (!valid) row = 0;
-                const uint64_t out = transpose64(row);
-                if (n < N) dst[n] = out;
+                uint64_t rowa = 0, rowb = 0;
+#pragma unroll
+                for (int q = 0; q < COPY_MAX_SRC; ++q) {
+                    if (q < nsrc) {
+                        const uint64_t va = __shfl(transpose64(xa[q]), p & 63, 64);
+                        const uint64_t vb = __shfl(transpose64(xb[q]), p & 63, 64);
+                        if ((p >> 6) == g_lo + q) {
+                            rowa = va;
+                            rowb = vb;
+                        }
+                    }
+                }
+                if (!valid) rowa = rowb = 0;
+                const uint64_t outa = transpose64(rowa), outb = transpose64(rowb);
+                if (na < N) dst[na] = outa;
+                if (nb < N) dst[nb] = outb;
             }
         } else {
             const uint64_t *ps = src + (size_t)(p >> 6) * N;
@@ -1252,51 +1297,50 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     }
     uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
     uint32_t totU = 0, totD = 0, totH = 0, totK = 0;
-    int since = 0;
     // every lane of the wavefront runs the same iterations (flushes are
-    // wave-wide); lanes past the last site only skip the work
-    for (int base = 64 * sub; base < N; base += 64 * wpg) {
-        const int n = base + lane;
-        if (live && n < N) {
-            const int y = n / L, x = n - y * L;
-            const int nr = y * L + (x + 1 == L ? 0 : x + 1);
-            const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
-            const uint8_t jn = R.jbits[n];
-            const uint64_t w = load_word<REPR>(buf, g, n, N);
-            const uint64_t wr = load_word<REPR>(buf, g, nr, N);
-            const uint64_t wd = load_word<REPR>(buf, g, nd, N);
-            const uint64_t br = w ^ wr, bd = w ^ wd;
-            vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
-            vinc(cD, w);
-            if (mode) {
-                uint64_t q, qr, qd;
-                if (mode == 1 && sh) {
-                    const bool two = pg + 1 < pgroups;
-                    q = (load_word<REPR>(buf, pg, n, N) >> sh) |
-                        (two ? load_word<REPR>(buf, pg + 1, n, N) << (64 - sh) : 0ull);
-                    qr = (load_word<REPR>(buf, pg, nr, N) >> sh) |
-                         (two ? load_word<REPR>(buf, pg + 1, nr, N) << (64 - sh) : 0ull);
-                    qd = (load_word<REPR>(buf, pg, nd, N) >> sh) |
-                         (two ? load_word<REPR>(buf, pg + 1, nd, N) << (64 - sh) : 0ull);
-                } else {
-                    q = load_word<REPR>(pbuf, pg, n, N);
-                    qr = load_word<REPR>(pbuf, pg, nr, N);
-                    qd = load_word<REPR>(pbuf, pg, nd, N);
+    // wave-wide); lanes past the last site only skip the work.  Counters are
+    // flushed after every 16 sites per lane (at most 2 per site: 32 < 2^VB);
+    // mode is uniform over the wavefront, so are the overlap flushes.
+    for (int b0 = 64 * sub; b0 < N; b0 += 16 * 64 * wpg) {
+#pragma unroll 4
+        for (int t = 0; t < 16; ++t) {
+            const int n = b0 + t * 64 * wpg + lane;
+            if (live && n < N) {
+                const int y = n / L, x = n - y * L;
+                const int nr = y * L + (x + 1 == L ? 0 : x + 1);
+                const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
+                const uint8_t jn = R.jbits[n];
+                const uint64_t w = load_word<REPR>(buf, g, n, N);
+                const uint64_t wr = load_word<REPR>(buf, g, nr, N);
+                const uint64_t wd = load_word<REPR>(buf, g, nd, N);
+                const uint64_t br = w ^ wr, bd = w ^ wd;
+                vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
+                vinc(cD, w);
+                if (mode) {
+                    uint64_t q, qr, qd;
+                    if (mode == 1 && sh) {
+                        const bool two = pg + 1 < pgroups;
+                        q = (load_word<REPR>(buf, pg, n, N) >> sh) |
+                            (two ? load_word<REPR>(buf, pg + 1, n, N) << (64 - sh) : 0ull);
+                        qr = (load_word<REPR>(buf, pg, nr, N) >> sh) |
+                             (two ? load_word<REPR>(buf, pg + 1, nr, N) << (64 - sh) : 0ull);
+                        qd = (load_word<REPR>(buf, pg, nd, N) >> sh) |
+                             (two ? load_word<REPR>(buf, pg + 1, nd, N) << (64 - sh) : 0ull);
+                    } else {
+                        q = load_word<REPR>(pbuf, pg, n, N);
+                        qr = load_word<REPR>(pbuf, pg, nr, N);
+                        qd = load_word<REPR>(pbuf, pg, nd, N);
+                    }
+                    vinc(cH, w ^ q);
+                    vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
                 }
-                vinc(cH, w ^ q);
-                vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
             }
         }
-        // flush every 16 sites per lane (at most 2 per site: 32 < 2^VB);
-        // mode is uniform over the wavefront, so are the overlap flushes
-        if (++since == 16 || base + 64 * wpg >= N) {
-            since = 0;
-            totU += vflush(cU);
-            totD += vflush(cD);
-            if (mode) {
-                totH += vflush(cH);
-                totK += vflush(cK);
-            }
+        totU += vflush(cU);
+        totD += vflush(cD);
+        if (mode) {
+            totH += vflush(cH);
+            totK += vflush(cK);
         }
     }
     if (wpg > 1) {
