@@ -63,23 +63,64 @@ __device__ __forceinline__ int wave_min(int v)
 
 __device__ __forceinline__ bool pop_active(const PopState &S) { return S.moved && S.status == PA_OK; }
 
+// Value of lane (lane ^ J) for a 32-bit register, with the cheapest gfx950
+// cross-lane form for each distance: permlane swaps for 32 and 16, an LDS
+// swizzle for 8 and 4, DPP quad permutes for 2 and 1.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
+{
+    if constexpr (J == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    } else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else if constexpr (J == 8 || J == 4) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1f);
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    } else {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    }
+}
+
+// One block-swap stage of the transpose for J < 32 with mask m (the bits a
+// lane without bit J keeps in each 32-bit half).  A lane keeps half of its
+// bits and needs the other half from lane ^ J; the half its partner needs
+// is packed into one 32-bit word, so each stage is one exchange.
+template <int J>
+__device__ __forceinline__ void transpose_stage(uint32_t &lo, uint32_t &hi, uint32_t m)
+{
+    const bool up = threadIdx.x & J;
+    const uint32_t send = up ? ((lo & m) | ((hi & m) << J)) : (((lo & ~m) >> J) | (hi & ~m));
+    const uint32_t r = lane_xor<J>(send);
+    if (up) {
+        lo = (lo & ~m) | (r & m);
+        hi = (hi & ~m) | ((r & ~m) >> J);
+    } else {
+        lo = (lo & m) | ((r & m) << J);
+        hi = (hi & m) | (r & ~m);
+    }
+}
+
 // 64 x 64 bit transpose across a wavefront: lane r holds row r (bit c =
-// element (r, c)); on return lane r holds column r.  Six block-swap stages;
-// at stage j a lane exchanges the half-blocks whose column bit j differs
-// from its own row bit j with lane r ^ j.
+// element (r, c)); on return lane r holds column r.  Six block-swap stages
+// (distances 32, 16, 8, 4, 2, 1), one 32-bit exchange each.
 __device__ __forceinline__ uint64_t transpose64(uint64_t x)
 {
-    const int lane = threadIdx.x & 63;
-    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int j = 32 >> st;
-        const uint64_t m = masks[st];
-        const uint64_t y = __shfl_xor(x, j, 64);
-        x = (lane & j) ? ((x & ~m) | ((y & ~m) >> j)) : ((x & m) | ((y & m) << j));
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {
+        const bool up = threadIdx.x & 32;
+        const uint32_t r = lane_xor<32>(up ? lo : hi);
+        if (up) lo = r;
+        else hi = r;
     }
-    return x;
+    transpose_stage<16>(lo, hi, 0x0000FFFFu);
+    transpose_stage<8>(lo, hi, 0x00FF00FFu);
+    transpose_stage<4>(lo, hi, 0x0F0F0F0Fu);
+    transpose_stage<2>(lo, hi, 0x33333333u);
+    transpose_stage<1>(lo, hi, 0x55555555u);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // Bit-sliced (vertical) counters: plane k holds bit k of 64 per-lane counts.
@@ -111,17 +152,21 @@ __device__ __forceinline__ void vinc2(uint64_t (&p)[VB], uint64_t a, uint64_t b)
 }
 
 // Per-lane counts summed over the wavefront: on return lane b holds the
-// total over all lanes of bit b's count, and the planes are cleared.
-__device__ __forceinline__ uint32_t vflush(uint64_t (&p)[VB])
+// total over all lanes of bit b's count, and the planes are cleared.  Only
+// the lowest `used` planes (wavefront-uniform) can be non-zero.
+__device__ __forceinline__ uint32_t vflush(uint64_t (&p)[VB], int used = VB)
 {
     uint32_t total = 0;
 #pragma unroll
     for (int k = 0; k < VB; ++k) {
-        total += (uint32_t)__popcll(transpose64(p[k])) << k;
+        if (k < used) total += (uint32_t)__popcll(transpose64(p[k])) << k;
         p[k] = 0;
     }
     return total;
 }
+
+// Bit planes that hold counts up to c.
+__device__ __forceinline__ int planes_for(int c) { return 32 - __clz(c); }
 
 // Exclusive scan of one value per thread across a workgroup of BS threads
 // (BS a multiple of 64); returns the exclusive prefix, *total the sum.
@@ -1302,6 +1347,8 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     // flushed after every 16 sites per lane (at most 2 per site: 32 < 2^VB);
     // mode is uniform over the wavefront, so are the overlap flushes.
     for (int b0 = 64 * sub; b0 < N; b0 += 16 * 64 * wpg) {
+        // sites per lane in this block of 16 (uniform): bounds the counts
+        const int tsites = min(16, (N - b0 + 64 * wpg - 1) / (64 * wpg));
 #pragma unroll 4
         for (int t = 0; t < 16; ++t) {
             const int n = b0 + t * 64 * wpg + lane;
@@ -1336,11 +1383,12 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
                 }
             }
         }
-        totU += vflush(cU);
-        totD += vflush(cD);
+        const int p1 = planes_for(tsites), p2 = planes_for(2 * tsites);
+        totU += vflush(cU, p2);
+        totD += vflush(cD, p1);
         if (mode) {
-            totH += vflush(cH);
-            totK += vflush(cK);
+            totH += vflush(cH, p1);
+            totK += vflush(cK, p2);
         }
     }
     if (wpg > 1) {
