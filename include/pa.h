@@ -64,6 +64,13 @@ typedef enum { PA_INT8 = 0, PA_MSC64 = 1 } pa_repr;
 enum { PA_Q_NONE = 0, PA_Q_INDEX_SHIFT = 1, PA_Q_TWO_POP = 2 };
 /* Free-energy weights, Eq. (appropriateWeight) (full) and Eq. (simpleWeight). */
 typedef enum { PA_W_FULL = 0, PA_W_SIMPLE = 1 } pa_weight_kind;
+/* Flag OR-ed into a pa_weight_kind argument: overlap averages (W[|q|],
+ * W[q^2], W[q_l] and the weighted P(q)) leave out, at each temperature, runs
+ * in which a family holds more than R_i / 2 replicas (in either population
+ * for PA_Q_TWO_POP), as in the comparison of Sec. III D (Table I); their
+ * weights are renormalised over the remaining runs.  The other averages and
+ * -beta W[F] are unchanged. */
+enum { PA_W_EXCLUDE_LARGE_FAMILY = 2 };
 
 /* One PA run.  Random numbers are drawn from Philox4x32-10 keyed by `seed`
  * (initial spins, sweeps, resampling) and `disorder_seed` (couplings). */
@@ -107,6 +114,18 @@ typedef struct {
     double W_absq, W_q2, W_ql, minus_beta_WF, var_w, var_w_pred;
     int32_t n_included;     /* runs with status PA_OK at this temperature */
 } pa_wavg;
+
+/* Family statistics of one (run, population, temperature i), from its
+ * record: the mean square family size rho_t = R_i sum_k n_k^2 with n_k the
+ * fraction of replicas in family k (Eq. (rho_t)), i.e. sum_k c_k^2 / R_i;
+ * the largest family; whether it exceeds R_i / 2; and whether the run is
+ * left out of overlap averages at this temperature under
+ * PA_W_EXCLUDE_LARGE_FAMILY (a large family in either population of a
+ * two-population run, or a status other than PA_OK). */
+typedef struct {
+    double rho_t;
+    int32_t R_i, famMax, large, excluded;
+} pa_famstat;
 
 /* Bytes of device workspace needed by pa_create for these runs.
  * runs: host [n_runs]; bytes: host out.  PA_ERR_ARG on an invalid descriptor. */
@@ -152,9 +171,24 @@ pa_status pa_run(pa_ctx *ctx, int32_t i_begin, int32_t i_end);
  * the same L and schedule).  pop selects the population whose records are
  * weighted.  host_out: host [n_runs/M][K].  Computed in FP64 on the device
  * from the records of temperatures 0..i of the steps done so far; records of
- * temperatures not reached yet are reported with n_included = 0. */
-pa_status pa_weighted_average(pa_ctx *ctx, int32_t M, pa_weight_kind kind, int32_t pop,
+ * temperatures not reached yet are reported with n_included = 0.  kind:
+ * PA_W_FULL or PA_W_SIMPLE, optionally | PA_W_EXCLUDE_LARGE_FAMILY. */
+pa_status pa_weighted_average(pa_ctx *ctx, int32_t M, int32_t kind, int32_t pop,
                               pa_wavg *host_out);
+
+/* Sec. IV C, Eq. (W_conf_q): the weighted overlap distribution
+ * W[P(q)] = sum_m w^(m) P^(m)(q) of each group of M consecutive runs (every
+ * run of a group needs qhist = 1, the same L and schedule), with P^(m) the
+ * empirical distribution of run m's overlap pairs (its histogram divided by
+ * its number of pairs) and the free-energy weights of `kind` (PA_W_FULL or
+ * PA_W_SIMPLE, optionally | PA_W_EXCLUDE_LARGE_FAMILY).  Bin d is Hamming
+ * distance d, q = 1 - 2d/N.  host_out: host [n_runs/M][K][N+1]; temperatures
+ * not reached yet, or with no included run, are NaN.  FP64 on the device. */
+pa_status pa_weighted_qhist(pa_ctx *ctx, int32_t M, int32_t kind, int32_t pop, double *host_out);
+
+/* Family statistics of every run of population pop at every temperature
+ * reached (pa_famstat above).  host_out: host [n_runs][K]. */
+pa_status pa_family_stats(pa_ctx *ctx, int32_t pop, pa_famstat *host_out);
 
 /* All records so far.  host_out: host [n_runs][n_pop][K]. */
 pa_status pa_read_obs(pa_ctx *ctx, pa_obs *host_out);

@@ -77,7 +77,10 @@ def lib():
         L.or_reweight_X.restype = C.c_uint64
         L.or_sweep_draw.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_sweep_draw.restype = C.c_uint32
-        L.or_weighted_average.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]
+        L.or_weighted_average.argtypes = [vp, vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]
+        L.or_weighted_qhist.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]
+        L.or_family_stats.argtypes = [vp, vp, vp, C.c_int, vp]
+        L.or_get_rho.argtypes = [vp, vp]
         L.or_many_runs.argtypes = [C.POINTER(_Desc), C.c_int, vp, vp, vp]
         L.or_many_runs_obs.argtypes = [C.POINTER(_Desc), C.c_int, vp]
         L.or_sweep_groups.argtypes = [vp, C.c_int, vp, C.c_int]
@@ -188,6 +191,13 @@ class OracleRun:
         lib().or_get_obs(self._h, _ptr(out))
         return out
 
+    def rho(self):
+        """Mean square family size rho_t [npop, K] (Eq. (rho_t)), computed in
+        the measurement from the family histogram."""
+        out = np.zeros((self.npop, self.K), np.float64)
+        lib().or_get_rho(self._h, _ptr(out))
+        return out
+
     def qhist(self):
         out = np.zeros((self.npop, self.K, self.N + 1), np.int32)
         if lib().or_get_qhist(self._h, _ptr(out)):
@@ -219,17 +229,54 @@ def sweep_draw(seed, n, j, i, pop, s):
     return int(lib().or_sweep_draw(seed, n, j, i, pop, s))
 
 
-def weighted_average(obs_mk, beta, N, R, kind=0):
-    """obs_mk: structured [M, K] records (one population per run)."""
+FAMSTAT_DTYPE = np.dtype([("rho_t", np.float64), ("R_i", np.int32), ("famMax", np.int32),
+                          ("large", np.int32), ("excluded", np.int32)])
+
+EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into `kind`
+
+
+def weighted_average(obs_mk, beta, N, R, kind=0, obs_other=None):
+    """obs_mk: structured [M, K] records (one population per run); obs_other:
+    the other population's records of two-population runs (for the
+    large-family exclusion), or None."""
     obs_mk = np.ascontiguousarray(obs_mk, dtype=OBS_DTYPE)
     M, K = obs_mk.shape
+    other = None if obs_other is None else np.ascontiguousarray(obs_other, dtype=OBS_DTYPE)
     beta = np.ascontiguousarray(beta, dtype=np.float64)
     R = np.ascontiguousarray(np.broadcast_to(np.asarray(R, np.int32), (M,)), dtype=np.int32)
     out = np.zeros(K, WAVG_DTYPE)
-    st = lib().or_weighted_average(_ptr(obs_mk), M, K, _ptr(beta), int(N), _ptr(R), int(kind),
+    st = lib().or_weighted_average(_ptr(obs_mk), _ptr(other), M, K, _ptr(beta), int(N), _ptr(R), int(kind),
                                    _ptr(out))
     if st:
         raise ValueError(f"or_weighted_average failed: {st}")
+    return out
+
+
+def weighted_qhist(obs_mk, qh_mkd, N, R, kind=0, obs_other=None):
+    """Eq. (W_conf_q) for one group: obs_mk [M, K] records and qh_mkd
+    [M, K, N+1] histograms of the weighted population; returns [K, N+1]."""
+    obs_mk = np.ascontiguousarray(obs_mk, dtype=OBS_DTYPE)
+    M, K = obs_mk.shape
+    other = None if obs_other is None else np.ascontiguousarray(obs_other, dtype=OBS_DTYPE)
+    qh = np.ascontiguousarray(qh_mkd, dtype=np.int32)
+    assert qh.shape == (M, K, N + 1)
+    R = np.ascontiguousarray(np.broadcast_to(np.asarray(R, np.int32), (M,)), dtype=np.int32)
+    out = np.zeros((K, N + 1), np.float64)
+    st = lib().or_weighted_qhist(_ptr(obs_mk), _ptr(other), _ptr(qh), M, K, int(N), _ptr(R), int(kind), _ptr(out))
+    if st:
+        raise ValueError(f"or_weighted_qhist failed: {st}")
+    return out
+
+
+def family_stats(rho_k, obs_k, obs_other_k=None):
+    """Family statistics [K] of one run's population: rho_t (Eq. (rho_t),
+    from OracleRun.rho()), largest family, > R_i/2 flag, exclusion flag."""
+    obs_k = np.ascontiguousarray(obs_k, dtype=OBS_DTYPE)
+    K = obs_k.shape[0]
+    rho = np.ascontiguousarray(rho_k, dtype=np.float64)
+    other = None if obs_other_k is None else np.ascontiguousarray(obs_other_k, dtype=OBS_DTYPE)
+    out = np.zeros(K, FAMSTAT_DTYPE)
+    lib().or_family_stats(_ptr(rho), _ptr(obs_k), _ptr(other), K, _ptr(out))
     return out
 
 

@@ -103,6 +103,7 @@ typedef struct {
     or_pop pop[2];
     or_obs *obs;            /* [npop][K] */
     int32_t *qh;            /* [npop][K][N+1] or NULL */
+    double *rho;            /* [npop][K] mean square family size, Eq. (rho_t) */
     int i, phase;
     int64_t e_mismatch;     /* tracked-vs-recomputed energy mismatches seen */
 } or_run;
@@ -223,7 +224,7 @@ void or_destroy(or_run *run)
         free(run->pop[p].X);
     }
     free(run->jR); free(run->jD);
-    free(run->beta); free(run->obs); free(run->qh);
+    free(run->beta); free(run->obs); free(run->qh); free(run->rho);
     free(run);
 }
 
@@ -302,6 +303,8 @@ or_run *or_create(const or_desc *d)
         }
     }
     run->obs = (or_obs *)calloc((size_t)run->npop * d->K, sizeof(or_obs));
+    run->rho = (double *)malloc(sizeof(double) * run->npop * d->K);
+    for (int k = 0; k < run->npop * d->K; k++) run->rho[k] = NAN;
     if (d->qhist)
         run->qh = (int32_t *)calloc((size_t)run->npop * d->K * (N + 1), sizeof(int32_t));
     run->i = 0;
@@ -616,12 +619,18 @@ static int measure_impl(or_run *run, int i)
         P->Emin = Emin;
         int32_t *counts = (int32_t *)calloc(run->d.R, sizeof(int32_t));
         for (int j = 0; j < Ri; j++) counts[F[j]]++;
+        double rho = 0.0;   /* Eq. (rho_t): R_i sum_k n_k^2, n_k = c_k / R_i */
         for (int f = 0; f < run->d.R; f++) {
             int64_t c = counts[f];
             o->famSumSq += c * c;
             if (c > o->famMax) o->famMax = c;
             if (c > 0) o->nFam++;
+            if (c > 0) {
+                double n = (double)c / (double)Ri;
+                rho += n * n;
+            }
         }
+        run->rho[(size_t)p * K + i] = (double)Ri * rho;
         free(counts);
         int32_t *hist = run->qh ? &run->qh[((size_t)p * K + i) * (N + 1)] : NULL;
         if (hist) memset(hist, 0, sizeof(int32_t) * (N + 1));
@@ -734,6 +743,12 @@ int or_get_qhist(const or_run *run, int32_t *out /* [npop][K][N+1] */)
     return OR_OK;
 }
 
+int or_get_rho(const or_run *run, double *out /* [npop][K] */)
+{
+    memcpy(out, run->rho, sizeof(double) * run->npop * run->d.K);
+    return OR_OK;
+}
+
 /* ------------------------------------------------------ weighted average -- */
 
 /* Per-run estimators at temperature i from the integer sums of one record. */
@@ -784,10 +799,51 @@ static double log_weight(const or_obs *om /* [K] of run m */, int i, int kind, i
  * W[Q_k] = sum_m w_{k-1}^(m) Q_k^(m) over the runs still included at k;
  * var_w = (1/n) sum (w - 1/n)^2 and var_w_pred = (exp(var A_i) - 1)/n^2,
  * Eq. (varWpred), var taken as (1/n) sum (A - mean A)^2. */
-int or_weighted_average(const or_obs *obs, int M, int K, const double *beta, int N,
+/* A family holds more than R_i / 2 replicas at temperature i in run m
+ * (Sec. III D, Table I); obs_other: the other population of two-population
+ * runs, or NULL. */
+static int family_over_half(const or_obs *obs, const or_obs *obs_other, int K, int m, int i)
+{
+    const or_obs *o = &obs[(size_t)m * K + i];
+    if (2 * o->famMax > o->R_i) return 1;
+    if (obs_other) {
+        const or_obs *q = &obs_other[(size_t)m * K + i];
+        if (2 * q->famMax > q->R_i) return 1;
+    }
+    return 0;
+}
+
+/* Weights of the overlap averages at temperature i: w_m over the runs with
+ * status OK, leaving out (flag 2 of kind) runs with a family above R_i / 2;
+ * returns the number of runs kept (0: no weights). */
+static int overlap_weights(const or_obs *obs, const or_obs *obs_other, int M, int K, int i, int kind,
+                           const int32_t *R, double *w)
+{
+    double amax = -INFINITY;
+    int n = 0;
+    double *a = (double *)malloc(sizeof(double) * M);
+    for (int m = 0; m < M; m++) {
+        const or_obs *om = &obs[(size_t)m * K];
+        a[m] = NAN;
+        if (om[i].status != OR_OK) continue;
+        if ((kind & 2) && family_over_half(obs, obs_other, K, m, i)) continue;
+        a[m] = log_weight(om, i, kind & 1, R[m]);
+        if (a[m] > amax) amax = a[m];
+        n++;
+    }
+    double Z = 0.0;
+    for (int m = 0; m < M; m++)
+        if (!isnan(a[m])) Z += exp(a[m] - amax);
+    for (int m = 0; m < M; m++) w[m] = isnan(a[m]) ? 0.0 : exp(a[m] - amax) / Z;
+    free(a);
+    return n;
+}
+
+int or_weighted_average(const or_obs *obs, const or_obs *obs_other, int M, int K, const double *beta, int N,
                         const int32_t *R, int kind, or_wavg *out /* [K] */)
 {
-    if (M < 1 || K < 1 || !obs || !beta || !R || !out || kind < 0 || kind > 1) return OR_ERR_ARG;
+    if (M < 1 || K < 1 || !obs || !beta || !R || !out || kind < 0 || kind > 3) return OR_ERR_ARG;
+    double *wq = (double *)malloc(sizeof(double) * M);
     double *a = (double *)malloc(sizeof(double) * M);
     double *w = (double *)malloc(sizeof(double) * M);
     double *aprev = (double *)malloc(sizeof(double) * M);
@@ -800,7 +856,7 @@ int or_weighted_average(const or_obs *obs, int M, int K, const double *beta, int
         for (int m = 0; m < M; m++) {
             const or_obs *om = &obs[(size_t)m * K];
             if (om[i].status != OR_OK) continue;
-            a[m] = log_weight(om, i, kind, R[m]);
+            a[m] = log_weight(om, i, kind & 1, R[m]);
             if (a[m] > amax) amax = a[m];
             n++;
         }
@@ -829,10 +885,20 @@ int or_weighted_average(const or_obs *obs, int M, int K, const double *beta, int
             o->W_m += w[m] * r.m;
             o->W_m2 += w[m] * r.m2;
             o->Wconf_chi += w[m] * r.chi;
-            o->W_absq += w[m] * r.absq;
-            o->W_q2 += w[m] * r.q2;
-            o->W_ql += w[m] * r.ql;
             sumA += om->A;
+        }
+        /* overlap averages, with their own weights (exclusion flag) */
+        if (overlap_weights(obs, obs_other, M, K, i, kind, R, wq) == 0) {
+            o->W_absq = o->W_q2 = o->W_ql = NAN;
+        } else {
+            for (int m = 0; m < M; m++) {
+                const or_obs *om = &obs[(size_t)m * K + i];
+                if (om->status != OR_OK || ((kind & 2) && family_over_half(obs, obs_other, K, m, i))) continue;
+                run_est r = estimators(om, b, N);
+                o->W_absq += wq[m] * r.absq;
+                o->W_q2 += wq[m] * r.q2;
+                o->W_ql += wq[m] * r.ql;
+            }
         }
         double se = 0.0, sm = 0.0, vw = 0.0, va = 0.0;
         double meanA = sumA / n;
@@ -875,7 +941,64 @@ int or_weighted_average(const or_obs *obs, int M, int K, const double *beta, int
         o->minus_beta_WF = mbWF;
         for (int m = 0; m < M; m++) aprev[m] = a[m];
     }
-    free(a); free(w); free(aprev);
+    free(a); free(w); free(aprev); free(wq);
+    return OR_OK;
+}
+
+/* Eq. (W_conf_q): W[P(q)] = sum_m w^(m) P^(m)(q), P^(m) the empirical
+ * distribution of run m's overlap pairs at temperature i (its histogram
+ * over Hamming distances divided by its number of pairs).  qh: [M][K][N+1]
+ * histograms of the weighted population; out: [K][N+1], NaN where no run is
+ * kept. */
+int or_weighted_qhist(const or_obs *obs, const or_obs *obs_other, const int32_t *qh, int M, int K, int N,
+                      const int32_t *R, int kind, double *out)
+{
+    if (M < 1 || K < 1 || !obs || !qh || !R || !out || kind < 0 || kind > 3) return OR_ERR_ARG;
+    double *w = (double *)malloc(sizeof(double) * M);
+    for (int i = 0; i < K; i++) {
+        double *o = &out[(size_t)i * (N + 1)];
+        if (overlap_weights(obs, obs_other, M, K, i, kind, R, w) == 0) {
+            for (int d = 0; d <= N; d++) o[d] = NAN;
+            continue;
+        }
+        for (int d = 0; d <= N; d++) {
+            double acc = 0.0;
+            for (int m = 0; m < M; m++) {
+                const or_obs *om = &obs[(size_t)m * K + i];
+                if (w[m] == 0.0 || om->nPairs <= 0) continue;
+                const int32_t h = qh[((size_t)m * K + i) * (N + 1) + d];
+                acc += w[m] * ((double)h / (double)om->nPairs);
+            }
+            o[d] = acc;
+        }
+    }
+    free(w);
+    return OR_OK;
+}
+
+/* Family statistics per temperature of one run's population: rho_t from
+ * Eq. (rho_t) (computed in the measurement from the family histogram), the
+ * largest family, whether it exceeds R_i / 2, and whether the run is left
+ * out of overlap averages (a large family in either population, or a status
+ * other than OK). */
+typedef struct {
+    double rho_t;
+    int32_t R_i, famMax, large, excluded;
+} or_famstat;
+
+int or_family_stats(const double *rho /* [K] */, const or_obs *obs /* [K] */, const or_obs *obs_other,
+                    int K, or_famstat *out /* [K] */)
+{
+    for (int i = 0; i < K; i++) {
+        const or_obs *o = &obs[i];
+        or_famstat f = {NAN, (int32_t)o->R_i, (int32_t)o->famMax, 0, 1};
+        if (o->status == OR_OK && o->R_i > 0) {
+            f.rho_t = rho[i];
+            f.large = 2 * o->famMax > o->R_i;
+            f.excluded = family_over_half(obs, obs_other, K, 0, i);
+        }
+        out[i] = f;
+    }
     return OR_OK;
 }
 

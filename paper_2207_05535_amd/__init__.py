@@ -22,6 +22,7 @@ PA_MULTINOMIAL, PA_NEAREST_INT = 0, 1
 PA_INT8, PA_MSC64 = 0, 1
 PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP = 0, 1, 2
 PA_W_FULL, PA_W_SIMPLE = 0, 1
+PA_W_EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into a weight kind
 
 REPRS = {"int8": PA_INT8, "msc": PA_MSC64, PA_INT8: PA_INT8, PA_MSC64: PA_MSC64}
 
@@ -44,6 +45,10 @@ PA_WAVG_DTYPE = np.dtype(
     [(n, np.float64) for n in ("W_e", "W_e2", "Wvar_c", "Wconf_c", "W_m", "W_m2", "Wvar_chi",
                                "Wconf_chi", "W_absq", "W_q2", "W_ql", "minus_beta_WF", "var_w",
                                "var_w_pred")] + [("n_included", np.int32), ("_pad", np.int32)])
+
+
+PA_FAMSTAT_DTYPE = np.dtype([("rho_t", np.float64), ("R_i", np.int32), ("famMax", np.int32),
+                             ("large", np.int32), ("excluded", np.int32)])
 
 
 class PAError(RuntimeError):
@@ -73,6 +78,8 @@ def lib():
             "pa_measure": [vp, i32, vp],
             "pa_run": [vp, i32, i32],
             "pa_weighted_average": [vp, i32, i32, i32, vp],
+            "pa_weighted_qhist": [vp, i32, i32, i32, vp],
+            "pa_family_stats": [vp, i32, vp],
             "pa_read_obs": [vp, vp],
             "pa_read_qhist": [vp, i32, vp],
             "pa_read_state": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
@@ -189,6 +196,14 @@ def pa_run(h, i_begin, i_end):
 
 def pa_weighted_average(h, M, kind, pop, out):
     _chk("pa_weighted_average", lib().pa_weighted_average(h, M, kind, pop, _p(out)), h)
+
+
+def pa_weighted_qhist(h, M, kind, pop, out):
+    _chk("pa_weighted_qhist", lib().pa_weighted_qhist(h, M, kind, pop, _p(out)), h)
+
+
+def pa_family_stats(h, pop, out):
+    _chk("pa_family_stats", lib().pa_family_stats(h, pop, _p(out)), h)
 
 
 def pa_read_obs(h, out):
@@ -378,6 +393,20 @@ class Context:
         K = len(self.runs[0]["beta"])
         out = np.zeros((self.n_runs // M, K), PA_WAVG_DTYPE)
         pa_weighted_average(self.h, M, kind, pop, out)
+        return out
+
+    def weighted_qhist(self, M, kind=PA_W_FULL, pop=0):
+        """Eq. (W_conf_q) per group of M runs: [n_runs/M, K, N+1]."""
+        K = len(self.runs[0]["beta"])
+        N = self.runs[0]["L"] ** 2
+        out = np.zeros((self.n_runs // M, K, N + 1), np.float64)
+        pa_weighted_qhist(self.h, M, kind, pop, out)
+        return out
+
+    def family_stats(self, pop=0):
+        """rho_t, largest family and exclusion flags: [n_runs, K]."""
+        out = np.zeros((self.n_runs, self.Kmax), PA_FAMSTAT_DTYPE)
+        pa_family_stats(self.h, pop, out)
         return out
 
     def state(self, run=0, pop=0):

@@ -47,6 +47,7 @@ struct Layout {
     std::vector<RunOff> runs;
     std::vector<TableOff> tables;
     size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items, queue, meas_items;
+    size_t qw, famst, wq;   // overlap weights, family statistics, weighted overlap distributions
     int n_items, n_chunk_items, n_meas_items, npop_ctx, Kmax, maxN;
     size_t total;
 };

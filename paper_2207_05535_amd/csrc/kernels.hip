@@ -1662,7 +1662,7 @@ __global__ void k_logw(const RunInfo *runs, const pa_obs *obs, int n_runs, int n
         }
         double a = NAN;
         if (i <= i_done && o.status == PA_OK && pop < R.npop)
-            a = log((double)o.R_i) + o.A + (kind == PA_W_FULL ? cum : 0.0);
+            a = log((double)o.R_i) + o.A + ((kind & 1) == PA_W_FULL ? cum : 0.0);
         logw[(size_t)run * R.K + i] = a;
     }
 }
@@ -1673,7 +1673,7 @@ __global__ void k_logw(const RunInfo *runs, const pa_obs *obs, int n_runs, int n
 // sample variance of w and its log-normal prediction; and ln W[Q_i] with
 // the weights of temperature i-1 renormalised over the runs included at i
 // (stored in minus_beta_WF, summed over i by k_wavg_cumsum).
-__global__ void k_wavg(const RunInfo *runs, const pa_obs *obs, const double *logw, int n_runs,
+__global__ void k_wavg(const RunInfo *runs, const pa_obs *obs, const double *logw, const double *qw, int n_runs,
                        int npop_ctx, int pop, int M, int K, pa_wavg *out)
 {
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1723,14 +1723,16 @@ __global__ void k_wavg(const RunInfo *runs, const pa_obs *obs, const double *log
         w.W_m += wm * ((double)o.sumAbsM / (dN * Ri));
         w.W_m2 += wm * ((double)o.sumM2 / (dN * dN * Ri));
         w.Wconf_chi += wm * (b * (double)vM / (dN * Ri * Ri));
-        if (o.nPairs > 0) {
+        const double wq = qw[(size_t)run * K + i];   // overlap weights (exclusion applied)
+        if (o.nPairs > 0 && !isnan(wq)) {
             const double np = (double)o.nPairs;
-            w.W_absq += wm * ((double)o.sumAbsQ / (dN * np));
-            w.W_q2 += wm * ((double)o.sumQ2 / (dN * dN * np));
-            w.W_ql += wm * ((double)o.sumQl / (2.0 * dN * np));
+            w.W_absq += wq * ((double)o.sumAbsQ / (dN * np));
+            w.W_q2 += wq * ((double)o.sumQ2 / (dN * dN * np));
+            w.W_ql += wq * ((double)o.sumQl / (2.0 * dN * np));
         }
         sumA += o.A;
     }
+    if (isnan(qw[(size_t)(grp * M) * K + i])) w.W_absq = w.W_q2 = w.W_ql = NAN;
     const double meanA = sumA / n;
     double se = 0.0, sm = 0.0, vw = 0.0, va = 0.0;
     for (int m = 0; m < M; ++m) {
@@ -1781,6 +1783,114 @@ __global__ void k_wavg(const RunInfo *runs, const pa_obs *obs, const double *log
         w.minus_beta_WF = (mx + log(s1)) - (mx0 + log(s0));
     }
     out[(size_t)grp * K + i] = w;
+}
+
+// A family holds more than R_i / 2 replicas in run `run` at temperature i
+// (population pop, or either population of a two-population run).
+__device__ __forceinline__ bool large_family(const RunInfo &R, const pa_obs *obs, int i, int run, int n_runs,
+                                             int npop_ctx, int pop)
+{
+    for (int p = 0; p < R.npop; ++p) {
+        if (p != pop && R.overlap != PA_Q_TWO_POP) continue;
+        const pa_obs &o = obs[((size_t)i * n_runs + run) * npop_ctx + p];
+        if (2 * o.famMax > o.R_i) return true;
+    }
+    return false;
+}
+
+// Weights of the overlap averages: the free-energy weights of k_logw,
+// normalised over the included runs of the group (with
+// PA_W_EXCLUDE_LARGE_FAMILY also leaving out runs with a family above
+// R_i / 2); 0 for a run left out, NaN for every run if none is left.
+__global__ void k_qweights(const RunInfo *runs, const pa_obs *obs, const double *logw, int n_runs, int npop_ctx,
+                           int pop, int M, int K, int flags, double *qw)
+{
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ngroups = n_runs / M;
+    if (gi >= ngroups * K) return;
+    const int grp = gi / K, i = gi - grp * K;
+    const bool excl = flags & PA_W_EXCLUDE_LARGE_FAMILY;
+    double amax = -INFINITY;
+    int n = 0;
+    for (int m = 0; m < M; ++m) {
+        const int run = grp * M + m;
+        const double a = logw[(size_t)run * K + i];
+        if (isnan(a) || (excl && large_family(runs[run], obs, i, run, n_runs, npop_ctx, pop))) continue;
+        amax = fmax(amax, a);
+        ++n;
+    }
+    double Z = 0.0;
+    for (int m = 0; m < M; ++m) {
+        const int run = grp * M + m;
+        const double a = logw[(size_t)run * K + i];
+        if (isnan(a) || (excl && large_family(runs[run], obs, i, run, n_runs, npop_ctx, pop))) continue;
+        Z += exp(a - amax);
+    }
+    for (int m = 0; m < M; ++m) {
+        const int run = grp * M + m;
+        const double a = logw[(size_t)run * K + i];
+        double w = 0.0;
+        if (n == 0) w = NAN;
+        else if (!isnan(a) && !(excl && large_family(runs[run], obs, i, run, n_runs, npop_ctx, pop)))
+            w = exp(a - amax) / Z;
+        qw[(size_t)run * K + i] = w;
+    }
+}
+
+// Eq. (W_conf_q): one workgroup per (group, temperature), threads over the
+// N + 1 bins: W[P(q)](d) = sum_m w_m h_m(d) / nPairs_m, runs in group order.
+__global__ void k_wqhist(const RunInfo *runs, const pa_obs *obs, const double *qw, int n_runs, int npop_ctx,
+                         int pop, int M, int K, double *out)
+{
+    const int grp = blockIdx.x / K, i = blockIdx.x - grp * K;
+    const int N = runs[grp * M].N;
+    const size_t Np1 = (size_t)N + 1;
+    double *o = out + ((size_t)grp * K + i) * Np1;
+    for (size_t d = threadIdx.x; d < Np1; d += blockDim.x) {
+        double acc = 0.0;
+        bool none = false;
+        for (int m = 0; m < M; ++m) {
+            const int run = grp * M + m;
+            const double w = qw[(size_t)run * K + i];
+            if (isnan(w)) {
+                none = true;
+                break;
+            }
+            if (w == 0.0) continue;
+            const pa_obs &ob = obs[((size_t)i * n_runs + run) * npop_ctx + pop];
+            if (ob.nPairs <= 0) continue;
+            const int32_t h = runs[run].qh[((size_t)pop * K + i) * Np1 + d];
+            acc += w * ((double)h / (double)ob.nPairs);
+        }
+        o[d] = none ? NAN : acc;
+    }
+}
+
+// Family statistics of every (run, temperature) of population pop.
+__global__ void k_famstats(const RunInfo *runs, const pa_obs *obs, int n_runs, int npop_ctx, int pop, int K,
+                           int i_done, pa_famstat *out)
+{
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n_runs * K) return;
+    const int run = gi / K, i = gi - run * K;
+    const RunInfo &R = runs[run];
+    pa_famstat f;
+    f.rho_t = NAN;
+    f.R_i = 0;
+    f.famMax = 0;
+    f.large = 0;
+    f.excluded = 1;
+    if (pop < R.npop && i < R.K && i <= i_done) {
+        const pa_obs &o = obs[((size_t)i * n_runs + run) * npop_ctx + pop];
+        f.R_i = (int32_t)o.R_i;
+        f.famMax = (int32_t)o.famMax;
+        if (o.status == PA_OK && o.R_i > 0) {
+            f.rho_t = (double)o.famSumSq / (double)o.R_i;
+            f.large = 2 * o.famMax > o.R_i ? 1 : 0;
+            f.excluded = large_family(R, obs, i, run, n_runs, npop_ctx, pop) ? 1 : 0;
+        }
+    }
+    out[gi] = f;
 }
 
 // -beta_i W[F_i] = ln Z(beta_0) + sum_{k=1..i} ln W[Q_k], Eq. (W_F).
@@ -1944,14 +2054,41 @@ hipError_t launch_measure(const LaunchCtx &c)
     return hipGetLastError();
 }
 
-hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K,
-                       int i_done, double *logw, pa_wavg *out)
+hipError_t launch_qweights(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
+                           double *logw, double *qw)
 {
     k_logw<<<(c.n_runs + 255) / 256, 256, 0, c.stream>>>(c.runs, obs, c.n_runs, c.npop_ctx, pop, kind, i_done,
                                                         logw);
     PA_CHECK_LAUNCH();
     const int ng = c.n_runs / M;
-    k_wavg<<<(ng * K + 127) / 128, 128, 0, c.stream>>>(c.runs, obs, logw, c.n_runs, c.npop_ctx, pop, M, K, out);
+    k_qweights<<<(ng * K + 127) / 128, 128, 0, c.stream>>>(c.runs, obs, logw, c.n_runs, c.npop_ctx, pop, M, K,
+                                                          kind & ~1, qw);
+    return hipGetLastError();
+}
+
+hipError_t launch_wqhist(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
+                         double *logw, double *qw, double *out)
+{
+    if (launch_qweights(c, obs, M, kind, pop, K, i_done, logw, qw) != hipSuccess) return hipGetLastError();
+    const int ng = c.n_runs / M;
+    k_wqhist<<<ng * K, 256, 0, c.stream>>>(c.runs, obs, qw, c.n_runs, c.npop_ctx, pop, M, K, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_famstats(const LaunchCtx &c, const pa_obs *obs, int pop, int K, int i_done, pa_famstat *out)
+{
+    k_famstats<<<(c.n_runs * K + 255) / 256, 256, 0, c.stream>>>(c.runs, obs, c.n_runs, c.npop_ctx, pop, K,
+                                                                 i_done, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K,
+                       int i_done, double *logw, double *qw, pa_wavg *out)
+{
+    if (launch_qweights(c, obs, M, kind, pop, K, i_done, logw, qw) != hipSuccess) return hipGetLastError();
+    const int ng = c.n_runs / M;
+    k_wavg<<<(ng * K + 127) / 128, 128, 0, c.stream>>>(c.runs, obs, logw, qw, c.n_runs, c.npop_ctx, pop, M, K,
+                                                      out);
     PA_CHECK_LAUNCH();
     k_wavg_cumsum<<<(ng + 127) / 128, 128, 0, c.stream>>>(out, ng, K);
     return hipGetLastError();

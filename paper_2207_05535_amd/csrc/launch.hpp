@@ -37,7 +37,12 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
 hipError_t launch_sweep_msc(const LaunchCtx &c);
 hipError_t launch_measure(const LaunchCtx &c);
 hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
-                       double *logw, pa_wavg *out);
+                       double *logw, double *qw, pa_wavg *out);
+hipError_t launch_qweights(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
+                           double *logw, double *qw);
+hipError_t launch_wqhist(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
+                         double *logw, double *qw, double *out);
+hipError_t launch_famstats(const LaunchCtx &c, const pa_obs *obs, int pop, int K, int i_done, pa_famstat *out);
 int int8_tile_rows(int L);
 size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);

@@ -130,7 +130,15 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     Lo.chunk_items = P.take(sizeof(ChunkItem) * Lo.n_chunk_items);
     Lo.obs = P.take(sizeof(pa_obs) * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx);
     Lo.logw = P.take(sizeof(double) * (size_t)Lo.Kmax * n_runs);
+    Lo.qw = P.take(sizeof(double) * (size_t)Lo.Kmax * n_runs);
     Lo.wavg = P.take(sizeof(pa_wavg) * (size_t)Lo.Kmax * n_runs);
+    Lo.famst = P.take(sizeof(pa_famstat) * (size_t)Lo.Kmax * n_runs);
+    {
+        size_t wq = 0;
+        for (int r = 0; r < n_runs; ++r)
+            if (runs[r].qhist) wq += (size_t)runs[r].K * (runs[r].L * runs[r].L + 1);
+        Lo.wq = P.take(sizeof(double) * wq);
+    }
     Lo.runs.resize(n_runs);
     for (int r = 0; r < n_runs; ++r) {
         const pa_run_desc &d = runs[r];
@@ -626,24 +634,71 @@ pa_status pa_run(pa_ctx *c, int32_t i_begin, int32_t i_end)
     return PA_OK;
 }
 
-pa_status pa_weighted_average(pa_ctx *c, int32_t M, pa_weight_kind kind, int32_t pop, pa_wavg *host_out)
+namespace {
+
+// Groups of M runs with one L and schedule each, population pop present.
+bool groups_ok(const pa_ctx *c, int M, int pop, bool need_qhist)
 {
-    if (!c || !host_out || M < 1 || c->n_runs % M != 0 || (kind != PA_W_FULL && kind != PA_W_SIMPLE))
-        return PA_ERR_ARG;
-    if (c->failed) return PA_ERR_DEVICE;
+    if (M < 1 || c->n_runs % M != 0) return false;
     const int K = c->descs[0].K;
     for (int r = 0; r < c->n_runs; ++r) {
         const pa_run_desc &d = c->descs[r];
-        if (d.K != K || pop < 0 || pop >= n_pop_of(d.overlap)) return PA_ERR_ARG;
+        if (d.K != K || pop < 0 || pop >= n_pop_of(d.overlap)) return false;
+        if (need_qhist && !d.qhist) return false;
         const pa_run_desc &d0 = c->descs[(r / M) * M];
-        if (d.L != d0.L || std::memcmp(d.beta, d0.beta, sizeof(double) * K) != 0) return PA_ERR_ARG;
+        if (d.L != d0.L || std::memcmp(d.beta, d0.beta, sizeof(double) * K) != 0) return false;
     }
+    return true;
+}
+
+bool kind_ok(int kind) { return kind >= 0 && kind <= (PA_W_SIMPLE | PA_W_EXCLUDE_LARGE_FAMILY); }
+
+}  // namespace
+
+pa_status pa_weighted_average(pa_ctx *c, int32_t M, int32_t kind, int32_t pop, pa_wavg *host_out)
+{
+    if (!c || !host_out || !kind_ok(kind) || !groups_ok(c, M, pop, false)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const int K = c->descs[0].K;
     const int i_done = c->phase == PH_MEASURED ? c->i : c->i - 1;
     pa_wavg *dout = at<pa_wavg>(c, c->lo.wavg);
-    if (launch_wavg(c->lc, at<pa_obs>(c, c->lo.obs), M, kind, pop, K, i_done, at<double>(c, c->lo.logw), dout) !=
-        hipSuccess)
+    if (launch_wavg(c->lc, at<pa_obs>(c, c->lo.obs), M, kind, pop, K, i_done, at<double>(c, c->lo.logw),
+                    at<double>(c, c->lo.qw), dout) != hipSuccess)
         return dev_fail(c);
     PA_HIP(c, hipMemcpyAsync(host_out, dout, sizeof(pa_wavg) * (size_t)(c->n_runs / M) * K, hipMemcpyDeviceToHost,
+                             c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_weighted_qhist(pa_ctx *c, int32_t M, int32_t kind, int32_t pop, double *host_out)
+{
+    if (!c || !host_out || !kind_ok(kind) || !groups_ok(c, M, pop, true)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const int K = c->descs[0].K;
+    const int N = c->descs[0].L * c->descs[0].L;   // every group must have it (checked above per group)
+    for (int r = 0; r < c->n_runs; ++r)
+        if (c->descs[r].L * c->descs[r].L != N) return PA_ERR_ARG;   // one bin count for the output array
+    const int i_done = c->phase == PH_MEASURED ? c->i : c->i - 1;
+    double *dout = at<double>(c, c->lo.wq);
+    if (launch_wqhist(c->lc, at<pa_obs>(c, c->lo.obs), M, kind, pop, K, i_done, at<double>(c, c->lo.logw),
+                      at<double>(c, c->lo.qw), dout) != hipSuccess)
+        return dev_fail(c);
+    const size_t n = (size_t)(c->n_runs / M) * K * (N + 1);
+    PA_HIP(c, hipMemcpyAsync(host_out, dout, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_family_stats(pa_ctx *c, int32_t pop, pa_famstat *host_out)
+{
+    if (!c || !host_out || pop < 0 || pop >= c->lo.npop_ctx) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    const int K = c->lo.Kmax;
+    const int i_done = c->phase == PH_MEASURED ? c->i : c->i - 1;
+    pa_famstat *dout = at<pa_famstat>(c, c->lo.famst);
+    if (launch_famstats(c->lc, at<pa_obs>(c, c->lo.obs), pop, K, i_done, dout) != hipSuccess) return dev_fail(c);
+    PA_HIP(c, hipMemcpyAsync(host_out, dout, sizeof(pa_famstat) * (size_t)c->n_runs * K, hipMemcpyDeviceToHost,
                              c->stream));
     PA_HIP(c, hipStreamSynchronize(c->stream));
     return PA_OK;

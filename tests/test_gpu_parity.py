@@ -252,6 +252,51 @@ def test_weighted_average_parity(repr_, kind):
     ctx.close()
 
 
+@pytest.mark.parametrize("overlap", [W.Q_INDEX_SHIFT, W.Q_TWO_POP])
+def test_weighted_overlap_distribution_and_family_stats_parity(overlap):
+    """Eq. (W_conf_q) on the device, with every weight kind and the
+    large-family exclusion (Table I), the exclusion in the overlap averages,
+    and the family statistics (Eq. (rho_t)), versus the oracle."""
+    say(f"weighted P(q) and family statistics, overlap={overlap}")
+    M, L = 6, 6
+    N = L * L
+    runs = [W.run_desc(L, W.EA_PMJ, seed=500 + m, disorder_seed=4, R=90, theta=1, K=12, beta_f=2.5,
+                       overlap=overlap, qhist=1) for m in range(2 * M)]
+    ctx = pa.Context(runs, "msc")
+    ctx.run(1, 12)
+    refs = [oracle.OracleRun(d).run_all() for d in runs]
+    npop = 2 if overlap == W.Q_TWO_POP else 1
+    obs = [np.stack([r.obs()[p] for r in refs]) for p in range(npop)]
+    qh = np.stack([r.qhist()[0] for r in refs])
+    other = obs[1] if npop == 2 else None
+    seen_large = False
+    for kind in (0, 1, 2, 3):
+        got_p = ctx.weighted_qhist(M, kind, 0)
+        got_a = ctx.weighted_average(M, kind, 0)
+        for grp in range(2):
+            sl = slice(grp * M, (grp + 1) * M)
+            ref_p = oracle.weighted_qhist(obs[0][sl], qh[sl], N, 90, kind=kind,
+                                          obs_other=None if other is None else other[sl])
+            ref_a = oracle.weighted_average(obs[0][sl], runs[0]["beta"], N, 90, kind=kind,
+                                            obs_other=None if other is None else other[sl])
+            assert np.array_equal(np.isnan(got_p[grp]), np.isnan(ref_p)), (kind, grp)
+            assert close(np.nan_to_num(got_p[grp]), np.nan_to_num(ref_p)), (kind, grp)
+            for f in ("W_absq", "W_q2", "W_ql", "W_e", "minus_beta_WF"):
+                g, r = got_a[grp][f], ref_a[f]
+                assert np.array_equal(np.isnan(g), np.isnan(r)) and close(np.nan_to_num(g), np.nan_to_num(r)), \
+                    (kind, grp, f)
+    for p in range(npop):
+        fs = ctx.family_stats(p)
+        for m, r in enumerate(refs):
+            ref = oracle.family_stats(r.rho()[p], r.obs()[p], r.obs()[1 - p] if npop == 2 else None)
+            for f in ("R_i", "famMax", "large", "excluded"):
+                assert np.array_equal(fs[m][f], ref[f]), (p, m, f)
+            assert close(fs[m]["rho_t"], ref["rho_t"]), (p, m)
+            seen_large |= bool(ref["large"].any())
+    assert seen_large, "the runs should reach families above R_i/2"
+    ctx.close()
+
+
 # --------------------------------------------------------- full-size samples
 
 
