@@ -184,6 +184,34 @@ def test_graph_replays_interleaved_with_eager(repr_):
 
 
 @pytest.mark.parametrize("repr_", REPRS)
+def test_state_between_resampling_and_sweeps(repr_):
+    """The resampled population, read between resampling and the sweeps,
+    equals the oracle's (labels, spins, copy counts), and the step then
+    continues exactly."""
+    say(f"state after resampling {repr_}")
+    d = W.run_desc(8, W.EA_PMJ, seed=21, disorder_seed=3, R=400, theta=2, K=8, beta_f=1.5,
+                   resampling=W.NEAREST_INT, overlap=W.Q_NONE)
+    orc = oracle.OracleRun(d)
+    ctx = pa.Context([d], repr_)
+    for i in range(1, d["K"]):
+        orc.anneal_step(i)
+        orc.resample(i)
+        ctx.anneal_step(i)
+        ctx.resample(i)
+        so, _, fo, _ = orc.state(0)
+        sg, _, fg, rg = ctx.state(0, 0)
+        assert np.array_equal(sg, so) and np.array_equal(fg, fo), f"i={i}"
+        assert np.array_equal(rg, orc.counts(0)[0]), f"i={i}"
+        orc.sweep(i)
+        orc.measure(i)
+        ctx.sweep(i)
+        ctx.measure(i)
+        assert_obs_equal(ctx.obs()[0, 0, i], orc.obs()[0, i], f"i={i}")
+    assert_state_equal(ctx, orc, 0, "final")
+    ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
 def test_checkpoint_restore_bit_exact(repr_):
     d = W.run_desc(8, W.FM, seed=8, R=500, theta=3, K=21, beta_f=1.0, resampling=W.NEAREST_INT,
                    overlap=W.Q_INDEX_SHIFT)
