@@ -77,6 +77,12 @@ def lib():
         L.or_reweight_X.restype = C.c_uint64
         L.or_sweep_draw.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_sweep_draw.restype = C.c_uint32
+        L.or_random_permutation.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, vp]
+        L.or_random_permutation.restype = C.c_int
+        L.or_wang_repair.argtypes = [vp, C.c_int, vp, vp]
+        L.or_wang_repair.restype = C.c_int
+        L.or_get_pairing.argtypes = [vp, C.c_int, vp]
+        L.or_get_pairing.restype = C.c_int
         L.or_weighted_average.argtypes = [vp, vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]
         L.or_weighted_qhist.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]
         L.or_family_stats.argtypes = [vp, vp, vp, C.c_int, vp]
@@ -191,6 +197,14 @@ class OracleRun:
         lib().or_get_obs(self._h, _ptr(out))
         return out
 
+    def pairing(self, pop=0):
+        """(status, pairs) of the permutation pairing at the current
+        temperature: pairs[k] is the partner of replica k."""
+        _, _, fam, _ = self.state(pop)
+        out = np.zeros(max(len(fam), 1), np.int32)
+        st = lib().or_get_pairing(self._h, pop, _ptr(out))
+        return st, out[:len(fam)]
+
     def rho(self):
         """Mean square family size rho_t [npop, K] (Eq. (rho_t)), computed in
         the measurement from the family histogram."""
@@ -233,6 +247,25 @@ FAMSTAT_DTYPE = np.dtype([("rho_t", np.float64), ("R_i", np.int32), ("famMax", n
                           ("large", np.int32), ("excluded", np.int32)])
 
 EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into `kind`
+
+
+def random_permutation(seed, i, pop, R, which=0):
+    """Permutation of [0, R) drawn for the pairing at temperature i
+    (which = 0: the initial pi, 1: the search pattern sigma)."""
+    out = np.zeros(max(R, 1), np.int32)
+    st = lib().or_random_permutation(C.c_uint64(seed), i, pop, R, which, _ptr(out))
+    assert st == OK, st
+    return out[:R]
+
+
+def wang_repair(fam, pi, sigma=None):
+    """Permutation pairing without incestuous pairs (Sec. III D): returns
+    (status, repaired pi); status 1 when a family exceeds R/2 (pi unchanged)."""
+    fam = np.ascontiguousarray(fam, np.int32)
+    out = np.ascontiguousarray(pi, np.int32).copy()
+    sg = None if sigma is None else np.ascontiguousarray(sigma, np.int32)
+    st = lib().or_wang_repair(_ptr(fam), len(fam), _ptr(out), None if sg is None else _ptr(sg))
+    return st, out
 
 
 def weighted_average(obs_mk, beta, N, R, kind=0, obs_other=None):

@@ -17,7 +17,9 @@
  *         parent placed next to each other (Sec. V A 1).
  *   (iv)  theta checkerboard single-spin-flip Metropolis sweeps (Sec. V A 1).
  *   (v)   population averages, Eqs. (PopAvrg), (e), (m), (c), (chi), and spin
- *         overlaps (Sec. III D): index shift floor(R_i/2) or two populations.
+ *         overlaps (Sec. III D): index shift floor(R_i/2), two populations,
+ *         or the permutation pairing of Wang et al. (with or without a
+ *         random search pattern).
  *   Sec. IV: free-energy weights, Eqs. (appropriateWeight), (simpleWeight);
  *         configurational averages, Eq. (W_conf); weighted variance,
  *         Eqs. (Wvar_C), (Wvar_Chi), (Wvar_bound); weighted free energy,
@@ -52,7 +54,9 @@ typedef struct {
     int32_t K;              /* number of temperatures beta[0..K-1] */
     const double *beta;     /* annealing schedule, beta[0] = 0 */
     int32_t resampling;     /* 0 = multinomial, 1 = nearest integer */
-    int32_t overlap;        /* 0 none, 1 index shift, 2 two populations */
+    int32_t overlap;        /* 0 none, 1 index shift, 2 two populations,
+                               3 permutation pairing, 4 the same with a
+                               random search pattern */
     int32_t qhist;          /* 1: keep overlap histograms per temperature */
 } or_desc;
 
@@ -75,7 +79,7 @@ typedef struct {            /* one per temperature of a group of runs */
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_CAPACITY = 3, OR_ERR_STATE = 4,
        OR_ERR_NUMERIC = 5 };
 
-enum { TAG_SWEEP = 1u, TAG_NI = 2u, TAG_MN = 3u, TAG_INIT = 4u, TAG_J = 5u };
+enum { TAG_SWEEP = 1u, TAG_NI = 2u, TAG_MN = 3u, TAG_INIT = 4u, TAG_J = 5u, TAG_PERM = 6u };
 
 enum { PH_MEASURED = 0, PH_ANNEALED = 1, PH_RESAMPLED = 2, PH_SWEPT = 3 };
 
@@ -237,7 +241,7 @@ or_run *or_create(const or_desc *d)
 {
     if (!d || d->L < 4 || (d->L & 1) || d->L > 1024 || d->R < 1 || d->R_cap < d->R ||
         d->theta < 0 || d->K < 2 || !d->beta || d->model < 0 || d->model > 1 ||
-        d->resampling < 0 || d->resampling > 1 || d->overlap < 0 || d->overlap > 2 ||
+        d->resampling < 0 || d->resampling > 1 || d->overlap < 0 || d->overlap > 4 ||
         d->R_cap >= (1 << 23))
         return NULL;
     if (d->resampling == 0 && d->R_cap != d->R) return NULL;
@@ -557,8 +561,9 @@ int or_sweep_groups(or_run *run, int i, const int32_t *groups, int ngroups)
 /* Integer sums over the population at beta_i: sum E, sum E^2, sum |M|,
  * sum M^2 (Eqs. (e), (m) and the squared-summand averages behind (c), (chi));
  * spin overlaps Q = N q = sum_n s_n s'_n for the index-shift pairs
- * (j, j + floor(R_i/2)), j < floor(R_i/2) (Sec. III D), or for the pairs
- * (j of population 0, j of population 1), j < min(R_0, R_1); link overlaps
+ * (j, j + floor(R_i/2)), j < floor(R_i/2) (Sec. III D), for the pairs
+ * (j of population 0, j of population 1), j < min(R_0, R_1), or for the R_i
+ * pairs (k, pi_k) of the permutation pairing below; link overlaps
  * Q_l = sum over the 2N bonds of (s_m s_n)(s'_m s'_n); family sizes c_f. */
 static void pair_overlap(const or_run *run, const int8_t *a, const int8_t *b,
                          int64_t *Q, int64_t *Ql, int *ham)
@@ -585,6 +590,136 @@ static void add_pair(or_obs *o, int32_t *hist, int64_t Q, int64_t Ql, int ham)
     o->sumQl += Ql;
     o->sumQl2 += Ql * Ql;
     if (hist) hist[ham]++;
+}
+
+/* ------------------------------------------- permutation pairing (q) -- */
+
+/* A uniformly random permutation of [0, R) for the pairing at temperature
+ * i of population pop: position m holds the index with the m-th smallest
+ * 64-bit key, ties by index.  The key of index k is o0 | o1 << 32
+ * (which = 0, the initial permutation pi) or o2 | o3 << 32 (which = 1, the
+ * search pattern sigma) of Philox(seed; k, 0, i, TAG_PERM << 28 | pop << 24). */
+typedef struct { uint64_t key; int32_t idx; } keyed;
+
+static int keyed_cmp(const void *a, const void *b)
+{
+    const keyed *x = (const keyed *)a, *y = (const keyed *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+int or_random_permutation(uint64_t seed, int i, int pop, int R, int which, int32_t *out)
+{
+    if (R < 0 || (which != 0 && which != 1) || (R > 0 && !out)) return OR_ERR_ARG;
+    uint32_t key[2];
+    key_of(seed, key);
+    keyed *k = (keyed *)malloc(sizeof(keyed) * (R > 0 ? R : 1));
+    for (int j = 0; j < R; j++) {
+        uint32_t o[4];
+        philox_at(key, (uint32_t)j, 0, (uint32_t)i, (TAG_PERM << 28) | ((uint32_t)pop << 24), o);
+        k[j].key = which == 0 ? ((uint64_t)o[0] | ((uint64_t)o[1] << 32))
+                              : ((uint64_t)o[2] | ((uint64_t)o[3] << 32));
+        k[j].idx = j;
+    }
+    qsort(k, R, sizeof(keyed), keyed_cmp);
+    for (int m = 0; m < R; m++) out[m] = k[m].idx;
+    free(k);
+    return OR_OK;
+}
+
+/* Size of the largest family among labels fam[0..R). */
+static int32_t largest_family(const int32_t *fam, int R)
+{
+    int32_t mx = 0, lab = 0;
+    for (int j = 0; j < R; j++)
+        if (fam[j] > lab) lab = fam[j];
+    int32_t *c = (int32_t *)calloc((size_t)lab + 1, sizeof(int32_t));
+    for (int j = 0; j < R; j++)
+        if (++c[fam[j]] > mx) mx = c[fam[j]];
+    free(c);
+    return mx;
+}
+
+/* Sec. III D, pairings from permutations (Wang et al.): turns the
+ * permutation pi (in place) into one in which no position k is paired with
+ * a replica of its own family, fam[pi[k]] != fam[k]; the overlaps are then
+ * those of the R pairs (k, pi[k]), every replica used twice.
+ *   sigma == NULL: repeatedly take the smallest position k whose pair is
+ *   incestuous and walk l = 1, 2, ... (positions mod R) to the first k + l
+ *   with pi[k + l] outside k's family and pi[k] outside the family of k + l;
+ *   exchange pi[k] and pi[k + l].
+ *   sigma != NULL (random search pattern): go through the positions in the
+ *   order sigma[0], sigma[1], ...; a mismatch at k = sigma[t] is repaired
+ *   with the first sigma[t + l], l = 1, 2, ... (indices of sigma mod R),
+ *   under the same two conditions.
+ * An exchange leaves both of its positions matched and touches no other, so
+ * the number of mismatches falls by at least one each time.  A suitable
+ * partner exists whenever no family holds more than R/2 replicas; if one
+ * does, no such permutation exists at all, pi is left as it was and 1 is
+ * returned (the measurement is then omitted).  Parity: pinned by brute
+ * force on small populations (tests). */
+int or_wang_repair(const int32_t *fam, int R, int32_t *pi, const int32_t *sigma)
+{
+    if (R < 1 || !fam || !pi) return OR_ERR_ARG;
+    if (2 * (int64_t)largest_family(fam, R) > R) return 1;
+    if (!sigma) {
+        for (;;) {
+            int k = -1;
+            for (int j = 0; j < R && k < 0; j++)
+                if (fam[pi[j]] == fam[j]) k = j;
+            if (k < 0) return OR_OK;
+            int found = 0;
+            for (int l = 1; l < R && !found; l++) {
+                int m = (k + l) % R;
+                if (fam[pi[m]] != fam[k] && fam[pi[k]] != fam[m]) {
+                    int32_t t = pi[k]; pi[k] = pi[m]; pi[m] = t;
+                    found = 1;
+                }
+            }
+            if (!found) return OR_ERR_NUMERIC;   /* unreachable when no family exceeds R/2 */
+        }
+    }
+    for (int t = 0; t < R; t++) {
+        int k = sigma[t];
+        if (fam[pi[k]] != fam[k]) continue;
+        int found = 0;
+        for (int l = 1; l < R && !found; l++) {
+            int m = sigma[(t + l) % R];
+            if (fam[pi[m]] != fam[k] && fam[pi[k]] != fam[m]) {
+                int32_t x = pi[k]; pi[k] = pi[m]; pi[m] = x;
+                found = 1;
+            }
+        }
+        if (!found) return OR_ERR_NUMERIC;
+    }
+    return OR_OK;
+}
+
+/* The pairing of population p at temperature i for overlap kinds 3 and 4:
+ * pi from or_random_permutation, repaired by or_wang_repair (with sigma for
+ * kind 4).  Returns 0 and fills out[R_i], or 1 when a family is too large. */
+static int wang_pairing(const or_run *run, int p, int i, int32_t *out)
+{
+    const or_pop *P = &run->pop[p];
+    int R = P->Rcur;
+    or_random_permutation(run->d.seed, i, p, R, 0, out);
+    int32_t *sigma = NULL;
+    if (run->d.overlap == 4) {
+        sigma = (int32_t *)malloc(sizeof(int32_t) * R);
+        or_random_permutation(run->d.seed, i, p, R, 1, sigma);
+    }
+    int st = or_wang_repair(P->f[P->cur], R, out, sigma);
+    free(sigma);
+    return st;
+}
+
+/* The repaired pairing of population p as it stands (for tests): returns 0
+ * and fills out[R_i], 1 if a family holds more than R_i/2 replicas, or an
+ * error for a run without permutation pairing. */
+int or_get_pairing(const or_run *run, int p, int32_t *out)
+{
+    if (!run || p < 0 || p >= run->npop || !out || run->d.overlap < 3) return OR_ERR_ARG;
+    return wang_pairing(run, p, run->i, out);
 }
 
 static int measure_impl(or_run *run, int i)
@@ -642,6 +777,16 @@ static int measure_impl(or_run *run, int i)
                 pair_overlap(run, &S[(size_t)j * N], &S[(size_t)(j + h) * N], &Q, &Ql, &ham);
                 add_pair(o, hist, Q, Ql, ham);
             }
+        } else if (run->d.overlap >= 3) {
+            int32_t *pi = (int32_t *)malloc(sizeof(int32_t) * Ri);
+            if (wang_pairing(run, p, i, pi) == OR_OK)
+                for (int k = 0; k < Ri; k++) {
+                    int64_t Q, Ql;
+                    int ham;
+                    pair_overlap(run, &S[(size_t)k * N], &S[(size_t)pi[k] * N], &Q, &Ql, &ham);
+                    add_pair(o, hist, Q, Ql, ham);
+                }
+            free(pi);
         }
         o->status = OR_OK;
     }
