@@ -60,8 +60,15 @@ enum { PA_MULTINOMIAL = 0, PA_NEAREST_INT = 1 };
  * 64-bit word (multi-spin coding).  Results are identical. */
 typedef enum { PA_INT8 = 0, PA_MSC64 = 1 } pa_repr;
 /* Spin-overlap pairing (Sec. III D): none; index shift j <-> j + floor(R_i/2);
- * or two independent populations on the same couplings, pairs j <-> j. */
-enum { PA_Q_NONE = 0, PA_Q_INDEX_SHIFT = 1, PA_Q_TWO_POP = 2 };
+ * two independent populations on the same couplings, pairs j <-> j; or the
+ * permutation pairing of Wang et al.: the R_i pairs (k, pi_k) of a random
+ * permutation pi repaired so that no pair lies inside one family
+ * (PA_Q_WANG), or repaired along a random search pattern (PA_Q_WANG_RDM).
+ * The permutations are the index orders of 64-bit Philox keys (counter
+ * (k, 0, i, 6 << 28): words 0-1 for pi, 2-3 for the search pattern).  A
+ * population with a family of more than R_i / 2 replicas has no such
+ * permutation; its record then has no pairs (nPairs = 0). */
+enum { PA_Q_NONE = 0, PA_Q_INDEX_SHIFT = 1, PA_Q_TWO_POP = 2, PA_Q_WANG = 3, PA_Q_WANG_RDM = 4 };
 /* Free-energy weights, Eq. (appropriateWeight) (full) and Eq. (simpleWeight). */
 typedef enum { PA_W_FULL = 0, PA_W_SIMPLE = 1 } pa_weight_kind;
 /* Flag OR-ed into a pa_weight_kind argument: overlap averages (W[|q|],
@@ -85,7 +92,7 @@ typedef struct {
     int32_t K;              /* number of temperatures, K >= 2 */
     const double *beta;     /* host [K]: schedule, beta[0] == 0, finite; copied */
     int32_t resampling;     /* PA_MULTINOMIAL or PA_NEAREST_INT */
-    int32_t overlap;        /* PA_Q_NONE, PA_Q_INDEX_SHIFT or PA_Q_TWO_POP */
+    int32_t overlap;        /* PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP, PA_Q_WANG or PA_Q_WANG_RDM */
     int32_t qhist;          /* 1: keep an overlap histogram per temperature */
 } pa_run_desc;
 
@@ -196,6 +203,15 @@ pa_status pa_read_obs(pa_ctx *ctx, pa_obs *host_out);
 /* Overlap histograms of one run (qhist = 1): host [n_pop][K][N+1] int32,
  * bin d = number of pairs at Hamming distance d (q = 1 - 2d/N). */
 pa_status pa_read_qhist(pa_ctx *ctx, int32_t run, int32_t *host_out);
+
+/* Permutation pairing of a PA_Q_WANG / PA_Q_WANG_RDM run at the last
+ * measured temperature (Sec. III D): host_pairs host [R_cap] int32 receives
+ * the partner pi_k of every replica k < R_i; *status (may be NULL) receives
+ * 0, or 1 when a family held more than R_i / 2 replicas (no pairing; pairs
+ * left unspecified), and *R_i (may be NULL) the population size.  Needs the
+ * context in its measured state (PA_ERR_STATE otherwise); PA_ERR_ARG for a
+ * run with another overlap kind. */
+pa_status pa_read_pairing(pa_ctx *ctx, int32_t run, int32_t *host_pairs, int32_t *status, int32_t *R_i);
 
 /* Current population of (run, pop) in canonical form: spins host
  * [R_cap][N] int8 (+1/-1, replica-major, site n = y L + x), energies and

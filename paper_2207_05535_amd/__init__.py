@@ -20,7 +20,7 @@ PA_OK, PA_ERR_ARG, PA_ERR_NOMEM, PA_ERR_CAPACITY, PA_ERR_STATE, PA_ERR_NUMERIC, 
 PA_FM, PA_EA_PMJ = 0, 1
 PA_MULTINOMIAL, PA_NEAREST_INT = 0, 1
 PA_INT8, PA_MSC64 = 0, 1
-PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP = 0, 1, 2
+PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP, PA_Q_WANG, PA_Q_WANG_RDM = 0, 1, 2, 3, 4
 PA_W_FULL, PA_W_SIMPLE = 0, 1
 PA_W_EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into a weight kind
 
@@ -83,6 +83,7 @@ def lib():
             "pa_read_obs": [vp, vp],
             "pa_read_qhist": [vp, i32, vp],
             "pa_read_state": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
+            "pa_read_pairing": [vp, i32, vp, vp, vp],
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
             "pa_set_tuning": [vp, i32, i32, i32, i32],
@@ -212,6 +213,12 @@ def pa_read_obs(h, out):
 
 def pa_read_qhist(h, run, out):
     _chk("pa_read_qhist", lib().pa_read_qhist(h, run, _p(out)), h)
+
+
+def pa_read_pairing(h, run, out):
+    st, Ri = C.c_int32(0), C.c_int32(0)
+    _chk("pa_read_pairing", lib().pa_read_pairing(h, run, _p(out), C.byref(st), C.byref(Ri)), h)
+    return st.value, Ri.value
 
 
 def pa_read_state(h, run, pop, spins, E, fam, counts):
@@ -418,6 +425,14 @@ class Context:
         r = np.zeros(d["R_cap"], np.int32)
         Ri, Rp = pa_read_state(self.h, run, pop, s, E, f, r)
         return s[:Ri], E[:Ri], f[:Ri], r[:Rp]
+
+    def pairing(self, run=0):
+        """(status, pairs) of a permutation-pairing run at the last measured
+        temperature: pairs[k] is the partner of replica k; status 1 when a
+        family held more than R_i / 2 replicas (no pairing)."""
+        out = np.zeros(self.runs[run]["R_cap"], np.int32)
+        st, Ri = pa_read_pairing(self.h, run, out)
+        return st, out[:Ri]
 
     def qhist(self, run=0):
         d = self.runs[run]

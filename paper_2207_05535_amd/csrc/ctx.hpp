@@ -31,7 +31,7 @@ struct Planner {
 struct RunOff {
     size_t spins[MAX_POP][2], E[MAX_POP][2], fam[MAX_POP][2], r[MAX_POP], C[MAX_POP], parent[MAX_POP],
         P[MAX_POP], part[MAX_POP], partS[MAX_POP], tot64[MAX_POP], base64[MAX_POP], tot32[MAX_POP],
-        base32[MAX_POP], qh, jbits;
+        base32[MAX_POP], qh, jbits, wang;
     int table;
 };
 
@@ -102,6 +102,7 @@ struct pa_ctx {
     bool sweep_pooled = false;          // sparse rounds over one list per workgroup
     std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
     bool any_multinomial = false;
+    bool any_wang = false;
     hipError_t last = hipSuccess;
 };
 

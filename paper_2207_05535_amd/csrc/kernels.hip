@@ -1277,6 +1277,16 @@ __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int 
 
 // -------------------------------------------------------------- step (v)
 
+// Partner words of the permutation pairing ([group][site] u64): the spare
+// spin buffer of population 0 (its previous population is no longer needed
+// once the step's copies are done); for int8 spins after the packed copy of
+// the population that k_wang_pack writes at its start.
+__device__ __forceinline__ uint8_t *wang_partner_words(const RunInfo &R, const PopState &S, bool int8)
+{
+    uint8_t *spare = R.spins[0][S.cur ^ 1];
+    return int8 ? spare + (size_t)R.groups_cap * R.N * 8 : spare;
+}
+
 // Word of 64 replicas of group g at site n, from either layout.
 template <int REPR>
 __device__ __forceinline__ uint64_t load_word(const uint8_t *buf, int g, int n, int N)
@@ -1311,7 +1321,7 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint8_t *buf = R.spins[it.pop][S.cur];
     // overlap partners of this group's replicas
-    int mode = 0;                      // 0 none, 1 index shift, 2 two populations
+    int mode = 0;                      // 0 none, 1 index shift, 2 two populations, 3 permutation pairs
     uint64_t pairmask = 0;
     const uint8_t *pbuf = buf;
     int pg = 0, sh = 0;
@@ -1339,6 +1349,14 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
                 pg = g;
             }
         }
+    } else if (live && is_wang(R.overlap) && wang_bufs(R.wang, R.R_cap, R.wang_lb).hdr[0] == 0) {
+        // permutation pairs (j, pi_j) for every replica: the partners'
+        // configurations were gathered into bit-packed words (k_wang_gather)
+        mode = 3;
+        const int cntp = min(64, Rc - g * 64);
+        pairmask = cntp >= 64 ? ~0ull : ((1ull << cntp) - 1);
+        pbuf = wang_partner_words(R, S, REPR == PA_INT8);
+        pg = g;
     }
     uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
     uint32_t totU = 0, totD = 0, totH = 0, totK = 0;
@@ -1365,7 +1383,12 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
                 vinc(cD, w);
                 if (mode) {
                     uint64_t q, qr, qd;
-                    if (mode == 1 && sh) {
+                    if (mode == 3) {
+                        const uint64_t *pw = (const uint64_t *)pbuf + (size_t)pg * N;
+                        q = pw[n];
+                        qr = pw[nr];
+                        qd = pw[nd];
+                    } else if (mode == 1 && sh) {
                         const bool two = pg + 1 < pgroups;
                         q = (load_word<REPR>(buf, pg, n, N) >> sh) |
                             (two ? load_word<REPR>(buf, pg + 1, n, N) << (64 - sh) : 0ull);
@@ -1463,6 +1486,303 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
     case 48: measure_group<REPR, 48>(it, g, sub, wpg, live, R, S, st, red); break;
     case 64: measure_group<REPR, 64>(it, g, sub, wpg, live, R, S, st, red); break;
     default: measure_group<REPR, 0>(it, g, sub, wpg, live, R, S, st, red); break;
+    }
+}
+
+// ---------------------------------------------- permutation pairing (q)
+//
+// Sec. III D, pairings from permutations (Wang et al.), for runs with
+// PA_Q_WANG / PA_Q_WANG_RDM, before the measurement of every temperature:
+//   k_wang_pairs   one workgroup per run: the permutations and the repair;
+//   k_wang_pack    (int8 spins) a bit-packed copy of the population;
+//   k_wang_gather  the partners' configurations as bit-packed words;
+// then k_measure takes the pairs (j, pi_j) like any other overlap pairs.
+//
+// The random permutations are index orders of 64-bit Philox keys: a key's
+// top bits pick one of B >= R_i buckets (a power of two, so about one key
+// per bucket), the bucket counts are scanned into starts, the indices are
+// scattered into their buckets, and an index's rank is its bucket's start
+// plus the members of the bucket with a smaller (key, index).  The repair is
+// serial by nature: the mismatched positions are listed in search order,
+// then one wavefront takes them in turn and finds each exchange partner
+// with a 64-wide search (a ballot over consecutive candidates).  With the
+// identity search pattern the candidates inside the mismatched replica's
+// own family, which is one run of equal labels, are skipped without being
+// tested: none of them can qualify.  Data that other wavefronts wrote in
+// the same launch is read with device-coherent loads after the writers have
+// waited for their stores.
+
+constexpr int WANG_THREADS = 1024;
+
+__device__ __forceinline__ int32_t ldc(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void stc(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier after which every wavefront's earlier stores have completed.
+__device__ __forceinline__ void wg_sync_stores()
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Key of index k for the pairing at temperature i: words 0-1 (pi) or 2-3
+// (the search pattern) of Philox(seed; k, 0, i, TAG_PERM << 28).
+__device__ __forceinline__ uint64_t perm_key(int k, int i, int which, uint32_t key0, uint32_t key1)
+{
+    const u32x4 o = philox10((uint32_t)k, 0u, (uint32_t)i, TAG_PERM << 28, key0, key1);
+    return which == 0 ? ((uint64_t)o.x | ((uint64_t)o.y << 32)) : ((uint64_t)o.z | ((uint64_t)o.w << 32));
+}
+
+// Exclusive prefix over the workgroup of one value per thread; *total gets
+// the sum.  sh: 17 ints of LDS.
+__device__ int block_scan_excl(int v, int *sh, int *total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int t = sh[w];
+            sh[w] = a;
+            a += t;
+        }
+        sh[16] = a;
+    }
+    __syncthreads();
+    const int r = sh[wv] + x - v;
+    *total = sh[16];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs, const PopState *st, int run0)
+{
+    __shared__ int sh[17];
+    __shared__ int big;
+    const int run = run0 + blockIdx.x;
+    const RunInfo &R = runs[run];
+    if (!is_wang(R.overlap)) return;
+    const PopState &S = st[run * MAX_POP];
+    if (!pop_active(S)) return;
+    const int Rc = S.Rcur, i = S.i;
+    const int T = blockDim.x, tid = threadIdx.x;
+    const int32_t *fam = R.fam[0][S.cur];
+    const WangBufs W = wang_bufs(R.wang, R.R_cap, R.wang_lb);
+    const bool rdm = R.overlap == PA_Q_WANG_RDM;
+    const uint32_t key0 = R.key0, key1 = R.key1;
+    // A family of more than Rc / 2 replicas (then no valid pairing exists)
+    // covers the middle index: it is one run of equal labels.
+    if (tid == 0) {
+        const int h = Rc >> 1, f = fam[h];
+        int lo = 0, hi = h;
+        while (lo < hi) {
+            const int m = (lo + hi) >> 1;
+            if (fam[m] < f) lo = m + 1;
+            else hi = m;
+        }
+        const int first = lo;
+        lo = h + 1;
+        hi = Rc;
+        while (lo < hi) {
+            const int m = (lo + hi) >> 1;
+            if (fam[m] <= f) lo = m + 1;
+            else hi = m;
+        }
+        big = 2 * (int64_t)(lo - first) > (int64_t)Rc ? 1 : 0;
+        if (big) stc(&W.hdr[0], 1);
+    }
+    __syncthreads();
+    if (big) return;
+
+    int lbc = 1;
+    while ((1 << lbc) < Rc) ++lbc;
+    const int B = 1 << lbc, shift = 64 - lbc;
+    for (int which = 0; which < (rdm ? 2 : 1); ++which) {
+        int32_t *out = which == 0 ? W.pi : W.sigma;
+        for (int b = tid; b < B; b += T) stc(&W.cnt[b], 0);
+        wg_sync_stores();
+        for (int k = tid; k < Rc; k += T) atomicAdd(&W.cnt[perm_key(k, i, which, key0, key1) >> shift], 1);
+        wg_sync_stores();
+        const int seg = (B + T - 1) / T;
+        const int b0 = min(B, tid * seg), b1 = min(B, b0 + seg);
+        int sum = 0;
+        for (int b = b0; b < b1; ++b) sum += ldc(&W.cnt[b]);
+        int total;
+        int acc = block_scan_excl(sum, sh, &total);
+        for (int b = b0; b < b1; ++b) {
+            const int c = ldc(&W.cnt[b]);
+            stc(&W.start[b], acc);
+            stc(&W.cnt[b], acc);   // fill cursor of the bucket
+            acc += c;
+        }
+        if (tid == 0) stc(&W.start[B], Rc);
+        wg_sync_stores();
+        for (int k = tid; k < Rc; k += T) {
+            const int b = (int)(perm_key(k, i, which, key0, key1) >> shift);
+            stc(&W.members[atomicAdd(&W.cnt[b], 1)], k);
+        }
+        wg_sync_stores();
+        for (int k = tid; k < Rc; k += T) {
+            const uint64_t kk = perm_key(k, i, which, key0, key1);
+            const int b = (int)(kk >> shift);
+            const int lo = ldc(&W.start[b]), hi = ldc(&W.start[b + 1]);
+            int r = lo;
+            for (int q = lo; q < hi; ++q) {
+                const int m = ldc(&W.members[q]);
+                if (m == k) continue;
+                const uint64_t km = perm_key(m, i, which, key0, key1);
+                r += (km < kk || (km == kk && m < k)) ? 1 : 0;
+            }
+            stc(&out[r], k);
+        }
+        wg_sync_stores();
+    }
+
+    // families of the initial partners, and the mismatched positions in
+    // search order (ascending)
+    for (int k = tid; k < Rc; k += T) stc(&W.fampi[k], fam[ldc(&W.pi[k])]);
+    wg_sync_stores();
+    const int seg = (Rc + T - 1) / T;
+    const int t0 = min(Rc, tid * seg), t1 = min(Rc, t0 + seg);
+    int mine = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int k = rdm ? ldc(&W.sigma[t]) : t;
+        mine += ldc(&W.fampi[k]) == fam[k] ? 1 : 0;
+    }
+    int nlist;
+    int pos = block_scan_excl(mine, sh, &nlist);
+    for (int t = t0; t < t1; ++t) {
+        const int k = rdm ? ldc(&W.sigma[t]) : t;
+        if (ldc(&W.fampi[k]) == fam[k]) stc(&W.list[pos++], t);
+    }
+    wg_sync_stores();
+    if (tid >= 64) return;
+
+    // the repair, one wavefront
+    const int lane = tid;
+    int status = 0;
+    for (int e = 0; e < nlist; ++e) {
+        const int t = ldc(&W.list[e]);
+        const int k = rdm ? ldc(&W.sigma[t]) : t;
+        const int fk = fam[k];
+        if (ldc(&W.fampi[k]) != fk) continue;   // already matched by an earlier exchange
+        int64_t u = t + 1;
+        if (!rdm) {   // skip the rest of k's family: the first later index with another label
+            int lo = t + 1, hi = Rc;
+            while (lo < hi) {
+                const int m = (lo + hi) >> 1;
+                if (fam[m] == fk) lo = m + 1;
+                else hi = m;
+            }
+            u = lo;
+        }
+        const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
+        int found = -1;
+        for (; u < uend; u += 64) {
+            const int64_t uu = u + lane;
+            bool ok = false;
+            int m = 0;
+            if (uu < uend) {
+                const int q = (int)(uu >= Rc ? uu - Rc : uu);
+                m = rdm ? ldc(&W.sigma[q]) : q;
+                ok = fam[m] != fk && ldc(&W.fampi[m]) != fk;
+            }
+            const uint64_t bal = __ballot(ok);
+            if (bal) {
+                found = __shfl(m, __ffsll((unsigned long long)bal) - 1, 64);
+                break;
+            }
+        }
+        if (found < 0) {   // impossible with no family above Rc / 2
+            status = 2;
+            break;
+        }
+        if (lane == 0) {
+            const int pk = ldc(&W.pi[k]), pm = ldc(&W.pi[found]), fm = ldc(&W.fampi[found]);
+            stc(&W.pi[k], pm);
+            stc(&W.pi[found], pk);
+            stc(&W.fampi[k], fm);
+            stc(&W.fampi[found], fk);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    if (lane == 0) {
+        stc(&W.hdr[0], status);
+        stc(&W.hdr[1], nlist);
+    }
+}
+
+__device__ __forceinline__ bool wang_group_live(const Item &it, const RunInfo &R, const PopState &S)
+{
+    return is_wang(R.overlap) && it.pop == 0 && pop_active(S) && it.group * 64 < S.Rcur &&
+           wang_bufs(R.wang, R.R_cap, R.wang_lb).hdr[0] == 0;
+}
+
+// int8 spins: bit-packed copy [group][site] of the population (one
+// wavefront per replica group, lane = site) at the start of the spare
+// buffer, as the source of k_wang_gather.
+__global__ void __launch_bounds__(256) k_wang_pack(const Item *items, int n_items, const RunInfo *runs,
+                                                   const PopState *st)
+{
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (idx >= n_items) return;
+    const Item it = items[idx];
+    const RunInfo &R = runs[it.run];
+    const PopState &S = st[it.run * MAX_POP];
+    if (!wang_group_live(it, R, S)) return;
+    const int N = R.N, g = it.group;
+    const uint8_t *src = R.spins[0][S.cur];
+    uint64_t *dst = (uint64_t *)R.spins[0][S.cur ^ 1] + (size_t)g * N;
+    for (int n = lane; n < N; n += 64) dst[n] = load_word<PA_INT8>(src, g, n, N);
+}
+
+// Partner words: bit b of word (g, n) is the spin at site n of the partner
+// pi_j of replica j = 64 g + b.  One wavefront per group: lane b reads its
+// partner's words 64 sites at a time (the bit at position pi_j mod 64 of
+// group pi_j / 64), and a 64 x 64 transpose turns the lanes' rows into the
+// sites' words.  Lanes past R_i read replica 0 (their bits are never used).
+__global__ void __launch_bounds__(256) k_wang_gather(const Item *items, int n_items, const RunInfo *runs,
+                                                     const PopState *st, int repr)
+{
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (idx >= n_items) return;
+    const Item it = items[idx];
+    const RunInfo &R = runs[it.run];
+    const PopState &S = st[it.run * MAX_POP];
+    if (!wang_group_live(it, R, S)) return;
+    const int N = R.N, g = it.group;
+    const WangBufs W = wang_bufs(R.wang, R.R_cap, R.wang_lb);
+    const uint64_t *src = repr == PA_MSC64 ? (const uint64_t *)R.spins[0][S.cur]
+                                           : (const uint64_t *)R.spins[0][S.cur ^ 1];
+    uint64_t *dst = (uint64_t *)wang_partner_words(R, S, repr == PA_INT8) + (size_t)g * N;
+    const int j = g * 64 + lane;
+    const int p = j < S.Rcur ? W.pi[j] : 0;
+    const uint64_t *row = src + (size_t)(p >> 6) * N;   // N is even: 16-byte aligned pairs of words
+    const int bit = p & 63;
+    for (int n0 = 0; n0 < N; n0 += 64) {
+        uint64_t x = 0;
+#pragma unroll 8
+        for (int s = 0; s < 64; s += 2)
+            if (n0 + s < N) {
+                const uint4 v = *(const uint4 *)(row + n0 + s);
+                const uint64_t w0 = (uint64_t)v.x | ((uint64_t)v.y << 32), w1 = (uint64_t)v.z | ((uint64_t)v.w << 32);
+                x |= ((w0 >> bit) & 1ull) << s;
+                x |= ((w1 >> bit) & 1ull) << (s + 1);
+            }
+        const uint64_t col = transpose64(x);
+        if (n0 + lane < N) dst[n0 + lane] = col;
     }
 }
 
@@ -2040,6 +2360,17 @@ int sweep_msc_resident(int threads, size_t lds)
 
 hipError_t launch_measure(const LaunchCtx &c)
 {
+    if (c.any_wang && c.n_runs > 0) {
+        k_wang_pairs<<<c.n_runs, WANG_THREADS, 0, c.stream>>>(c.runs, c.st, c.run0);
+        PA_CHECK_LAUNCH();
+        const int blocks = (c.n_items + 3) / 4;
+        if (c.repr == PA_INT8) {
+            k_wang_pack<<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st);
+            PA_CHECK_LAUNCH();
+        }
+        k_wang_gather<<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st, c.repr);
+        PA_CHECK_LAUNCH();
+    }
     if (c.n_meas_items > 0) {
         if (c.repr == PA_MSC64)
             k_measure<PA_MSC64><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);

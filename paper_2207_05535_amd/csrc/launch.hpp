@@ -17,6 +17,7 @@ struct LaunchCtx {
     int run0, n_runs, npop_ctx;    // per-run launches cover runs [run0, run0 + n_runs)
     int repr;
     bool any_multinomial;
+    bool any_wang;                 // some run pairs replicas by permutations
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
     const SweepItem *meas_items;   // device [n_meas_items]: groups per measure workgroup
     int n_meas_items;

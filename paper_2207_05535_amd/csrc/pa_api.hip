@@ -47,7 +47,7 @@ bool desc_ok(const pa_run_desc &d, pa_repr repr)
     if (d.R < 1 || d.R_cap < d.R || d.R_cap >= (1 << 23)) return false;
     if (d.resampling != PA_MULTINOMIAL && d.resampling != PA_NEAREST_INT) return false;
     if (d.resampling == PA_MULTINOMIAL && d.R_cap != d.R) return false;
-    if (d.overlap < PA_Q_NONE || d.overlap > PA_Q_TWO_POP) return false;
+    if (d.overlap < PA_Q_NONE || d.overlap > PA_Q_WANG_RDM) return false;
     if (d.qhist != 0 && d.qhist != 1) return false;
     if (d.theta < 0 || d.theta >= (1 << 24)) return false;
     if (d.K < 2 || d.K > (1 << 20) || d.beta == nullptr) return false;
@@ -85,6 +85,7 @@ void plan_run_buffers(Planner &P, const pa_run_desc &d, pa_repr repr, RunOff &o)
     }
     o.qh = d.qhist ? P.take(sizeof(int32_t) * (size_t)npop * d.K * (N + 1)) : 0;
     o.jbits = P.take(N);
+    o.wang = is_wang(d.overlap) ? P.take(sizeof(int32_t) * wang_ints(d.R_cap)) : 0;
 }
 
 void plan_table(Planner &P, int N, const pa_run_desc &d, TableOff &T)
@@ -223,6 +224,8 @@ RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8
     I.obs = obs;
     I.qh = d.qhist ? (int32_t *)(base + o.qh) : nullptr;
     I.jbits = base + o.jbits;
+    I.wang = is_wang(d.overlap) ? (int32_t *)(base + o.wang) : nullptr;
+    I.wang_lb = wang_lb_of(d.R_cap);
     I.tabX = (const uint64_t *)(tbase + T.X);
     I.tabx = (const double *)(tbase + T.x);
     I.tabT = (const uint64_t *)(tbase + T.T);
@@ -420,6 +423,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         c->betas[r].assign(runs[r].beta, runs[r].beta + runs[r].K);
         c->descs[r].beta = c->betas[r].data();
         if (runs[r].resampling == PA_MULTINOMIAL) c->any_multinomial = true;
+        if (is_wang(runs[r].overlap)) c->any_wang = true;
     }
     // table sources must point at the context's own copies
     for (auto &t : c->lo.tables) {
@@ -466,6 +470,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.npop_ctx = Lo.npop_ctx;
     c->lc.repr = repr;
     c->lc.any_multinomial = c->any_multinomial;
+    c->lc.any_wang = c->any_wang;
     c->lc.stats = at<unsigned long long>(c, Lo.stats);
     c->lc.sweep_queue = at<unsigned int>(c, Lo.queue);
     c->lc.sweep_grid = 0;
@@ -729,6 +734,27 @@ pa_status pa_read_qhist(pa_ctx *c, int32_t run, int32_t *host_out)
     PA_HIP(c, hipMemcpyAsync(host_out, at<int32_t>(c, c->lo.runs[run].qh), sizeof(int32_t) * n,
                              hipMemcpyDeviceToHost, c->stream));
     PA_HIP(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_read_pairing(pa_ctx *c, int32_t run, int32_t *host_pairs, int32_t *status, int32_t *R_i)
+{
+    if (!c || run < 0 || run >= c->n_runs || !host_pairs) return PA_ERR_ARG;
+    const pa_run_desc &d = c->descs[run];
+    if (!is_wang(d.overlap)) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED) return PA_ERR_STATE;
+    PopState S;
+    PA_HIP(c, hipMemcpyAsync(&S, c->lc.st + (size_t)run * MAX_POP, sizeof(S), hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    const RunInfo &I = c->hinfo[run];
+    const WangBufs W = wang_bufs(I.wang, I.R_cap, I.wang_lb);
+    int32_t hdr[4];
+    PA_HIP(c, hipMemcpyAsync(hdr, W.hdr, sizeof(hdr), hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipMemcpyAsync(host_pairs, W.pi, sizeof(int32_t) * S.Rcur, hipMemcpyDeviceToHost, c->stream));
+    PA_HIP(c, hipStreamSynchronize(c->stream));
+    if (status) *status = hdr[0];
+    if (R_i) *R_i = S.Rcur;
     return PA_OK;
 }
 

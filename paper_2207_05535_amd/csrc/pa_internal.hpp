@@ -24,6 +24,7 @@ constexpr uint32_t TAG_NI = 2u;
 constexpr uint32_t TAG_MN = 3u;
 constexpr uint32_t TAG_INIT = 4u;
 constexpr uint32_t TAG_J = 5u;
+constexpr uint32_t TAG_PERM = 6u;
 
 constexpr int MAX_POP = 2;
 
@@ -52,6 +53,7 @@ struct RunInfo {
     uint32_t key0, key1;
     // record of (population p, temperature i): obs[i * obs_stride + obs_off + p]
     int32_t obs_stride, obs_off;
+    int32_t wang_lb, pad0;        // permutation pairing: log2 of the bucket capacity
     // device pointers into the caller's workspace
     uint8_t *spins[MAX_POP][2];   // int8: [group][site][64] bytes; MSC: [group][site] u64
     int32_t *E[MAX_POP][2];       // energies [R_cap]
@@ -69,6 +71,7 @@ struct RunInfo {
     pa_obs *obs;                  // records, indexed through obs_stride and obs_off
     int32_t *qh;                  // [n_pop][K][N+1] or nullptr
     uint8_t *jbits;               // [N]: bit0 = J_R(n) < 0, bit1 = J_D(n) < 0
+    int32_t *wang;                // permutation pairing scratch (see WangBufs) or nullptr
     const uint64_t *tabX;         // [K][N+1]  floor(exp(-dbeta_i 4k) 2^40)
     const double *tabx;           // [K][N+1]  exp(-dbeta_i 4k)
     const uint64_t *tabT;         // [K][2]    Metropolis thresholds for dE = 4, 8
@@ -113,5 +116,37 @@ struct ChunkItem {    // one chunk of CH replicas of one (run, pop)
 };
 
 __host__ __device__ inline int n_pop_of(int overlap) { return overlap == PA_Q_TWO_POP ? 2 : 1; }
+__host__ __device__ inline bool is_wang(int overlap) { return overlap == PA_Q_WANG || overlap == PA_Q_WANG_RDM; }
+
+// Permutation-pairing scratch of a run (int32 units), B = 2^wang_lb >= R_cap:
+// pi, sigma, fam[pi], bucket members, mismatch list [R_cap] each; bucket
+// counts [B]; bucket starts [B + 1]; header [4] (status: 0 paired, 1 a
+// family above R_i / 2, 2 no partner found; mismatch count).
+__host__ __device__ inline int wang_lb_of(int R_cap)
+{
+    int lb = 1;
+    while ((1 << lb) < R_cap) ++lb;
+    return lb;
+}
+__host__ __device__ inline size_t wang_ints(int R_cap)
+{
+    return 5 * (size_t)R_cap + 2 * ((size_t)1 << wang_lb_of(R_cap)) + 1 + 4;
+}
+struct WangBufs {
+    int32_t *pi, *sigma, *fampi, *members, *list, *cnt, *start, *hdr;
+};
+__host__ __device__ inline WangBufs wang_bufs(int32_t *w, int R_cap, int lb)
+{
+    WangBufs b;
+    b.pi = w;
+    b.sigma = b.pi + R_cap;
+    b.fampi = b.sigma + R_cap;
+    b.members = b.fampi + R_cap;
+    b.list = b.members + R_cap;
+    b.cnt = b.list + R_cap;
+    b.start = b.cnt + ((size_t)1 << lb);
+    b.hdr = b.start + ((size_t)1 << lb) + 1;
+    return b;
+}
 
 }  // namespace pa

@@ -238,7 +238,7 @@ pa_status rebuild(pa_server *s)
 {
     size_t n_items = 0, n_chunks = 0, n_meas = 0;
     int hi = 0, npop_ctx = 1;
-    bool mn = false;
+    bool mn = false, wang = false;
     std::vector<SweepItem> sweep;
     size_t lds = 0;
     for (int k = 0; k < s->max_slots; ++k) {
@@ -251,6 +251,7 @@ pa_status rebuild(pa_server *s)
         hi = k + 1;
         npop_ctx = std::max(npop_ctx, npop);
         mn = mn || sl.d.resampling == PA_MULTINOMIAL;
+        wang = wang || is_wang(sl.d.overlap);
         if (s->repr == PA_MSC64) {
             const int G = groups_of(s, sl.d.L);
             const int N = sl.d.L * sl.d.L;
@@ -303,6 +304,7 @@ pa_status rebuild(pa_server *s)
     c.n_runs = hi;
     c.npop_ctx = npop_ctx;
     c.any_multinomial = mn;
+    c.any_wang = wang;
     c.sweep_items = (const SweepItem *)(s->base + s->sweep_off);
     c.n_sweep_items = (int)sweep.size();
     c.sweep_threads = s->threads;
@@ -520,6 +522,7 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     c.n_runs = 1;
     c.npop_ctx = npop;
     c.any_multinomial = d.resampling == PA_MULTINOMIAL;
+    c.any_wang = is_wang(d.overlap);
     if (launch_init(c, (const uint64_t *)(blk + b.dseed)) != hipSuccess || launch_measure(c) != hipSuccess)
         return sfail(s);
     s->dirty = true;

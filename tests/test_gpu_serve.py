@@ -30,8 +30,9 @@ def say(msg):
 
 
 def mixed_trace():
-    """Nine requests of several sizes, models, resampling kinds, overlap
-    estimators and schedule lengths, with staggered arrivals."""
+    """Eleven requests of several sizes, models, resampling kinds, overlap
+    estimators (permutation pairing among them) and schedule lengths, with
+    staggered arrivals."""
     specs = [
         (8, W.FM, W.MULTINOMIAL, W.Q_NONE, 12, 300),
         (12, W.EA_PMJ, W.NEAREST_INT, W.Q_INDEX_SHIFT, 9, 500),
@@ -42,6 +43,8 @@ def mixed_trace():
         (24, W.EA_PMJ, W.MULTINOMIAL, W.Q_INDEX_SHIFT, 6, 400),
         (6, W.EA_PMJ, W.NEAREST_INT, W.Q_TWO_POP, 13, 250),
         (32, W.FM, W.MULTINOMIAL, W.Q_INDEX_SHIFT, 5, 200),
+        (12, W.EA_PMJ, W.MULTINOMIAL, W.Q_WANG_RDM, 10, 300),
+        (10, W.FM, W.NEAREST_INT, W.Q_WANG, 8, 260),
     ]
     out = []
     for q, (L, model, rs, ov, K, R) in enumerate(specs):
