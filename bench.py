@@ -295,6 +295,50 @@ def run_serving(trace, arena_bytes, max_slots, rate=20.0):
     }
 
 
+def run_q_estimators(M=16, K=61):
+    """Overlap estimators of Sec. III D side by side on one synthetic +-J
+    sample (L=32, R=2e4, theta=10, beta 0->2.4): M runs per estimator in one
+    context; per step the whole-step and measurement times (the pairing
+    kernels run inside the measurement), and at the last temperature the
+    share of runs left out for a family above R_i/2 (Table I) and the
+    weighted |q| and q^2 with those runs excluded."""
+    import torch
+
+    import paper_2207_05535_amd as pa
+    import workloads as W
+
+    out = {"workload": f"{M} runs of EA +-J L=32 on one disorder sample per estimator, R=20000, "
+                       f"beta 0->2.4 in {K} points, theta=10, multinomial"}
+    for name, ov in (("index_shift", W.Q_INDEX_SHIFT), ("two_populations", W.Q_TWO_POP),
+                     ("permutation", W.Q_WANG), ("permutation_random_search", W.Q_WANG_RDM)):
+        runs = W.q_comparison_runs(M, overlap=ov, K=K)
+        ctx = pa.Context(runs, "msc")
+        tune(ctx, "cache")
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K - 1)]
+        for k, i in enumerate(range(1, K)):
+            a, b, c = evs[k]
+            a.record()
+            ctx.anneal_step(i)
+            ctx.resample(i)
+            ctx.sweep(i)
+            b.record()
+            ctx.measure(i)
+            c.record()
+        torch.cuda.synchronize()
+        step_ms = sum(a.elapsed_time(c) for a, _, c in evs) / (K - 1)
+        meas_ms = sum(b.elapsed_time(c) for _, b, c in evs) / (K - 1)
+        fs = ctx.family_stats(0)
+        wa = ctx.weighted_average(M, pa.PA_W_FULL | pa.PA_W_EXCLUDE_LARGE_FAMILY, 0)[0][K - 1]
+        out[name] = {"ms_per_step": round(step_ms, 4), "measure_ms_per_step": round(meas_ms, 4),
+                     "excluded_fraction_last": float(fs["excluded"][:, K - 1].mean()),
+                     "W_absq_last": float(wa["W_absq"]), "W_q2_last": float(wa["W_q2"]),
+                     "runs_included_last": int(M - fs["excluded"][:, K - 1].sum())}
+        ctx.close()
+        log(f"q estimators: {name} {out[name]}")
+    return out
+
+
 def cpu_baseline(desc, max_seconds=20.0):
     """The oracle (single-threaded C, as it stands) on a bounded sample of
     the same workload: R = 2000 of the 1e5 replicas, the same lattice, theta
@@ -324,8 +368,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving",
-                    help="comma-separated subset of headline,plain,two_pop,batched,serving "
+    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving,q_estimators",
+                    help="comma-separated subset of headline,plain,two_pop,batched,serving,q_estimators "
                          "(for profiling runs; the headline value is null when it is left out)")
     ap.add_argument("--extra-steps", type=int, default=0,
                     help="temperature steps of the two_pop and batched workloads (0: whole schedule)")
@@ -394,6 +438,9 @@ def main():
         trace = W.serving_trace()
         log(f"serving: {len(trace)} requests")
         line["serving"] = run_serving(trace, 4 << 30, args.serving_slots, args.serving_rate)
+    if "q_estimators" in only:
+        log("overlap estimators: index shift, two populations, permutation pairing")
+        line["q_estimators"] = run_q_estimators()
     if not args.no_cpu_baseline and "headline" in only:
         log("cpu baseline: oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(desc)

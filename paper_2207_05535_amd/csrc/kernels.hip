@@ -1670,9 +1670,15 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
     wg_sync_stores();
     if (tid >= 64) return;
 
-    // the repair, one wavefront
+    // the repair, one wavefront.  With the identity pattern the mismatches
+    // of one family come one after the other, and a candidate that failed
+    // for one of them fails for the next as well (exchanges only hand this
+    // family's replicas to candidates), so the search resumes after the
+    // previous partner (unwrapped candidate index prev_u).
     const int lane = tid;
     int status = 0;
+    int prev_f = -1;
+    int64_t prev_u = 0;
     for (int e = 0; e < nlist; ++e) {
         const int t = ldc(&W.list[e]);
         const int k = rdm ? ldc(&W.sigma[t]) : t;
@@ -1687,6 +1693,7 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                 else hi = m;
             }
             u = lo;
+            if (fk == prev_f && prev_u + 1 > u) u = prev_u + 1;
         }
         const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
         int found = -1;
@@ -1701,7 +1708,9 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
             }
             const uint64_t bal = __ballot(ok);
             if (bal) {
-                found = __shfl(m, __ffsll((unsigned long long)bal) - 1, 64);
+                const int first = __ffsll((unsigned long long)bal) - 1;
+                found = __shfl(m, first, 64);
+                prev_u = u + first;
                 break;
             }
         }
@@ -1709,6 +1718,7 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
             status = 2;
             break;
         }
+        prev_f = fk;
         if (lane == 0) {
             const int pk = ldc(&W.pi[k]), pm = ldc(&W.pi[found]), fm = ldc(&W.fampi[found]);
             stc(&W.pi[k], pm);

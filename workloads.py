@@ -111,6 +111,15 @@ def batched_fm_uneven(n_per_L: int = 1024, Ls=(8, 16, 24, 32), R=2000, K=150,
     return runs
 
 
+def q_comparison_runs(M: int = 16, overlap=Q_INDEX_SHIFT, L=32, R=20_000, K=61, beta_f=2.4,
+                      sample: int = 0) -> list[dict]:
+    """M runs on one EA +-J disorder sample for comparing overlap estimators
+    (Sec. III D): L=32, R=2e4, theta=10, beta 0->2.4, multinomial."""
+    return [run_desc(L, EA_PMJ, seed=RUN_SEED_BASE + 0x200000 + m,
+                     disorder_seed=DISORDER_SEED_BASE + 0x3200 + sample, R=R, theta=10, K=K,
+                     beta_f=beta_f, overlap=overlap, qhist=1) for m in range(M)]
+
+
 def serving_trace(n_requests: int = 500, rate_per_s: float = 20.0,
                   Ls=(16, 24, 32, 48, 64), R=50_000, K=201, trace_seed=0xA110000):
     """Poisson arrival trace of EA +-J requests: list of (t_arrival_s, desc).
