@@ -1670,63 +1670,88 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
     wg_sync_stores();
     if (tid >= 64) return;
 
-    // the repair, one wavefront.  With the identity pattern the mismatches
-    // of one family come one after the other, and a candidate that failed
-    // for one of them fails for the next as well (exchanges only hand this
-    // family's replicas to candidates), so the search resumes after the
-    // previous partner (unwrapped candidate index prev_u).
+    // The repair, one wavefront, over the list in batches of 64 entries.
+    // What does not change during the repair (position, its place in the
+    // search order, its family, the end of its family's run of labels, its
+    // initial partner) is loaded for a whole batch at once; an entry is
+    // still open unless an earlier exchange in this repair took its
+    // position as the partner (an exchange leaves both of its positions
+    // matched for good), which the lanes track by comparing positions.
+    // With the identity pattern the mismatches of one family come one after
+    // the other, and a candidate that failed for one of them fails for the
+    // next as well (exchanges only hand this family's replicas to
+    // candidates), so the search resumes after the previous partner
+    // (unwrapped candidate index prev_u).
     const int lane = tid;
     int status = 0;
     int prev_f = -1;
     int64_t prev_u = 0;
-    for (int e = 0; e < nlist; ++e) {
-        const int t = ldc(&W.list[e]);
-        const int k = rdm ? ldc(&W.sigma[t]) : t;
-        const int fk = fam[k];
-        if (ldc(&W.fampi[k]) != fk) continue;   // already matched by an earlier exchange
-        int64_t u = t + 1;
-        if (!rdm) {   // skip the rest of k's family: the first later index with another label
-            int lo = t + 1, hi = Rc;
-            while (lo < hi) {
-                const int m = (lo + hi) >> 1;
-                if (fam[m] == fk) lo = m + 1;
-                else hi = m;
+    for (int e0 = 0; e0 < nlist && status == 0; e0 += 64) {
+        const int e = e0 + lane;
+        int t_l = 0, k_l = -1, f_l = 0, hi_l = 0, p_l = 0;
+        bool open_l = false;
+        if (e < nlist) {
+            t_l = ldc(&W.list[e]);
+            k_l = rdm ? ldc(&W.sigma[t_l]) : t_l;
+            f_l = fam[k_l];
+            open_l = ldc(&W.fampi[k_l]) == f_l;
+            p_l = ldc(&W.pi[k_l]);
+            if (!rdm) {   // the first later index with another label
+                int lo = t_l + 1, hi = Rc;
+                while (lo < hi) {
+                    const int m = (lo + hi) >> 1;
+                    if (fam[m] == f_l) lo = m + 1;
+                    else hi = m;
+                }
+                hi_l = lo;
             }
-            u = lo;
-            if (fk == prev_f && prev_u + 1 > u) u = prev_u + 1;
         }
-        const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
-        int found = -1;
-        for (; u < uend; u += 64) {
-            const int64_t uu = u + lane;
-            bool ok = false;
-            int m = 0;
-            if (uu < uend) {
-                const int q = (int)(uu >= Rc ? uu - Rc : uu);
-                m = rdm ? ldc(&W.sigma[q]) : q;
-                ok = fam[m] != fk && ldc(&W.fampi[m]) != fk;
+        const int nb = min(64, nlist - e0);
+        for (int j = 0; j < nb; ++j) {
+            if (!__shfl((int)open_l, j, 64)) continue;
+            const int t = __shfl(t_l, j, 64), k = __shfl(k_l, j, 64), fk = __shfl(f_l, j, 64);
+            const int pk = __shfl(p_l, j, 64);
+            int64_t u = t + 1;
+            if (!rdm) {
+                u = __shfl(hi_l, j, 64);
+                if (fk == prev_f && prev_u + 1 > u) u = prev_u + 1;
             }
-            const uint64_t bal = __ballot(ok);
-            if (bal) {
-                const int first = __ffsll((unsigned long long)bal) - 1;
-                found = __shfl(m, first, 64);
-                prev_u = u + first;
+            const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
+            int found = -1, fm = 0;
+            for (; u < uend; u += 64) {
+                const int64_t uu = u + lane;
+                bool ok = false;
+                int m = 0, fpm = 0;
+                if (uu < uend) {
+                    const int q = (int)(uu >= Rc ? uu - Rc : uu);
+                    m = rdm ? ldc(&W.sigma[q]) : q;
+                    fpm = ldc(&W.fampi[m]);
+                    ok = fam[m] != fk && fpm != fk;
+                }
+                const uint64_t bal = __ballot(ok);
+                if (bal) {
+                    const int first = __ffsll((unsigned long long)bal) - 1;
+                    found = __shfl(m, first, 64);
+                    fm = __shfl(fpm, first, 64);
+                    prev_u = u + first;
+                    break;
+                }
+            }
+            if (found < 0) {   // impossible with no family above Rc / 2
+                status = 2;
                 break;
             }
+            if (lane == 0) {
+                const int pm = ldc(&W.pi[found]);
+                stc(&W.pi[k], pm);
+                stc(&W.pi[found], pk);
+                stc(&W.fampi[k], fm);
+                stc(&W.fampi[found], fk);
+            }
+            if (k_l == found) open_l = false;
+            prev_f = fk;
+            __builtin_amdgcn_s_waitcnt(0);
         }
-        if (found < 0) {   // impossible with no family above Rc / 2
-            status = 2;
-            break;
-        }
-        prev_f = fk;
-        if (lane == 0) {
-            const int pk = ldc(&W.pi[k]), pm = ldc(&W.pi[found]), fm = ldc(&W.fampi[found]);
-            stc(&W.pi[k], pm);
-            stc(&W.pi[found], pk);
-            stc(&W.fampi[k], fm);
-            stc(&W.fampi[found], fk);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
     }
     if (lane == 0) {
         stc(&W.hdr[0], status);
