@@ -77,6 +77,8 @@ def lib():
         L.or_reweight_X.restype = C.c_uint64
         L.or_sweep_draw.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_sweep_draw.restype = C.c_uint32
+        L.or_exact_dos.argtypes = [C.c_int, vp]
+        L.or_exact_dos.restype = C.c_int
         L.or_random_permutation.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, vp]
         L.or_random_permutation.restype = C.c_int
         L.or_wang_repair.argtypes = [vp, C.c_int, vp, vp]
@@ -247,6 +249,16 @@ FAMSTAT_DTYPE = np.dtype([("rho_t", np.float64), ("R_i", np.int32), ("famMax", n
                           ("large", np.int32), ("excluded", np.int32)])
 
 EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into `kind`
+
+
+def exact_dos(L):
+    """Exact density of states of the periodic L x L ferromagnet (L <= 8):
+    g[m] = number of configurations with E = -2N + 4m, as Python ints."""
+    N = L * L
+    raw = np.zeros(2 * (N + 1), np.uint64)
+    st = lib().or_exact_dos(L, _ptr(raw))
+    assert st == OK, st
+    return [int(raw[2 * m]) | (int(raw[2 * m + 1]) << 64) for m in range(N + 1)]
 
 
 def random_permutation(seed, i, pop, R, which=0):

@@ -50,7 +50,9 @@ typedef struct {
     uint64_t disorder_seed; /* Philox key for the couplings (spin glass) */
     int32_t R;              /* target population size */
     int32_t R_cap;          /* capacity (>= R) */
-    int32_t theta;          /* sweeps per temperature */
+    int32_t theta;          /* sweeps per temperature; -1: theta = infinity, the
+                               energies drawn from the exact distribution
+                               at beta_i (ferromagnet, L <= 8, no overlaps) */
     int32_t K;              /* number of temperatures beta[0..K-1] */
     const double *beta;     /* annealing schedule, beta[0] = 0 */
     int32_t resampling;     /* 0 = multinomial, 1 = nearest integer */
@@ -79,7 +81,7 @@ typedef struct {            /* one per temperature of a group of runs */
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_CAPACITY = 3, OR_ERR_STATE = 4,
        OR_ERR_NUMERIC = 5 };
 
-enum { TAG_SWEEP = 1u, TAG_NI = 2u, TAG_MN = 3u, TAG_INIT = 4u, TAG_J = 5u, TAG_PERM = 6u };
+enum { TAG_SWEEP = 1u, TAG_NI = 2u, TAG_MN = 3u, TAG_INIT = 4u, TAG_J = 5u, TAG_PERM = 6u, TAG_DOS = 7u };
 
 enum { PH_MEASURED = 0, PH_ANNEALED = 1, PH_RESAMPLED = 2, PH_SWEPT = 3 };
 
@@ -108,6 +110,7 @@ typedef struct {
     or_obs *obs;            /* [npop][K] */
     int32_t *qh;            /* [npop][K][N+1] or NULL */
     double *rho;            /* [npop][K] mean square family size, Eq. (rho_t) */
+    uint64_t *dosC;         /* theta = infinity: energy draw thresholds [K][N+1] */
     int i, phase;
     int64_t e_mismatch;     /* tracked-vs-recomputed energy mismatches seen */
 } or_run;
@@ -228,8 +231,112 @@ void or_destroy(or_run *run)
         free(run->pop[p].X);
     }
     free(run->jR); free(run->jD);
-    free(run->beta); free(run->obs); free(run->qh); free(run->rho);
+    free(run->beta); free(run->obs); free(run->qh); free(run->rho); free(run->dosC);
     free(run);
+}
+
+/* ------------------------------------------ theta = infinity limit -- */
+
+/* Exact density of states of the periodic L x L ferromagnet, the input of
+ * the theta = infinity limit (Sec. V B: simple sampling of the exact energy
+ * distribution): g[m] = number of configurations with E = -2N + 4m,
+ * m = 0..N.  Written as Z = Tr T^L over rows, with integer weights in the
+ * number u of unsatisfied bonds (E = -2N + 2u): a row s carries its
+ * unsatisfied horizontal bonds h(s), and two neighbouring rows s, s' the
+ * vertical ones, the Hamming distance of s and s'.  The Hamming factor
+ * y^d(s, s') is the product over columns of (1 if equal, y if not), applied
+ * one column at a time.  For each first row, the rows 2..L are added one
+ * after the other and the last row is closed onto the first; polynomials in
+ * y are exact 128-bit integer coefficient arrays (L <= 8).  Odd u never
+ * occurs on the periodic lattice. */
+typedef unsigned __int128 u128;
+
+static int row_unsat(int s, int L)
+{
+    int h = 0;
+    for (int x = 0; x < L; x++) h += ((s >> x) & 1) != ((s >> ((x + 1) % L)) & 1);
+    return h;
+}
+
+int or_exact_dos(int L, uint64_t *out /* [N+1][2]: low, high 64 bits of g[m] */)
+{
+    if (L < 4 || L > 8 || (L & 1) || !out) return OR_ERR_ARG;
+    const int N = L * L, U = 2 * N + 1, S = 1 << L;
+    u128 *v = (u128 *)calloc((size_t)S * U, sizeof(u128));
+    u128 *w = (u128 *)calloc((size_t)S * U, sizeof(u128));
+    u128 *z = (u128 *)calloc((size_t)U, sizeof(u128));
+    for (int s1 = 0; s1 < S; s1++) {
+        memset(v, 0, sizeof(u128) * S * U);
+        v[(size_t)s1 * U + row_unsat(s1, L)] = 1;
+        for (int r = 1; r <= L; r++) {
+            /* vertical bonds to the next row (for r = L: back to row 1) */
+            for (int b = 0; b < L; b++) {
+                for (int s = 0; s < S; s++)
+                    for (int u = 0; u < U; u++) {
+                        u128 a = v[(size_t)s * U + u];
+                        if (u > 0) a += v[(size_t)(s ^ (1 << b)) * U + u - 1];
+                        w[(size_t)s * U + u] = a;
+                    }
+                u128 *t = v; v = w; w = t;
+            }
+            if (r == L) break;
+            /* the new row's horizontal bonds */
+            for (int s = 0; s < S; s++) {
+                int h = row_unsat(s, L);
+                for (int u = U - 1; u >= 0; u--) v[(size_t)s * U + u] = u >= h ? v[(size_t)s * U + u - h] : 0;
+            }
+        }
+        for (int u = 0; u < U; u++) z[u] += v[(size_t)s1 * U + u];   /* closed onto row 1 = s1 */
+    }
+    for (int m = 0; m <= N; m++) {
+        out[2 * m] = (uint64_t)z[2 * m];
+        out[2 * m + 1] = (uint64_t)(z[2 * m] >> 64);
+    }
+    free(v); free(w); free(z);
+    return OR_OK;
+}
+
+/* Energy draw table at inverse temperature beta: weights
+ * w_m = g_m exp(-4 beta m) (relative to the ground state) in FP64, g_m
+ * rounded to the nearest double; cumulative S_m in increasing m; threshold
+ * C_m = floor(2^64 S_m / S_N), or 2^64 - 1 where S_m / S_N = 1.  A uniform
+ * 64-bit draw v selects the smallest m with v < C_m, or m = N if there is
+ * none, so level m is drawn with probability w_m / S_N up to 2^-64 per
+ * level. */
+static void dos_table(const uint64_t *g2, int N, double beta, uint64_t *C)
+{
+    double *S = (double *)malloc(sizeof(double) * (N + 1));
+    double acc = 0.0;
+    for (int m = 0; m <= N; m++) {
+        u128 gm = ((u128)g2[2 * m + 1] << 64) | g2[2 * m];
+        acc += (double)gm * exp(-4.0 * beta * (double)m);
+        S[m] = acc;
+    }
+    for (int m = 0; m <= N; m++) {
+        double q = S[m] / acc;
+        C[m] = q >= 1.0 ? UINT64_MAX : (uint64_t)ldexp(q, 64);
+    }
+    free(S);
+}
+
+/* Step (iv) at theta = infinity: every replica's energy is replaced by an
+ * independent draw from the exact distribution at beta_i; the draw of
+ * replica j is v = o0 | o1 << 32 of Philox(seed; j, 0, i, TAG_DOS << 28 |
+ * pop << 24).  The configurations are not used in this limit. */
+static void dos_sample(or_run *run, int p, int i)
+{
+    or_pop *P = &run->pop[p];
+    const int N = run->N;
+    const uint64_t *C = &run->dosC[(size_t)i * (N + 1)];
+    for (int j = 0; j < P->Rcur; j++) {
+        uint32_t o[4];
+        philox_at(run->key, (uint32_t)j, 0, (uint32_t)i, (TAG_DOS << 28) | ((uint32_t)p << 24), o);
+        uint64_t v = (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+        int m = N;
+        for (int k = 0; k <= N; k++)
+            if (v < C[k]) { m = k; break; }
+        P->E[P->cur][j] = -2 * N + 4 * m;
+    }
 }
 
 /* Step (i): draw R_0 = R configurations from the uniform distribution at
@@ -240,11 +347,12 @@ void or_destroy(or_run *run)
 or_run *or_create(const or_desc *d)
 {
     if (!d || d->L < 4 || (d->L & 1) || d->L > 1024 || d->R < 1 || d->R_cap < d->R ||
-        d->theta < 0 || d->K < 2 || !d->beta || d->model < 0 || d->model > 1 ||
+        d->theta < -1 || d->K < 2 || !d->beta || d->model < 0 || d->model > 1 ||
         d->resampling < 0 || d->resampling > 1 || d->overlap < 0 || d->overlap > 4 ||
         d->R_cap >= (1 << 23))
         return NULL;
     if (d->resampling == 0 && d->R_cap != d->R) return NULL;
+    if (d->theta == -1 && (d->model != 0 || d->L > 8 || d->overlap != 0)) return NULL;
     or_run *run = (or_run *)calloc(1, sizeof(or_run));
     run->d = *d;
     run->N = d->L * d->L;
@@ -307,6 +415,13 @@ or_run *or_create(const or_desc *d)
         }
     }
     run->obs = (or_obs *)calloc((size_t)run->npop * d->K, sizeof(or_obs));
+    if (d->theta == -1) {
+        uint64_t *g2 = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (N + 1));
+        or_exact_dos(L, g2);
+        run->dosC = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)d->K * (N + 1));
+        for (int k = 0; k < d->K; k++) dos_table(g2, N, run->beta[k], &run->dosC[(size_t)k * (N + 1)]);
+        free(g2);
+    }
     run->rho = (double *)malloc(sizeof(double) * run->npop * d->K);
     for (int k = 0; k < run->npop * d->K; k++) run->rho[k] = NAN;
     if (d->qhist)
@@ -531,6 +646,10 @@ int or_sweep(or_run *run, int i)
     uint64_t T8 = or_sweep_threshold(run->beta[i], 8);
     for (int p = 0; p < run->npop; p++) {
         if (run->pop[p].status != OR_OK) continue;
+        if (run->d.theta == -1) {
+            dos_sample(run, p, i);
+            continue;
+        }
         for (int g = 0; g * 64 < run->pop[p].Rcur; g++) sweep_group(run, p, i, g, T4, T8);
     }
     run->phase = PH_SWEPT;
@@ -740,6 +859,14 @@ static int measure_impl(or_run *run, int i)
         int32_t Emin = 0;
         for (int j = 0; j < Ri; j++) {
             const int8_t *sj = &S[(size_t)j * N];
+            if (run->d.theta == -1) {   /* energies only (theta = infinity) */
+                int32_t e = i == 0 ? energy_of(run, sj) : E[j];
+                E[j] = e;
+                o->sumE += e;
+                o->sumE2 += (int64_t)e * e;
+                if (j == 0 || e < Emin) Emin = e;
+                continue;
+            }
             int32_t e = energy_of(run, sj);
             if (e != E[j]) run->e_mismatch++;
             E[j] = e;
