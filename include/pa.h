@@ -88,13 +88,33 @@ typedef struct {
     uint64_t disorder_seed; /* couplings of PA_EA_PMJ; ignored for PA_FM */
     int32_t R;              /* target population size, >= 1 */
     int32_t R_cap;          /* capacity, R <= R_cap < 2^23; == R for multinomial */
-    int32_t theta;          /* Metropolis sweeps per temperature, 0 <= theta < 2^24 */
+    int32_t theta;          /* Metropolis sweeps per temperature, 0 <= theta < 2^24, or
+                               PA_THETA_EXACT (see below) */
     int32_t K;              /* number of temperatures, K >= 2 */
     const double *beta;     /* host [K]: schedule, beta[0] == 0, finite; copied */
     int32_t resampling;     /* PA_MULTINOMIAL or PA_NEAREST_INT */
     int32_t overlap;        /* PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP, PA_Q_WANG or PA_Q_WANG_RDM */
     int32_t qhist;          /* 1: keep an overlap histogram per temperature */
 } pa_run_desc;
+
+/* theta = PA_THETA_EXACT is the theta = infinity limit of Sec. V B: step
+ * (iv) replaces every replica's energy by an independent draw from the
+ * exact energy distribution g(E) exp(-beta_i E) / Z of the periodic
+ * ferromagnet (model PA_FM, L <= 10, overlap PA_Q_NONE).  g comes from
+ * pa_exact_dos; the draw of replica j is v = o0 | o1 << 32 of
+ * Philox(seed; j, 0, i, 7 << 28 | pop << 24), and the level is the smallest
+ * m with v < C_m, C_m = floor(2^64 S_m / S_N) (2^64 - 1 where S_m = S_N),
+ * S_m = sum_{k <= m} (double)g_k exp(-4 beta_i k) in FP64 in increasing k;
+ * m = N if there is none.  Only energies are followed: the records' |M|
+ * and M^2 sums are zero and the configurations are not updated. */
+enum { PA_THETA_EXACT = -1 };
+
+/* Exact density of states of the periodic L x L ferromagnet (host
+ * computation, no device): host_out[2m], host_out[2m + 1] receive the low
+ * and high 64 bits of g_m, the number of configurations with
+ * E = -2N + 4m, m = 0..N (N = L^2).  L even, 4 <= L <= 10 (PA_ERR_ARG
+ * otherwise).  Used by the theta = infinity limit; cached per L. */
+pa_status pa_exact_dos(int32_t L, uint64_t *host_out);
 
 /* One record per (run, population, temperature i): integer sums over the
  * population at beta_i (Eqs. (PopAvrg), (e), (m), (c), (chi)), overlaps

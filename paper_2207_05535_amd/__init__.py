@@ -23,6 +23,7 @@ PA_INT8, PA_MSC64 = 0, 1
 PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP, PA_Q_WANG, PA_Q_WANG_RDM = 0, 1, 2, 3, 4
 PA_W_FULL, PA_W_SIMPLE = 0, 1
 PA_W_EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into a weight kind
+PA_THETA_EXACT = -1             # theta = infinity: energies drawn from the exact distribution
 
 REPRS = {"int8": PA_INT8, "msc": PA_MSC64, PA_INT8: PA_INT8, PA_MSC64: PA_MSC64}
 
@@ -84,6 +85,7 @@ def lib():
             "pa_read_qhist": [vp, i32, vp],
             "pa_read_state": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
             "pa_read_pairing": [vp, i32, vp, vp, vp],
+            "pa_exact_dos": [i32, vp],
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
             "pa_set_tuning": [vp, i32, i32, i32, i32],
@@ -213,6 +215,15 @@ def pa_read_obs(h, out):
 
 def pa_read_qhist(h, run, out):
     _chk("pa_read_qhist", lib().pa_read_qhist(h, run, _p(out)), h)
+
+
+def pa_exact_dos(L):
+    """Exact density of states of the periodic L x L ferromagnet (L <= 10):
+    g[m] = number of configurations with E = -2N + 4m, as Python ints."""
+    N = L * L
+    raw = np.zeros(2 * (N + 1), np.uint64)
+    _chk("pa_exact_dos", lib().pa_exact_dos(L, _p(raw)))
+    return [int(raw[2 * m]) | (int(raw[2 * m + 1]) << 64) for m in range(N + 1)]
 
 
 def pa_read_pairing(h, run, out):

@@ -31,7 +31,7 @@ struct Planner {
 struct RunOff {
     size_t spins[MAX_POP][2], E[MAX_POP][2], fam[MAX_POP][2], r[MAX_POP], C[MAX_POP], parent[MAX_POP],
         P[MAX_POP], part[MAX_POP], partS[MAX_POP], tot64[MAX_POP], base64[MAX_POP], tot32[MAX_POP],
-        base32[MAX_POP], qh, jbits, wang;
+        base32[MAX_POP], qh, jbits, wang, dos;
     int table;
 };
 
@@ -65,6 +65,9 @@ void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::
 RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8_t *tbase, const TableOff &T,
                      pa_obs *obs, int obs_stride, int obs_off);
 PopState initial_popstate(const pa_run_desc &d);
+// theta = infinity: energy draw thresholds [K][N+1] of a run (see pa.h);
+// false if the density of states is not available for its L.
+bool dos_thresholds(const pa_run_desc &d, std::vector<uint64_t> &out);
 // Measure items of one (run, pop): 4 / waves-per-group consecutive groups each.
 void meas_items_of(const pa_run_desc &d, int run, int pop, std::vector<SweepItem> &out);
 inline int n_meas_items_of(const pa_run_desc &d)
@@ -103,6 +106,7 @@ struct pa_ctx {
     std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
     bool any_multinomial = false;
     bool any_wang = false;
+    bool any_exact_dos = false;
     hipError_t last = hipSuccess;
 };
 

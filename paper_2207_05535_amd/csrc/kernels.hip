@@ -1358,6 +1358,28 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
         pbuf = wang_partner_words(R, S, REPR == PA_INT8);
         pg = g;
     }
+    if (R.exact_dos && S.i > 0) {
+        // theta = infinity: the energies were drawn (k_dos_sample); only
+        // their sums and minimum are recorded.  One barrier, as below.
+        __syncthreads();
+        if (!live || sub != 0) return;
+        const int j = g * 64 + lane;
+        const bool valid = j < Rc;
+        const int64_t E = valid ? R.E[it.pop][S.cur][j] : 0;
+        int64_t part[MEAS_PART];
+        part[0] = wave_sum<int64_t>(E);
+        part[1] = wave_sum<int64_t>(E * E);
+        for (int k = 2; k < MEAS_PART - 1; ++k) part[k] = 0;
+        part[MEAS_PART - 1] = wave_min(valid ? (int)E : INT32_MAX);
+        if (lane < MEAS_PART) {
+            int64_t mine = 0;
+#pragma unroll
+            for (int k = 0; k < MEAS_PART; ++k)
+                if (lane == k) mine = part[k];
+            R.part[it.pop][(size_t)g * MEAS_PART + lane] = mine;
+        }
+        return;
+    }
     uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
     uint32_t totU = 0, totD = 0, totH = 0, totK = 0;
     // every lane of the wavefront runs the same iterations (flushes are
@@ -1432,7 +1454,7 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     const int j = g * 64 + lane;
     const bool valid = j < Rc;
     const int64_t E = 2 * (int64_t)U - 2 * (int64_t)N;
-    const int64_t M = (int64_t)N - 2 * (int64_t)D;
+    const int64_t M = R.exact_dos ? 0 : (int64_t)N - 2 * (int64_t)D;   // energies only at theta = infinity
     if (valid) R.E[it.pop][S.cur][j] = (int32_t)E;
     const int64_t v = valid ? 1 : 0;
     const bool pair = mode && ((pairmask >> lane) & 1u);
@@ -1487,6 +1509,39 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
     case 64: measure_group<REPR, 64>(it, g, sub, wpg, live, R, S, st, red); break;
     default: measure_group<REPR, 0>(it, g, sub, wpg, live, R, S, st, red); break;
     }
+}
+
+// ----------------------------------------------- theta = infinity draws
+//
+// Step (iv) in the theta = infinity limit (Sec. V B): every replica's energy
+// is an independent draw from the exact distribution at beta_i.  One thread
+// per replica (a wavefront per replica group): a 64-bit Philox draw and a
+// binary search over the level thresholds C[i][0..N] (non-decreasing) for
+// the first level with v < C_m, the top level if there is none.
+__global__ void __launch_bounds__(256) k_dos_sample(const Item *items, int n_items, const RunInfo *runs,
+                                                    const PopState *st)
+{
+    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (idx >= n_items) return;
+    const Item it = items[idx];
+    const RunInfo &R = runs[it.run];
+    if (!R.exact_dos) return;
+    const PopState &S = st[it.run * MAX_POP + it.pop];
+    if (!pop_active(S)) return;
+    const int j = it.group * 64 + lane;
+    if (j >= S.Rcur) return;
+    const int N = R.N, i = S.i;
+    const u32x4 o = philox10((uint32_t)j, 0u, (uint32_t)i, (TAG_DOS << 28) | ((uint32_t)it.pop << 24), R.key0,
+                             R.key1);
+    const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
+    const uint64_t *C = R.tabD + (size_t)i * (N + 1);
+    int lo = 0, hi = N + 1;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (v < C[m]) hi = m;
+        else lo = m + 1;
+    }
+    R.E[it.pop][S.cur][j] = -2 * N + 4 * min(lo, N);
 }
 
 // ---------------------------------------------- permutation pairing (q)
@@ -2391,6 +2446,13 @@ int sweep_msc_resident(int threads, size_t lds)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     return per_cu * cus;
+}
+
+hipError_t launch_dos_sample(const LaunchCtx &c)
+{
+    if (!c.any_exact_dos || c.n_items == 0) return hipSuccess;
+    k_dos_sample<<<(c.n_items + 3) / 4, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st);
+    return hipGetLastError();
 }
 
 hipError_t launch_measure(const LaunchCtx &c)

@@ -18,6 +18,7 @@ struct LaunchCtx {
     int repr;
     bool any_multinomial;
     bool any_wang;                 // some run pairs replicas by permutations
+    bool any_exact_dos;            // some run is at theta = infinity
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
     const SweepItem *meas_items;   // device [n_meas_items]: groups per measure workgroup
     int n_meas_items;
@@ -37,6 +38,7 @@ hipError_t launch_resample(const LaunchCtx &c);
 hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop, int theta);
 hipError_t launch_sweep_msc(const LaunchCtx &c);
 hipError_t launch_measure(const LaunchCtx &c);
+hipError_t launch_dos_sample(const LaunchCtx &c);   // theta = infinity draws (no-op without such runs)
 hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
                        double *logw, double *qw, pa_wavg *out);
 hipError_t launch_qweights(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,

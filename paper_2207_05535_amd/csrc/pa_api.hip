@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,7 +50,11 @@ bool desc_ok(const pa_run_desc &d, pa_repr repr)
     if (d.resampling == PA_MULTINOMIAL && d.R_cap != d.R) return false;
     if (d.overlap < PA_Q_NONE || d.overlap > PA_Q_WANG_RDM) return false;
     if (d.qhist != 0 && d.qhist != 1) return false;
-    if (d.theta < 0 || d.theta >= (1 << 24)) return false;
+    if (d.theta == PA_THETA_EXACT) {
+        if (d.model != PA_FM || d.L > 10 || d.overlap != PA_Q_NONE) return false;
+    } else if (d.theta < 0 || d.theta >= (1 << 24)) {
+        return false;
+    }
     if (d.K < 2 || d.K > (1 << 20) || d.beta == nullptr) return false;
     if (d.beta[0] != 0.0) return false;
     for (int i = 0; i < d.K; ++i)
@@ -86,6 +91,7 @@ void plan_run_buffers(Planner &P, const pa_run_desc &d, pa_repr repr, RunOff &o)
     o.qh = d.qhist ? P.take(sizeof(int32_t) * (size_t)npop * d.K * (N + 1)) : 0;
     o.jbits = P.take(N);
     o.wang = is_wang(d.overlap) ? P.take(sizeof(int32_t) * wang_ints(d.R_cap)) : 0;
+    o.dos = d.theta == PA_THETA_EXACT ? P.take(sizeof(uint64_t) * (size_t)d.K * (N + 1)) : 0;
 }
 
 void plan_table(Planner &P, int N, const pa_run_desc &d, TableOff &T)
@@ -183,6 +189,108 @@ void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::
     }
 }
 
+}  // namespace pa
+
+namespace {
+
+using u128 = unsigned __int128;
+
+// Exact density of states of the periodic L x L ferromagnet by the row
+// transfer matrix, Z = Tr T^L with T(s, s') = y^(h(s') + d(s, s')), y
+// counting unsatisfied bonds (h: within a row, periodic; d: the Hamming
+// distance of two neighbouring rows).  The trace runs over the first row;
+// rows related by a cyclic shift or a global flip have the same diagonal
+// element, so one row per class is propagated and weighted by the class
+// size.  The Hamming factor is a product over columns of [[1, y], [y, 1]],
+// applied in place to each pair of rows that differ in one column.  Counts
+// are exact in 128 bits for L <= 10.  Returns the coefficients of y^u,
+// u = 0..2N (odd u never occurs on the periodic lattice).
+std::vector<u128> fm_dos_by_transfer(int L)
+{
+    const int N = L * L, S = 1 << L, D = 2 * N + 1, mask = S - 1;
+    auto rot = [&](int s) { return ((s << 1) | (s >> (L - 1))) & mask; };
+    auto hrow = [&](int s) { return __builtin_popcount((unsigned)(s ^ rot(s))); };
+    std::vector<int> weight(S, 0);
+    for (int s = 0; s < S; ++s) {
+        int rep = s;
+        for (int f = 0; f < 2; ++f) {
+            int t = f ? (~s & mask) : s;
+            for (int k = 0; k < L; ++k, t = rot(t)) rep = std::min(rep, t);
+        }
+        ++weight[rep];
+    }
+    std::vector<u128> cur((size_t)S * D), total(D, 0);
+    for (int s1 = 0; s1 < S; ++s1) {
+        if (weight[s1] == 0) continue;
+        std::fill(cur.begin(), cur.end(), (u128)0);
+        cur[(size_t)s1 * D + hrow(s1)] = 1;
+        for (int r = 0; r < L; ++r) {
+            for (int b = 0; b < L; ++b) {   // bonds to the next row (the first row after the last)
+                const int bit = 1 << b;
+                for (int s = 0; s < S; ++s) {
+                    if (s & bit) continue;
+                    u128 *a = &cur[(size_t)s * D], *c = &cur[(size_t)(s | bit) * D];
+                    for (int u = D - 1; u >= 1; --u) {
+                        const u128 au = a[u] + c[u - 1], cu = c[u] + a[u - 1];
+                        a[u] = au;
+                        c[u] = cu;
+                    }
+                }
+            }
+            if (r == L - 1) break;
+            for (int s = 0; s < S; ++s) {   // the new row's own bonds
+                const int k = hrow(s);
+                if (k == 0) continue;
+                u128 *a = &cur[(size_t)s * D];
+                for (int u = D - 1; u >= 0; --u) a[u] = u >= k ? a[u - k] : 0;
+            }
+        }
+        for (int u = 0; u < D; ++u) total[u] += (u128)weight[s1] * cur[(size_t)s1 * D + u];
+    }
+    return total;
+}
+
+// g_m for E = -2N + 4m, m = 0..N, cached per L.
+const std::vector<u128> &fm_dos(int L)
+{
+    static std::mutex mu;
+    static std::map<int, std::vector<u128>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(L);
+    if (it == cache.end()) {
+        const std::vector<u128> byu = fm_dos_by_transfer(L);
+        std::vector<u128> g(L * L + 1);
+        for (int m = 0; m <= L * L; ++m) g[m] = byu[2 * m];
+        it = cache.emplace(L, std::move(g)).first;
+    }
+    return it->second;
+}
+
+}  // namespace
+
+namespace pa {
+
+bool dos_thresholds(const pa_run_desc &d, std::vector<uint64_t> &out)
+{
+    if (d.L < 4 || d.L > 10 || (d.L & 1)) return false;
+    const int N = d.L * d.L;
+    const std::vector<u128> &g = fm_dos(d.L);
+    out.assign((size_t)d.K * (N + 1), 0);
+    std::vector<double> S(N + 1);
+    for (int i = 0; i < d.K; ++i) {
+        double acc = 0.0;
+        for (int m = 0; m <= N; ++m) {
+            acc += (double)g[m] * std::exp(-4.0 * d.beta[i] * (double)m);
+            S[m] = acc;
+        }
+        for (int m = 0; m <= N; ++m) {
+            const double q = S[m] / acc;
+            out[(size_t)i * (N + 1) + m] = q >= 1.0 ? UINT64_MAX : (uint64_t)std::ldexp(q, 64);
+        }
+    }
+    return true;
+}
+
 RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8_t *tbase, const TableOff &T,
                      pa_obs *obs, int obs_stride, int obs_off)
 {
@@ -193,7 +301,8 @@ RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8
     I.npop = n_pop_of(d.overlap);
     I.R = d.R;
     I.R_cap = d.R_cap;
-    I.theta = d.theta;
+    I.theta = d.theta == PA_THETA_EXACT ? 0 : d.theta;   // no Metropolis sweeps at theta = infinity
+    I.exact_dos = d.theta == PA_THETA_EXACT ? 1 : 0;
     I.K = d.K;
     I.model = d.model;
     I.resampling = d.resampling;
@@ -226,6 +335,7 @@ RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8
     I.jbits = base + o.jbits;
     I.wang = is_wang(d.overlap) ? (int32_t *)(base + o.wang) : nullptr;
     I.wang_lb = wang_lb_of(d.R_cap);
+    I.tabD = d.theta == PA_THETA_EXACT ? (const uint64_t *)(base + o.dos) : nullptr;
     I.tabX = (const uint64_t *)(tbase + T.X);
     I.tabx = (const double *)(tbase + T.x);
     I.tabT = (const uint64_t *)(tbase + T.T);
@@ -344,6 +454,7 @@ pa_status enqueue_step(pa_ctx *c)
                 return dev_fail(c);
         }
     }
+    if (launch_dos_sample(c->lc) != hipSuccess) return dev_fail(c);
     if (launch_measure(c->lc) != hipSuccess) return dev_fail(c);
     return PA_OK;
 }
@@ -424,6 +535,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         c->descs[r].beta = c->betas[r].data();
         if (runs[r].resampling == PA_MULTINOMIAL) c->any_multinomial = true;
         if (is_wang(runs[r].overlap)) c->any_wang = true;
+        if (runs[r].theta == PA_THETA_EXACT) c->any_exact_dos = true;
     }
     // table sources must point at the context's own copies
     for (auto &t : c->lo.tables) {
@@ -471,6 +583,7 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.repr = repr;
     c->lc.any_multinomial = c->any_multinomial;
     c->lc.any_wang = c->any_wang;
+    c->lc.any_exact_dos = c->any_exact_dos;
     c->lc.stats = at<unsigned long long>(c, Lo.stats);
     c->lc.sweep_queue = at<unsigned int>(c, Lo.queue);
     c->lc.sweep_grid = 0;
@@ -506,7 +619,8 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
                               hipMemcpyHostToDevice, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(at<uint64_t>(c, Lo.dseed), dseed.data(), sizeof(uint64_t) * n_runs,
                               hipMemcpyHostToDevice, s) == hipSuccess;
-    std::vector<std::vector<uint64_t>> hX(Lo.tables.size()), hT(Lo.tables.size());
+    std::vector<std::vector<uint64_t>> hX(Lo.tables.size()), hT(Lo.tables.size()), hD;
+    hD.reserve(n_runs);
     std::vector<std::vector<double>> hx(Lo.tables.size());
     for (size_t t = 0; t < Lo.tables.size() && ok; ++t) {
         const TableOff &T = Lo.tables[t];
@@ -533,6 +647,12 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         if (d.qhist && ok)
             ok = launch_fill_u32(at<void>(c, o.qh), 0, (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1), s) ==
                  hipSuccess;
+        if (d.theta == PA_THETA_EXACT && ok) {   // energy draw thresholds (host copy kept until the sync)
+            hD.emplace_back();
+            ok = dos_thresholds(d, hD.back()) &&
+                 hipMemcpyAsync(at<uint64_t>(c, o.dos), hD.back().data(), sizeof(uint64_t) * hD.back().size(),
+                                hipMemcpyHostToDevice, s) == hipSuccess;
+        }
     }
     ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, STAT_BYTES / 4, s) == hipSuccess;
     ok = ok && launch_fill_u32(at<void>(c, Lo.queue), 0, 2, s) == hipSuccess;
@@ -584,6 +704,7 @@ pa_status pa_sweep(pa_ctx *c, int32_t i)
                 return dev_fail(c);
         }
     }
+    if (launch_dos_sample(c->lc) != hipSuccess) return dev_fail(c);
     c->phase = PH_SWEPT;
     return PA_OK;
 }
@@ -734,6 +855,17 @@ pa_status pa_read_qhist(pa_ctx *c, int32_t run, int32_t *host_out)
     PA_HIP(c, hipMemcpyAsync(host_out, at<int32_t>(c, c->lo.runs[run].qh), sizeof(int32_t) * n,
                              hipMemcpyDeviceToHost, c->stream));
     PA_HIP(c, hipStreamSynchronize(c->stream));
+    return PA_OK;
+}
+
+pa_status pa_exact_dos(int32_t L, uint64_t *host_out)
+{
+    if (L < 4 || L > 10 || (L & 1) || !host_out) return PA_ERR_ARG;
+    const std::vector<u128> &g = fm_dos(L);
+    for (int m = 0; m <= L * L; ++m) {
+        host_out[2 * m] = (uint64_t)g[m];
+        host_out[2 * m + 1] = (uint64_t)(g[m] >> 64);
+    }
     return PA_OK;
 }
 

@@ -161,7 +161,8 @@ struct Tuner {
         for (int k = 0; k < steps && out == PA_OK; ++k) {
             if (launch_anneal(c->lc) != hipSuccess || launch_resample(c->lc) != hipSuccess ||
                 hipEventRecord(ev[2 * k], c->stream) != hipSuccess || launch_sweep_msc(c->lc) != hipSuccess ||
-                hipEventRecord(ev[2 * k + 1], c->stream) != hipSuccess || launch_measure(c->lc) != hipSuccess)
+                hipEventRecord(ev[2 * k + 1], c->stream) != hipSuccess || launch_dos_sample(c->lc) != hipSuccess ||
+                launch_measure(c->lc) != hipSuccess)
                 out = dev_fail(c);
         }
         if (out == PA_OK && hipStreamSynchronize(c->stream) != hipSuccess) out = dev_fail(c);

@@ -25,6 +25,7 @@ constexpr uint32_t TAG_MN = 3u;
 constexpr uint32_t TAG_INIT = 4u;
 constexpr uint32_t TAG_J = 5u;
 constexpr uint32_t TAG_PERM = 6u;
+constexpr uint32_t TAG_DOS = 7u;
 
 constexpr int MAX_POP = 2;
 
@@ -53,7 +54,8 @@ struct RunInfo {
     uint32_t key0, key1;
     // record of (population p, temperature i): obs[i * obs_stride + obs_off + p]
     int32_t obs_stride, obs_off;
-    int32_t wang_lb, pad0;        // permutation pairing: log2 of the bucket capacity
+    int32_t wang_lb;              // permutation pairing: log2 of the bucket capacity
+    int32_t exact_dos;            // 1: theta = infinity (energies drawn; theta is 0 here)
     // device pointers into the caller's workspace
     uint8_t *spins[MAX_POP][2];   // int8: [group][site][64] bytes; MSC: [group][site] u64
     int32_t *E[MAX_POP][2];       // energies [R_cap]
@@ -72,6 +74,7 @@ struct RunInfo {
     int32_t *qh;                  // [n_pop][K][N+1] or nullptr
     uint8_t *jbits;               // [N]: bit0 = J_R(n) < 0, bit1 = J_D(n) < 0
     int32_t *wang;                // permutation pairing scratch (see WangBufs) or nullptr
+    const uint64_t *tabD;         // theta = infinity: energy draw thresholds [K][N+1] or nullptr
     const uint64_t *tabX;         // [K][N+1]  floor(exp(-dbeta_i 4k) 2^40)
     const double *tabx;           // [K][N+1]  exp(-dbeta_i 4k)
     const uint64_t *tabT;         // [K][2]    Metropolis thresholds for dE = 4, 8

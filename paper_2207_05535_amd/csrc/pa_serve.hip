@@ -238,7 +238,7 @@ pa_status rebuild(pa_server *s)
 {
     size_t n_items = 0, n_chunks = 0, n_meas = 0;
     int hi = 0, npop_ctx = 1;
-    bool mn = false, wang = false;
+    bool mn = false, wang = false, exact = false;
     std::vector<SweepItem> sweep;
     size_t lds = 0;
     for (int k = 0; k < s->max_slots; ++k) {
@@ -252,6 +252,7 @@ pa_status rebuild(pa_server *s)
         npop_ctx = std::max(npop_ctx, npop);
         mn = mn || sl.d.resampling == PA_MULTINOMIAL;
         wang = wang || is_wang(sl.d.overlap);
+        exact = exact || sl.d.theta == PA_THETA_EXACT;
         if (s->repr == PA_MSC64) {
             const int G = groups_of(s, sl.d.L);
             const int N = sl.d.L * sl.d.L;
@@ -305,6 +306,7 @@ pa_status rebuild(pa_server *s)
     c.npop_ctx = npop_ctx;
     c.any_multinomial = mn;
     c.any_wang = wang;
+    c.any_exact_dos = exact;
     c.sweep_items = (const SweepItem *)(s->base + s->sweep_off);
     c.n_sweep_items = (int)sweep.size();
     c.sweep_threads = s->threads;
@@ -504,6 +506,11 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
         (st = upload(s, blk + b.meas, meas.data(), sizeof(SweepItem) * meas.size())) != PA_OK ||
         (st = upload(s, blk + b.dseed, &ds, sizeof(ds))) != PA_OK)
         return st;
+    if (d.theta == PA_THETA_EXACT) {   // energy draw thresholds of the theta = infinity limit
+        std::vector<uint64_t> D;
+        if (!dos_thresholds(sl.d, D)) return PA_ERR_ARG;
+        if ((st = upload(s, blk + b.o.dos, D.data(), sizeof(uint64_t) * D.size())) != PA_OK) return st;
+    }
     bool ok = true;
     for (int p = 0; p < npop && ok; ++p) ok = launch_fill_u32(blk + b.o.r[p], 0, d.R_cap, s->stream) == hipSuccess;
     if (d.qhist && ok)
@@ -523,6 +530,7 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     c.npop_ctx = npop;
     c.any_multinomial = d.resampling == PA_MULTINOMIAL;
     c.any_wang = is_wang(d.overlap);
+    c.any_exact_dos = d.theta == PA_THETA_EXACT;
     if (launch_init(c, (const uint64_t *)(blk + b.dseed)) != hipSuccess || launch_measure(c) != hipSuccess)
         return sfail(s);
     s->dirty = true;
@@ -555,6 +563,7 @@ pa_status pa_server_step(pa_server *s, int32_t *finished, int32_t *n_finished)
                 return sfail(s);
         }
     }
+    if (launch_dos_sample(c) != hipSuccess) return sfail(s);
     if (launch_measure(c) != hipSuccess) return sfail(s);
     for (int k = 0; k < s->max_slots; ++k) {
         Slot &sl = s->slots[k];

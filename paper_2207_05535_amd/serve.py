@@ -81,9 +81,10 @@ class Server:
 
 def run_flips(obs, desc):
     """Attempted flips of a finished run: sum over steps i >= 1 of theta R_i N
-    (both populations for two-population runs)."""
+    (both populations for two-population runs); none at theta = infinity,
+    where energies are drawn instead of sweeping."""
     N = desc["L"] ** 2
-    return int(obs["R_i"][1:].sum()) * desc["theta"] * N
+    return int(obs["R_i"][1:].sum()) * max(desc["theta"], 0) * N
 
 
 def replay(server, trace, time_scale=1.0, max_inflight=2, clock=time.perf_counter, progress=None):

@@ -58,7 +58,8 @@ def test_workspace_size_valid_and_monotone():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(L=7), dict(L=2), dict(L=2048), dict(theta=-1), dict(R=0), dict(R_cap=10),
+    dict(L=7), dict(L=2), dict(L=2048), dict(theta=-2), dict(R=0), dict(R_cap=10),
+    dict(theta=-1, model=1), dict(theta=-1, L=12), dict(theta=-1, overlap=1),   # theta = infinity: FM, L <= 10, no q
     dict(R_cap=2000),                      # multinomial needs R_cap == R
     dict(model=3), dict(resampling=5), dict(overlap=7), dict(qhist=2),
     dict(beta=[0.1, 0.2, 0.3]),            # beta_0 must be 0
@@ -70,6 +71,14 @@ def test_workspace_size_rejects(bad):
     d = W.with_(W.fm_L8_R1000(), **bad)
     st, _ = _size([d])
     assert st == pa.PA_ERR_ARG
+
+
+def test_exact_dos_validates_before_computing():
+    lib = pa.lib()
+    buf = np.zeros(2 * 145, np.uint64)
+    for L in (2, 3, 12):
+        assert lib.pa_exact_dos(L, buf.ctypes.data) == pa.PA_ERR_ARG
+    assert lib.pa_exact_dos(8, None) == pa.PA_ERR_ARG
 
 
 def test_msc_lattice_limit():

@@ -1,0 +1,136 @@
+"""GPU parity of the theta = infinity limit (Sec. V B) and the library's exact
+density of states.
+
+* pa_exact_dos equals the oracle's density of states (computed by its own
+  transfer matrix) for L = 4, 6, 8; at L = 10, beyond the oracle's range, it
+  sums to 2^N, is symmetric, and reproduces Kaufman's partition function
+  (tests/exact.py) to 25 digits.
+* theta = infinity runs step by step against the oracle (both spin layouts,
+  both resampling kinds, several replica groups with a ragged last one):
+  records, energies, family labels and counts bit-exact; ln Q and A within
+  1e-10.
+* At L = 10 and R = 2 10^4 the drawn energies pass a chi-square test against
+  the exact distribution at every checked temperature.
+* theta = infinity runs batched with Metropolis runs give each run's own
+  oracle records.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import exact
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2207_05535_amd as pa  # noqa: E402
+
+RTOL, ATOL = 1e-10, 1e-12
+INT_FIELDS = ["R_i", "sumE", "sumE2", "sumAbsM", "sumM2", "nPairs", "sumQ", "sumAbsQ", "sumQ2",
+              "sumQl", "sumQl2", "famSumSq", "famMax", "nFam", "Emin", "status"]
+REPRS = ["int8", "msc"]
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def close(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.all(np.abs(a - b) <= RTOL * np.maximum(np.abs(a), np.abs(b)) + ATOL)
+
+
+def assert_obs_equal(g, o, where=""):
+    for f in INT_FIELDS:
+        assert np.array_equal(np.asarray(g[f]), np.asarray(o[f])), f"{where}: field {f}: {g[f]} != {o[f]}"
+    for f in ("lnQ", "A"):
+        assert close(g[f], o[f]), f"{where}: field {f}: {g[f]} vs {o[f]}"
+
+
+def test_library_dos():
+    say("exact density of states: library vs oracle and Kaufman")
+    for L in (4, 6, 8):
+        assert pa.pa_exact_dos(L) == oracle.exact_dos(L), L
+    import mpmath as mp
+    g = pa.pa_exact_dos(10)
+    N = 100
+    assert sum(g) == 2 ** N and g == g[::-1] and g[0] == 2 and g[1] == 0 and g[2] == 2 * N
+    with mp.workdps(50):
+        for beta in (0.2, 0.4407, 0.7):
+            Z = mp.fsum(mp.mpf(gm) * mp.exp(-mp.mpf(beta) * (-2 * N + 4 * m)) for m, gm in enumerate(g))
+            ref = exact.kaufman_lnZ(10, beta, dps=50)
+            assert abs(mp.log(Z) - ref) < mp.mpf(10) ** -25 * abs(ref), beta
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+@pytest.mark.parametrize("resampling", [W.NEAREST_INT, W.MULTINOMIAL])
+def test_stepwise_parity(repr_, resampling):
+    say(f"theta = infinity stepwise {repr_} resampling={resampling}")
+    d = W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x6100 + resampling, R=700, theta=W.THETA_EXACT, K=21,
+                   beta_f=1.0, resampling=resampling)
+    orc = oracle.OracleRun(d)
+    ctx = pa.Context([d], repr_)
+    assert_obs_equal(ctx.obs()[0, 0, 0], orc.obs()[0, 0], "i=0")
+    for i in range(1, d["K"]):
+        orc.step(i)
+        ctx.step(i)
+        assert_obs_equal(ctx.obs()[0, 0, i], orc.obs()[0, i], f"i={i}")
+        if i % 5 == 0 or i == d["K"] - 1:
+            _, Eo, fo, _ = orc.state(0)
+            _, Eg, fg, rg = ctx.state(0, 0)
+            assert np.array_equal(Eg, Eo) and np.array_equal(fg, fo), f"i={i}"
+            assert np.array_equal(rg, orc.counts(0)[0]), f"i={i}"
+    ctx.close()
+
+
+def test_full_size_L10_energy_law():
+    from scipy import stats
+    L, R = 10, 20000
+    N = L * L
+    d = W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x6200, R=R, theta=W.THETA_EXACT, K=31, beta_f=0.6)
+    say("theta = infinity L=10 R=2e4 energy law")
+    g = np.array([float(x) for x in pa.pa_exact_dos(L)])
+    Es = np.array([-2 * N + 4 * m for m in range(N + 1)])
+    ctx = pa.Context([d], "msc")
+    for i in range(1, d["K"]):
+        ctx.step(i)
+        if i % 6:
+            continue
+        _, E, _, _ = ctx.state(0, 0)
+        p = g * np.exp(-d["beta"][i] * (Es - Es[0]) - 0.0)
+        p /= p.sum()
+        obs = np.bincount((E - Es[0]) // 4, minlength=N + 1)
+        keep = p * len(E) >= 5
+        e_ = p[keep] * len(E)
+        o_ = obs[keep].astype(np.float64)
+        rest_o, rest_e = len(E) - o_.sum(), len(E) - e_.sum()
+        chi2 = ((o_ - e_) ** 2 / e_).sum() + ((rest_o - rest_e) ** 2 / rest_e if rest_e > 1e-9 else 0.0)
+        assert stats.chi2.sf(chi2, keep.sum()) > 1e-4, (i, chi2)
+        o = ctx.obs()[0, 0, i]
+        assert o["sumE"] == E.sum() and o["sumAbsM"] == 0 and o["sumM2"] == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_batched_with_metropolis_runs(repr_):
+    say(f"theta = infinity batched with Metropolis runs {repr_}")
+    runs = [W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x6300, R=300, theta=W.THETA_EXACT, K=9, beta_f=0.8),
+            W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x6301, R=300, theta=3, K=9, beta_f=0.8),
+            W.run_desc(6, W.FM, seed=W.RUN_SEED_BASE + 0x6302, R=150, theta=W.THETA_EXACT, K=9, beta_f=0.8,
+                       resampling=W.NEAREST_INT),
+            W.run_desc(10, W.EA_PMJ, seed=W.RUN_SEED_BASE + 0x6303, R=200, theta=2, K=9, beta_f=0.8,
+                       overlap=W.Q_INDEX_SHIFT)]
+    ctx = pa.Context(runs, repr_)
+    ctx.run(1, 9)
+    got = ctx.obs()
+    for r, d in enumerate(runs):
+        orc = oracle.OracleRun(d).run_all()
+        assert_obs_equal(got[r, 0], orc.obs()[0], f"run {r}")
+    ctx.close()

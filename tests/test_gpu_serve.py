@@ -30,9 +30,9 @@ def say(msg):
 
 
 def mixed_trace():
-    """Eleven requests of several sizes, models, resampling kinds, overlap
-    estimators (permutation pairing among them) and schedule lengths, with
-    staggered arrivals."""
+    """Twelve requests of several sizes, models, resampling kinds, overlap
+    estimators (permutation pairing among them), schedule lengths and one at
+    theta = infinity, with staggered arrivals."""
     specs = [
         (8, W.FM, W.MULTINOMIAL, W.Q_NONE, 12, 300),
         (12, W.EA_PMJ, W.NEAREST_INT, W.Q_INDEX_SHIFT, 9, 500),
@@ -45,11 +45,12 @@ def mixed_trace():
         (32, W.FM, W.MULTINOMIAL, W.Q_INDEX_SHIFT, 5, 200),
         (12, W.EA_PMJ, W.MULTINOMIAL, W.Q_WANG_RDM, 10, 300),
         (10, W.FM, W.NEAREST_INT, W.Q_WANG, 8, 260),
+        (8, W.FM, W.MULTINOMIAL, W.Q_NONE, 9, 400, W.THETA_EXACT),
     ]
     out = []
-    for q, (L, model, rs, ov, K, R) in enumerate(specs):
+    for q, (L, model, rs, ov, K, R, *th) in enumerate(specs):
         d = W.run_desc(L, model, seed=W.RUN_SEED_BASE + 0x7000 + q,
-                       disorder_seed=W.DISORDER_SEED_BASE + 0x70 + q, R=R, theta=3, K=K,
+                       disorder_seed=W.DISORDER_SEED_BASE + 0x70 + q, R=R, theta=th[0] if th else 3, K=K,
                        beta_f=1.5 if model == W.EA_PMJ else 0.6, resampling=rs, overlap=ov)
         out.append((0.002 * q, d))
     return out
