@@ -339,6 +339,43 @@ def run_q_estimators(M=16, K=61):
     return out
 
 
+def run_theta_infinity(M=1024, R=1000, L=10, beta_f=0.44, K=45):
+    """The theta = infinity limit of Sec. V B beside finite theta: M runs of
+    the L = 10 ferromagnet per theta in one context (R = 1000, beta 0 ->
+    0.44 in K points); the mean, variance and skewness of -beta F-hat over
+    the runs at the last temperature, and its bias against the exact value
+    from the density of states."""
+    import numpy as np
+
+    import paper_2207_05535_amd as pa
+    import workloads as W
+
+    N = L * L
+    g = pa.pa_exact_dos(L)
+    terms = [math.log(gm) - beta_f * (-2 * N + 4 * m) for m, gm in enumerate(g) if gm > 0]
+    top = max(terms)
+    lnZ = top + math.log(sum(math.exp(t - top) for t in terms))
+    out = {"workload": f"{M} runs of the L={L} ferromagnet per theta, R={R}, beta 0->{beta_f} in {K} points, "
+                       f"multinomial; -beta F-hat at beta={beta_f}",
+           "minus_beta_F_exact": lnZ}
+    for name, th in (("theta_inf", W.THETA_EXACT), ("theta_5", 5), ("theta_1", 1)):
+        runs = [W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x300000 + m, R=R, theta=th, K=K, beta_f=beta_f)
+                for m in range(M)]
+        ctx = pa.Context(runs, "msc")
+        tune(ctx, "cache")
+        t0 = time.perf_counter()
+        ctx.run(1, K)
+        A = ctx.obs()[:, 0, K - 1]["A"].astype(np.float64)
+        dt = time.perf_counter() - t0
+        ctx.close()
+        sd = A.std()
+        out[name] = {"mean": float(A.mean()), "var": float(A.var()),
+                     "skewness": float(((A - A.mean()) ** 3).mean() / sd ** 3) if sd > 0 else 0.0,
+                     "bias": float(A.mean() - lnZ), "run_s": round(dt, 3)}
+        log(f"theta infinity comparison: {name} {out[name]}")
+    return out
+
+
 def cpu_baseline(desc, max_seconds=20.0):
     """The oracle (single-threaded C, as it stands) on a bounded sample of
     the same workload: R = 2000 of the 1e5 replicas, the same lattice, theta
@@ -368,8 +405,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving,q_estimators",
-                    help="comma-separated subset of headline,plain,two_pop,batched,serving,q_estimators "
+    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving,q_estimators,theta_inf",
+                    help="comma-separated subset of headline,plain,two_pop,batched,serving,q_estimators,"
+                         "theta_inf "
                          "(for profiling runs; the headline value is null when it is left out)")
     ap.add_argument("--extra-steps", type=int, default=0,
                     help="temperature steps of the two_pop and batched workloads (0: whole schedule)")
@@ -441,6 +479,9 @@ def main():
     if "q_estimators" in only:
         log("overlap estimators: index shift, two populations, permutation pairing")
         line["q_estimators"] = run_q_estimators()
+    if "theta_inf" in only:
+        log("theta = infinity versus finite theta: spread of -beta F-hat")
+        line["theta_inf"] = run_theta_infinity()
     if not args.no_cpu_baseline and "headline" in only:
         log("cpu baseline: oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(desc)
