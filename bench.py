@@ -376,6 +376,87 @@ def run_theta_infinity(M=1024, R=1000, L=10, beta_f=0.44, K=45):
     return out
 
 
+def run_bias_vs_M(P=30720, L=10, R=100, K=61, beta_f=0.6, thetas=(1, 5),
+                  Ms=(1, 2, 4, 8, 16, 30, 32, 64, 128, 256)):
+    """Bias of weighted averages versus M (Sec. V B, Table III, Figs. 2 and
+    11) at small synthetic scale: per theta a pool of P runs of the L = 10
+    ferromagnet (R = 100, beta 0 -> 0.6 in K points) in one context, weighted
+    averages over S = P / M groups for each M on the device; near-critical
+    absolute bias (averaged over 0.42 <= beta <= 0.46, relative for c) of
+    W[e], W[f] and W_var[c] with bootstrap errors, the exponent b of a fit
+    a M^-b, the RMSD at beta = 0.44, var w against Eq. (varWpred) at M = 30,
+    and for M = 2 the bias of W[f] beside Wang's (beta/2) var F-hat with the
+    fit a + b / beta over beta >= 0.5."""
+    import numpy as np
+
+    import paper_2207_05535_amd as pa
+    import workloads as W
+    from paper_2207_05535_amd import bias as B
+
+    N = L * L
+    g = pa.pa_exact_dos(L)
+    beta = np.array(W.linear_schedule(beta_f, K))
+    ex = [B.exact_fm(g, L, b) for b in beta]
+    win = np.where((beta >= 0.42 - 1e-9) & (beta <= 0.46 + 1e-9))[0]
+    i44 = int(np.argmin(np.abs(beta - 0.44)))
+    out = {"workload": f"pool of {P} runs of the L={L} ferromagnet per theta, R={R}, beta 0->{beta_f} in {K} points, "
+                       f"multinomial; exact references from the density of states"}
+    for th in thetas:
+        runs = [W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x400000 + 0x10000 * th + m, R=R, theta=th, K=K,
+                           beta_f=beta_f) for m in range(P)]
+        ctx = pa.Context(runs, "msc")
+        tune(ctx, "cache")
+        ctx.run(1, K)
+        res = {"M": list(Ms)}
+        per_obs = {"e": [], "f": [], "c": []}
+        errs = {"e": [], "f": [], "c": []}
+        rm = []
+        for M in Ms:
+            w = ctx.weighted_average(M, pa.PA_W_FULL, 0)          # [S, K]
+            est = {"e": w["W_e"], "c": w["Wvar_c"], "f": B.weighted_f(w, np.where(beta > 0, beta, np.nan), N)}
+            for o in per_obs:
+                ref = np.array([x[o] for x in ex])
+                dev = est[o][:, win] - ref[win]
+                if o == "c":
+                    dev = dev / ref[win]
+
+                def near_critical(x, axis=0):
+                    return np.abs(x.mean(axis=axis)).mean(axis=-1)
+                val, err = B.bootstrap(dev, stat=near_critical, n_boot=400, seed=M)
+                per_obs[o].append(float(val))
+                errs[o].append(float(err))
+            e44 = w["W_e"][:, i44]
+            rm.append(float(B.rmsd(e44.mean() - ex[i44]["e"], e44.var())))
+            if M == 30:
+                res["var_w_M30"] = {"measured": float(w["var_w"][:, i44].mean()),
+                                    "predicted": float(w["var_w_pred"][:, i44].mean())}
+            if M == 2:
+                f2 = est["f"]
+                sel = np.where(beta >= 0.5)[0]
+                fb = f2[:, sel].mean(axis=0) - np.array([ex[i]["f"] for i in sel])
+                wang = B.wang_f_bias(beta[sel], f2[:, sel].var(axis=0), N)
+                a, b = B.fit_a_plus_b_over_beta(beta[sel], fb)
+                res["f_bias_M2"] = {"beta": [float(x) for x in beta[sel][::2]],
+                                    "measured": [float(x) for x in fb[::2]],
+                                    "wang_estimate": [float(x) for x in wang[::2]],
+                                    "fit_a_plus_b_over_beta": [float(a), float(b)]}
+        for o in per_obs:
+            y, s = np.array(per_obs[o]), np.array(errs[o])
+            res[o] = {"near_critical_abs_bias": [float(x) for x in y], "error": [float(x) for x in s]}
+            sig = y > 3 * s          # fit only where the bias stands out of its statistical error
+            if sig.sum() >= 3:
+                a, b, sb = B.fit_power_law(np.array(Ms, float)[sig], y[sig], s[sig])
+                res[o].update(fit_b=float(b), fit_sigma_b=float(sb), fit_a=float(a),
+                              fit_M=[int(m) for m in np.array(Ms)[sig]])
+            else:
+                res[o].update(fit_b=None, fit_sigma_b=None, fit_a=None, fit_M=[])
+        res["rmsd_e_beta044"] = rm
+        ctx.close()
+        out[f"theta_{th}"] = res
+        log(f"bias vs M: theta={th} b(e)={res['e']['fit_b']} b(f)={res['f']['fit_b']} b(c)={res['c']['fit_b']}")
+    return out
+
+
 def cpu_baseline(desc, max_seconds=20.0):
     """The oracle (single-threaded C, as it stands) on a bounded sample of
     the same workload: R = 2000 of the 1e5 replicas, the same lattice, theta
@@ -405,9 +486,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving,q_estimators,theta_inf",
+    ap.add_argument("--only", default="headline,plain,two_pop,batched,serving,q_estimators,theta_inf,bias",
                     help="comma-separated subset of headline,plain,two_pop,batched,serving,q_estimators,"
-                         "theta_inf "
+                         "theta_inf,bias "
                          "(for profiling runs; the headline value is null when it is left out)")
     ap.add_argument("--extra-steps", type=int, default=0,
                     help="temperature steps of the two_pop and batched workloads (0: whole schedule)")
@@ -482,6 +563,9 @@ def main():
     if "theta_inf" in only:
         log("theta = infinity versus finite theta: spread of -beta F-hat")
         line["theta_inf"] = run_theta_infinity()
+    if "bias" in only:
+        log("bias versus M of weighted averages")
+        line["bias_vs_M"] = run_bias_vs_M()
     if not args.no_cpu_baseline and "headline" in only:
         log("cpu baseline: oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(desc)
