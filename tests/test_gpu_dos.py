@@ -134,3 +134,20 @@ def test_batched_with_metropolis_runs(repr_):
         orc = oracle.OracleRun(d).run_all()
         assert_obs_equal(got[r, 0], orc.obs()[0], f"run {r}")
     ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+@pytest.mark.parametrize("L,R", [(4, 1), (4, 64), (6, 65)])
+def test_edge_sizes(repr_, L, R):
+    say(f"theta = infinity edge sizes {repr_} L={L} R={R}")
+    d = W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x6400 + R, R=R, theta=W.THETA_EXACT, K=8, beta_f=1.5,
+                   resampling=W.NEAREST_INT)
+    orc = oracle.OracleRun(d).run_all()
+    ctx = pa.Context([d], repr_)
+    ctx.run(1, d["K"])
+    assert_obs_equal(ctx.obs()[0, 0], orc.obs()[0], "all records")
+    _, Eo, fo, _ = orc.state(0)
+    _, Eg, fg, _ = ctx.state(0, 0)
+    assert np.array_equal(Eg, Eo) and np.array_equal(fg, fo)
+    ctx.close()
+

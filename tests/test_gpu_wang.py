@@ -169,3 +169,29 @@ def test_batched_with_other_overlap_kinds(repr_):
             assert_obs_equal(got[r, p], orc.obs()[p], f"run {r} pop {p}")
         assert np.array_equal(ctx.qhist(r), orc.qhist()), f"run {r}"
     ctx.close()
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+@pytest.mark.parametrize("L,R,theta,kind", [(4, 1, 1, W.Q_WANG), (4, 2, 1, W.Q_WANG_RDM), (6, 64, 2, W.Q_WANG),
+                                            (4, 65, 1, W.Q_WANG_RDM), (10, 129, 0, W.Q_WANG)])
+def test_edge_sizes(repr_, L, R, theta, kind):
+    """One replica (never a valid pairing), two replicas, exactly one and
+    just over one replica group, and theta = 0, against the oracle."""
+    say(f"permutation pairing edge sizes {repr_} L={L} R={R} theta={theta} kind={kind}")
+    d = W.run_desc(L, W.EA_PMJ, seed=W.RUN_SEED_BASE + 0x5400 + R, disorder_seed=11, R=R, theta=theta, K=6,
+                   beta_f=1.0, resampling=W.NEAREST_INT, overlap=kind, qhist=1)
+    orc = oracle.OracleRun(d)
+    ctx = pa.Context([d], repr_)
+    for i in range(d["K"]):
+        if i:
+            orc.step(i)
+            ctx.step(i)
+        assert_obs_equal(ctx.obs()[0, 0, i], orc.obs()[0, i], f"i={i}")
+        st_o, p_o = orc.pairing(0)
+        st_g, p_g = ctx.pairing(0)
+        assert st_g == st_o and (st_o != 0 or np.array_equal(p_g, p_o)), f"i={i}"
+    if R == 1:
+        assert (ctx.obs()[0, 0]["nPairs"] == 0).all()
+    assert np.array_equal(ctx.qhist(0), orc.qhist())
+    ctx.close()
+
