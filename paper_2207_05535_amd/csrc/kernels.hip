@@ -1122,6 +1122,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
         }
     const int i = __builtin_amdgcn_readfirstlane(S.i);
     const Thresholds Th = thresholds_of(R.tabT, i);
+    const bool saturated = Th.all4 || Th.all8;
     const uint32_t c3p = (TAG_SWEEP << 28) | ((uint32_t)pop << 24);
     const int lastg = group0 + G - 1;
     const uint64_t vlast = (Rc - lastg * 64 >= 64) ? ~0ull : ((1ull << (Rc - lastg * 64)) - 1);
@@ -1138,22 +1139,11 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
             __syncthreads();
             if (tid == 0) ctl[(h + 1) & 1] = 0;   // the next half-sweep's count; last read before this barrier
             int cnt = 0;
-            // dense rounds
-            for (int u0 = ub; u0 < ue; u0 += 64) {
-                const int u = u0 + lane;
+            // dense rounds, 64 units per pass; one unit (lane) per site word
+            auto chunk = [&](bool live_unit, int gs, int k, int kh, int ku, int kd, int addr, uint32_t n) {
                 uint64_t und4 = 0, und8 = 0, acc = 0;
-                int addr = 0;
-                uint32_t n = 0, g = 0;
-                if (u < ue) {
-                    const int gs = u / nh, k = u - gs * nh;
-                    const int y = k / half, m = k - y * half;
-                    const int p = (y + colour) & 1;
-                    int mh = p ? m + 1 : m - 1;                  // the other horizontal neighbour
-                    mh = mh < 0 ? half - 1 : (mh == half ? 0 : mh);
-                    const int kh = k - m + mh;
-                    const int ku = y == 0 ? k + nh - half : k - half;
-                    const int kd = y + 1 == L ? k - nh + half : k + half;
-                    addr = gs * N + colour * nh + k;
+                const uint32_t g = (uint32_t)(group0 + gs);
+                if (live_unit) {
                     const uint64_t *oth = lat + (size_t)gs * N + (colour ^ 1) * nh;
                     const uint64_t w = lat[addr];
                     uint64_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
@@ -1165,14 +1155,14 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                         j3 = jmask((uint8_t)jm, 3);
                     }
                     SiteClass sc = classify<EA>(w, oth[k], oth[kh], oth[ku], oth[kd], j0, j1, j2, j3);
-                    if (Th.all4) { sc.flip |= sc.one; sc.one = 0; }
-                    if (Th.all8) { sc.flip |= sc.zero; sc.zero = 0; }
+                    if (saturated) {   // uniform, only where a threshold is 2^32 (beta_i = 0)
+                        if (Th.all4) { sc.flip |= sc.one; sc.one = 0; }
+                        if (Th.all8) { sc.flip |= sc.zero; sc.zero = 0; }
+                    }
                     const uint64_t valid = group0 + gs == lastg ? vlast : ~0ull;
                     acc = sc.flip;
                     und4 = sc.one & valid;
                     und8 = sc.zero & valid;
-                    n = (uint32_t)(y * L + 2 * m + p);
-                    g = (uint32_t)(group0 + gs);
                     nflips += (uint32_t)__popcll(valid);
                     ++nwords;
                 }
@@ -1198,6 +1188,59 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     en[slot] = ((uint32_t)addr << 16) | n;
                 }
                 cnt += __popcll(need);
+            };
+            // Strength-reduced indices: when a pass starts on a multiple of
+            // 64 units, a row half (L/2 words) divides 64 an even number of
+            // times and a colour's half-lattice (N/2 words) is a multiple of
+            // 64, every lane keeps its column, parity and horizontal
+            // neighbour offset for the whole pass; its row advances by
+            // 64/(L/2) per pass, and all lanes move to the next replica group
+            // together.  Only the up/down wraps are tested per pass.
+            constexpr bool STEP_ROWS = LT > 0 && 64 % (LT / 2) == 0 && (64 / (LT / 2)) % 2 == 0 &&
+                                       (LT * LT / 2) % 64 == 0;
+            if (STEP_ROWS && (ub & 63) == 0 && ub < ue) {
+                constexpr int RS = STEP_ROWS ? 64 / (LT / 2) : 0;   // rows per pass
+                int gs = __builtin_amdgcn_readfirstlane(ub / nh);
+                int k = ub - gs * nh + lane;
+                int y = k / half;
+                const int m = k - y * half;
+                const int p = (y + colour) & 1;   // constant: y advances by an even count
+                int mh = p ? m + 1 : m - 1;
+                mh = mh < 0 ? half - 1 : (mh == half ? 0 : mh);
+                const int dh = mh - m;
+                int addr = gs * N + colour * nh + k;
+                uint32_t n = (uint32_t)(y * L + 2 * m + p);
+                for (int u0 = ub; u0 < ue; u0 += 64) {
+                    const int ku = y == 0 ? k + nh - half : k - half;
+                    const int kd = y + 1 == L ? k - nh + half : k + half;
+                    chunk(u0 + lane < ue, gs, k, k + dh, ku, kd, addr, n);
+                    k += 64;
+                    y += RS;
+                    n += (uint32_t)(RS * L);
+                    addr += 64;
+                    if (k >= nh) {   // every lane at once: the next replica group
+                        k -= nh;
+                        y -= L;
+                        n -= (uint32_t)N;
+                        addr += N - nh;
+                        ++gs;
+                    }
+                }
+            } else {
+                for (int u0 = ub; u0 < ue; u0 += 64) {
+                    const int u = u0 + lane;
+                    const bool in = u < ue;
+                    const int uu = in ? u : ub;   // any in-range unit; the chunk ignores it
+                    const int gs = uu / nh, k = uu - gs * nh;
+                    const int y = k / half, m = k - y * half;
+                    const int p = (y + colour) & 1;
+                    int mh = p ? m + 1 : m - 1;                  // the other horizontal neighbour
+                    mh = mh < 0 ? half - 1 : (mh == half ? 0 : mh);
+                    const int kh = k - m + mh;
+                    const int ku = y == 0 ? k + nh - half : k - half;
+                    const int kd = y + 1 == L ? k - nh + half : k + half;
+                    chunk(in, gs, k, kh, ku, kd, gs * N + colour * nh + k, (uint32_t)(y * L + 2 * m + p));
+                }
             }
             if (pool)
                 sweep_sparse_pooled(lat, e4, e8, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
