@@ -607,6 +607,10 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
 
     hipStream_t s = c->stream;
     bool ok = true;
+    // one clear of the whole workspace first: the histograms, records,
+    // descendant counts and counters that kernels accumulate into start at
+    // zero (a single launch, whatever the number of runs)
+    ok = ok && launch_fill_u32(c->ws, 0, Lo.total / 4, s) == hipSuccess;
     ok = ok && hipMemcpyAsync((void *)c->lc.runs, c->hinfo.data(), sizeof(RunInfo) * n_runs, hipMemcpyHostToDevice, s) ==
                    hipSuccess;
     ok = ok && hipMemcpyAsync(c->lc.st, hst.data(), sizeof(PopState) * hst.size(), hipMemcpyHostToDevice, s) ==
@@ -637,27 +641,16 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         ok = ok && hipMemcpyAsync(at<double>(c, T.beta), T.beta_src, sizeof(double) * T.K, hipMemcpyHostToDevice,
                                   s) == hipSuccess;
     }
-    // zero the histograms, records and scratch that kernels accumulate into
     for (int r = 0; r < n_runs && ok; ++r) {
         const pa_run_desc &d = c->descs[r];
         const RunOff &o = Lo.runs[r];
-        for (int p = 0; p < n_pop_of(d.overlap) && ok; ++p) {
-            ok = launch_fill_u32(at<void>(c, o.r[p]), 0, d.R_cap, s) == hipSuccess;
-        }
-        if (d.qhist && ok)
-            ok = launch_fill_u32(at<void>(c, o.qh), 0, (size_t)n_pop_of(d.overlap) * d.K * (d.L * d.L + 1), s) ==
-                 hipSuccess;
-        if (d.theta == PA_THETA_EXACT && ok) {   // energy draw thresholds (host copy kept until the sync)
+        if (d.theta == PA_THETA_EXACT) {   // energy draw thresholds (host copy kept until the sync)
             hD.emplace_back();
             ok = dos_thresholds(d, hD.back()) &&
                  hipMemcpyAsync(at<uint64_t>(c, o.dos), hD.back().data(), sizeof(uint64_t) * hD.back().size(),
                                 hipMemcpyHostToDevice, s) == hipSuccess;
         }
     }
-    ok = ok && launch_fill_u32(at<void>(c, Lo.stats), 0, STAT_BYTES / 4, s) == hipSuccess;
-    ok = ok && launch_fill_u32(at<void>(c, Lo.queue), 0, 2, s) == hipSuccess;
-    ok = ok && launch_fill_u32(at<void>(c, Lo.obs), 0,
-                               sizeof(pa_obs) / 4 * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx, s) == hipSuccess;
     ok = ok && (repr != PA_MSC64 || upload_sweep_plan(c) == PA_OK);
     ok = ok && launch_init(c->lc, at<uint64_t>(c, Lo.dseed)) == hipSuccess;
     ok = ok && launch_measure(c->lc) == hipSuccess;
