@@ -109,6 +109,8 @@ def percentile(xs, q):
 
 
 TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache.json")
+# shapes tuned on a context like the serving stream (+-J, L in {16,24,32,48,64}, R = 5e4)
+SERVING_TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache_serving.json")
 
 
 def tune(ctx, mode):
@@ -263,7 +265,7 @@ def workload_summary(b, steps, name):
 def run_serving(trace, arena_bytes, max_slots, rate=20.0):
     import paper_2207_05535_amd as pa
     from paper_2207_05535_amd.serve import Server, replay
-    srv = Server(arena_bytes, max_slots=max_slots, tuning_cache=TUNING_CACHE)
+    srv = Server(arena_bytes, max_slots=max_slots, tuning_cache=SERVING_TUNING_CACHE)
     last = [0.0]
 
     def progress(done, n, t):
