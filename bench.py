@@ -113,16 +113,21 @@ TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache.json")
 SERVING_TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache_serving.json")
 
 
+SEARCH_OUT = [os.path.join(os.getcwd(), "tuning_cache_search.json")]
+
+
 def tune(ctx, mode):
     """Applies autotuned launch shapes: from the committed cache if it holds
     every L of the context, else by a search on the context's own next
-    steps (its state is left unchanged)."""
+    steps (its state is left unchanged).  mode "search" searches afresh and
+    merges the result into the file named by --tune-out."""
     if mode == "off":
         return None
     if mode == "search":
-        out = os.path.join(ROOT, "gpurun_out")
-        os.makedirs(out, exist_ok=True)
-        return ctx.autotune(steps=3, cache_path=os.path.join(out, "tuning_cache.json"))
+        d = os.path.dirname(SEARCH_OUT[0])
+        if d:
+            os.makedirs(d, exist_ok=True)
+        return ctx.autotune(steps=3, cache_path=SEARCH_OUT[0])
     return ctx.autotune(steps=3, cache_path=TUNING_CACHE)
 
 
@@ -497,6 +502,8 @@ def main():
     ap.add_argument("--tune", choices=("cache", "search", "off"), default="cache",
                     help="launch shapes: committed autotuner cache (search for missing L), "
                          "a fresh search, or the built-in defaults")
+    ap.add_argument("--tune-out", default=SEARCH_OUT[0],
+                    help="JSON file the shapes of --tune search are written to")
     ap.add_argument("--serving-slots", type=int, default=12)
     ap.add_argument("--serving-rate", type=float, default=20.0,
                     help="arrival rate of the serving trace in requests/s (the trace's arrival times "
@@ -504,6 +511,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    SEARCH_OUT[0] = os.path.abspath(args.tune_out)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs one population-annealing "
