@@ -1322,12 +1322,11 @@ __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int 
 
 // Partner words of the permutation pairing ([group][site] u64): the spare
 // spin buffer of population 0 (its previous population is no longer needed
-// once the step's copies are done); for int8 spins after the packed copy of
-// the population that k_wang_pack writes at its start.
-__device__ __forceinline__ uint8_t *wang_partner_words(const RunInfo &R, const PopState &S, bool int8)
+// once the step's copies are done; it holds at least 8 bytes per site and
+// group in either layout).
+__device__ __forceinline__ uint8_t *wang_partner_words(const RunInfo &R, const PopState &S)
 {
-    uint8_t *spare = R.spins[0][S.cur ^ 1];
-    return int8 ? spare + (size_t)R.groups_cap * R.N * 8 : spare;
+    return R.spins[0][S.cur ^ 1];
 }
 
 // Word of 64 replicas of group g at site n, from either layout.
@@ -1398,7 +1397,7 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
         mode = 3;
         const int cntp = min(64, Rc - g * 64);
         pairmask = cntp >= 64 ? ~0ull : ((1ull << cntp) - 1);
-        pbuf = wang_partner_words(R, S, REPR == PA_INT8);
+        pbuf = wang_partner_words(R, S);
         pg = g;
     }
     if (R.exact_dos && S.i > 0) {
@@ -1592,7 +1591,7 @@ __global__ void __launch_bounds__(256) k_dos_sample(const Item *items, int n_ite
 // Sec. III D, pairings from permutations (Wang et al.), for runs with
 // PA_Q_WANG / PA_Q_WANG_RDM, before the measurement of every temperature:
 //   k_wang_pairs   one workgroup per run: the permutations and the repair;
-//   k_wang_pack    (int8 spins) a bit-packed copy of the population;
+//   k_wang_rows    the population as bit rows, one per replica;
 //   k_wang_gather  the partners' configurations as bit-packed words;
 // then k_measure takes the pairs (j, pi_j) like any other overlap pairs.
 //
@@ -1863,10 +1862,12 @@ __device__ __forceinline__ bool wang_group_live(const Item &it, const RunInfo &R
            wang_bufs(R.wang, R.R_cap, R.wang_lb).hdr[0] == 0;
 }
 
-// int8 spins: bit-packed copy [group][site] of the population (one
-// wavefront per replica group, lane = site) at the start of the spare
-// buffer, as the source of k_wang_gather.
-__global__ void __launch_bounds__(256) k_wang_pack(const Item *items, int n_items, const RunInfo *runs,
+// Bit rows of population 0: word blk * 64 groups_cap + j holds, in bit s,
+// the spin of replica j at site 64 blk + s.  One wavefront per replica
+// group: lane s takes the word of site 64 blk + s (64 replicas), and a
+// 64 x 64 transpose turns the 64 site words into the group's 64 rows.
+template <int REPR>
+__global__ void __launch_bounds__(256) k_wang_rows(const Item *items, int n_items, const RunInfo *runs,
                                                    const PopState *st)
 {
     const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1875,19 +1876,25 @@ __global__ void __launch_bounds__(256) k_wang_pack(const Item *items, int n_item
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP];
     if (!wang_group_live(it, R, S)) return;
-    const int N = R.N, g = it.group;
-    const uint8_t *src = R.spins[0][S.cur];
-    uint64_t *dst = (uint64_t *)R.spins[0][S.cur ^ 1] + (size_t)g * N;
-    for (int n = lane; n < N; n += 64) dst[n] = load_word<PA_INT8>(src, g, n, N);
+    const int N = R.N, g = it.group, nb = (N + 63) / 64;
+    const size_t R64 = (size_t)R.groups_cap * 64;
+    uint64_t *rows = wang_rows(R.wang, R.R_cap) + (size_t)g * 64 + lane;
+    const uint8_t *buf = R.spins[0][S.cur];
+#pragma unroll 4
+    for (int blk = 0; blk < nb; ++blk) {
+        const int n = blk * 64 + lane;
+        const uint64_t w = n < N ? load_word<REPR>(buf, g, n, N) : 0ull;
+        rows[(size_t)blk * R64] = transpose64(w);
+    }
 }
 
 // Partner words: bit b of word (g, n) is the spin at site n of the partner
 // pi_j of replica j = 64 g + b.  One wavefront per group: lane b reads its
-// partner's words 64 sites at a time (the bit at position pi_j mod 64 of
-// group pi_j / 64), and a 64 x 64 transpose turns the lanes' rows into the
-// sites' words.  Lanes past R_i read replica 0 (their bits are never used).
+// partner's bit row one 64-site block at a time, and a transpose turns the
+// 64 rows into the block's 64 site words.  Lanes past R_i read replica 0
+// (their bits are never used).
 __global__ void __launch_bounds__(256) k_wang_gather(const Item *items, int n_items, const RunInfo *runs,
-                                                     const PopState *st, int repr)
+                                                     const PopState *st)
 {
     const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (idx >= n_items) return;
@@ -1895,27 +1902,18 @@ __global__ void __launch_bounds__(256) k_wang_gather(const Item *items, int n_it
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP];
     if (!wang_group_live(it, R, S)) return;
-    const int N = R.N, g = it.group;
+    const int N = R.N, g = it.group, nb = (N + 63) / 64;
+    const size_t R64 = (size_t)R.groups_cap * 64;
     const WangBufs W = wang_bufs(R.wang, R.R_cap, R.wang_lb);
-    const uint64_t *src = repr == PA_MSC64 ? (const uint64_t *)R.spins[0][S.cur]
-                                           : (const uint64_t *)R.spins[0][S.cur ^ 1];
-    uint64_t *dst = (uint64_t *)wang_partner_words(R, S, repr == PA_INT8) + (size_t)g * N;
     const int j = g * 64 + lane;
     const int p = j < S.Rcur ? W.pi[j] : 0;
-    const uint64_t *row = src + (size_t)(p >> 6) * N;   // N is even: 16-byte aligned pairs of words
-    const int bit = p & 63;
-    for (int n0 = 0; n0 < N; n0 += 64) {
-        uint64_t x = 0;
-#pragma unroll 8
-        for (int s = 0; s < 64; s += 2)
-            if (n0 + s < N) {
-                const uint4 v = *(const uint4 *)(row + n0 + s);
-                const uint64_t w0 = (uint64_t)v.x | ((uint64_t)v.y << 32), w1 = (uint64_t)v.z | ((uint64_t)v.w << 32);
-                x |= ((w0 >> bit) & 1ull) << s;
-                x |= ((w1 >> bit) & 1ull) << (s + 1);
-            }
-        const uint64_t col = transpose64(x);
-        if (n0 + lane < N) dst[n0 + lane] = col;
+    const uint64_t *rows = wang_rows(R.wang, R.R_cap) + p;
+    uint64_t *dst = (uint64_t *)wang_partner_words(R, S) + (size_t)g * N;
+#pragma unroll 4
+    for (int blk = 0; blk < nb; ++blk) {
+        const uint64_t col = transpose64(rows[(size_t)blk * R64]);
+        const int n = blk * 64 + lane;
+        if (n < N) dst[n] = col;
     }
 }
 
@@ -2504,11 +2502,12 @@ hipError_t launch_measure(const LaunchCtx &c)
         k_wang_pairs<<<c.n_runs, WANG_THREADS, 0, c.stream>>>(c.runs, c.st, c.run0);
         PA_CHECK_LAUNCH();
         const int blocks = (c.n_items + 3) / 4;
-        if (c.repr == PA_INT8) {
-            k_wang_pack<<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st);
-            PA_CHECK_LAUNCH();
-        }
-        k_wang_gather<<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st, c.repr);
+        if (c.repr == PA_INT8)
+            k_wang_rows<PA_INT8><<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st);
+        else
+            k_wang_rows<PA_MSC64><<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st);
+        PA_CHECK_LAUNCH();
+        k_wang_gather<<<blocks, 256, 0, c.stream>>>(c.items, c.n_items, c.runs, c.st);
         PA_CHECK_LAUNCH();
     }
     if (c.n_meas_items > 0) {

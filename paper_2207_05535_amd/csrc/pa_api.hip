@@ -90,7 +90,7 @@ void plan_run_buffers(Planner &P, const pa_run_desc &d, pa_repr repr, RunOff &o)
     }
     o.qh = d.qhist ? P.take(sizeof(int32_t) * (size_t)npop * d.K * (N + 1)) : 0;
     o.jbits = P.take(N);
-    o.wang = is_wang(d.overlap) ? P.take(sizeof(int32_t) * wang_ints(d.R_cap)) : 0;
+    o.wang = is_wang(d.overlap) ? P.take(sizeof(int32_t) * wang_ints(d.R_cap, N)) : 0;
     o.dos = d.theta == PA_THETA_EXACT ? P.take(sizeof(uint64_t) * (size_t)d.K * (N + 1)) : 0;
 }
 

@@ -124,17 +124,26 @@ __host__ __device__ inline bool is_wang(int overlap) { return overlap == PA_Q_WA
 // Permutation-pairing scratch of a run (int32 units), B = 2^wang_lb >= R_cap:
 // pi, sigma, fam[pi], bucket members, mismatch list [R_cap] each; bucket
 // counts [B]; bucket starts [B + 1]; header [4] (status: 0 paired, 1 a
-// family above R_i / 2, 2 no partner found; mismatch count).
+// family above R_i / 2, 2 no partner found; mismatch count); then, 8-byte
+// aligned, the bit rows of the population (64-bit words).
 __host__ __device__ inline int wang_lb_of(int R_cap)
 {
     int lb = 1;
     while ((1 << lb) < R_cap) ++lb;
     return lb;
 }
-__host__ __device__ inline size_t wang_ints(int R_cap)
+__host__ __device__ inline size_t wang_ints_head(int R_cap)   // the int32 arrays, even count
 {
-    return 5 * (size_t)R_cap + 2 * ((size_t)1 << wang_lb_of(R_cap)) + 1 + 4;
+    return (5 * (size_t)R_cap + 2 * ((size_t)1 << wang_lb_of(R_cap)) + 1 + 4 + 1) & ~(size_t)1;
 }
+// Bit rows of the population (see k_wang_rows): ceil(N/64) blocks of
+// 64 groups_cap words, after the int32 arrays.
+__host__ __device__ inline size_t wang_row_words(int R_cap, int N)
+{
+    return (size_t)((N + 63) / 64) * (size_t)(((R_cap + 63) / 64) * 64);
+}
+__host__ __device__ inline size_t wang_ints(int R_cap, int N) { return wang_ints_head(R_cap) + 2 * wang_row_words(R_cap, N); }
+__host__ __device__ inline uint64_t *wang_rows(int32_t *w, int R_cap) { return (uint64_t *)(w + wang_ints_head(R_cap)); }
 struct WangBufs {
     int32_t *pi, *sigma, *fampi, *members, *list, *cnt, *start, *hdr;
 };
