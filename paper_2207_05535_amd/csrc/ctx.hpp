@@ -65,6 +65,10 @@ void compute_tables(const pa_run_desc &d, int N, std::vector<uint64_t> &X, std::
 RunInfo make_runinfo(const pa_run_desc &d, uint8_t *base, const RunOff &o, uint8_t *tbase, const TableOff &T,
                      pa_obs *obs, int obs_stride, int obs_off);
 PopState initial_popstate(const pa_run_desc &d);
+// LDS ints of the permutation-pairing repair: 2 R_cap of the largest such
+// run whose labels (8 bytes per replica) fit the workgroup LDS beside the
+// kernel's own, 0 if none does (those runs repair in global memory).
+int wang_lds_ints_of(const pa_run_desc *const *runs, int n, int lds_limit);
 // theta = infinity: energy draw thresholds [K][N+1] of a run (see pa.h);
 // false if the density of states is not available for its L.
 bool dos_thresholds(const pa_run_desc &d, std::vector<uint64_t> &out);

@@ -1664,10 +1664,12 @@ __device__ int block_scan_excl(int v, int *sh, int *total)
     return r;
 }
 
-__global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs, const PopState *st, int run0)
+__global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs, const PopState *st, int run0,
+                                                              int lds_ints)
 {
     __shared__ int sh[17];
     __shared__ int big;
+    extern __shared__ int32_t wlds[];   // lds_ints: labels and partner labels when they fit
     const int run = run0 + blockIdx.x;
     const RunInfo &R = runs[run];
     if (!is_wang(R.overlap)) return;
@@ -1765,7 +1767,24 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
         if (ldc(&W.fampi[k]) == fam[k]) stc(&W.list[pos++], t);
     }
     wg_sync_stores();
+    // When 2 R_i ints fit the workgroup's LDS, the repair reads and writes
+    // the family labels and the partners' labels there, and logs its
+    // exchanges (in the bucket arrays, free by now) instead of applying them
+    // to pi in global memory; they are replayed onto pi in LDS at the end.
+    const bool in_lds = 2 * Rc <= lds_ints;
+    int32_t *Lfam = wlds, *Lfpi = wlds + Rc;
+    if (in_lds) {
+        for (int k = tid; k < Rc; k += T) {
+            Lfam[k] = fam[k];
+            Lfpi[k] = ldc(&W.fampi[k]);
+        }
+        __syncthreads();
+    }
     if (tid >= 64) return;
+    auto famv = [&](int m) { return in_lds ? Lfam[m] : fam[m]; };
+    auto fpiv = [&](int m) { return in_lds ? Lfpi[m] : ldc(&W.fampi[m]); };
+    int32_t *swaps = W.cnt;   // [2 B + 1] ints, B >= R_i: room for R_i exchanges
+    int nsw = 0;
 
     // The repair, one wavefront, over the list in batches of 64 entries.
     // What does not change during the repair (position, its place in the
@@ -1790,14 +1809,14 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
         if (e < nlist) {
             t_l = ldc(&W.list[e]);
             k_l = rdm ? ldc(&W.sigma[t_l]) : t_l;
-            f_l = fam[k_l];
-            open_l = ldc(&W.fampi[k_l]) == f_l;
-            p_l = ldc(&W.pi[k_l]);
+            f_l = famv(k_l);
+            open_l = fpiv(k_l) == f_l;
+            if (!in_lds) p_l = ldc(&W.pi[k_l]);
             if (!rdm) {   // the first later index with another label
                 int lo = t_l + 1, hi = Rc;
                 while (lo < hi) {
                     const int m = (lo + hi) >> 1;
-                    if (fam[m] == f_l) lo = m + 1;
+                    if (famv(m) == f_l) lo = m + 1;
                     else hi = m;
                 }
                 hi_l = lo;
@@ -1822,8 +1841,8 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                 if (uu < uend) {
                     const int q = (int)(uu >= Rc ? uu - Rc : uu);
                     m = rdm ? ldc(&W.sigma[q]) : q;
-                    fpm = ldc(&W.fampi[m]);
-                    ok = fam[m] != fk && fpm != fk;
+                    fpm = fpiv(m);
+                    ok = famv(m) != fk && fpm != fk;
                 }
                 const uint64_t bal = __ballot(ok);
                 if (bal) {
@@ -1838,22 +1857,60 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                 status = 2;
                 break;
             }
-            if (lane == 0) {
-                const int pm = ldc(&W.pi[found]);
-                stc(&W.pi[k], pm);
-                stc(&W.pi[found], pk);
-                stc(&W.fampi[k], fm);
-                stc(&W.fampi[found], fk);
+            if (in_lds) {
+                if (lane == 0) {
+                    Lfpi[k] = fm;
+                    Lfpi[found] = fk;
+                    swaps[2 * nsw] = k;
+                    swaps[2 * nsw + 1] = found;
+                }
+                ++nsw;
+            } else {
+                if (lane == 0) {
+                    const int pm = ldc(&W.pi[found]);
+                    stc(&W.pi[k], pm);
+                    stc(&W.pi[found], pk);
+                    stc(&W.fampi[k], fm);
+                    stc(&W.fampi[found], fk);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
             }
             if (k_l == found) open_l = false;
             prev_f = fk;
-            __builtin_amdgcn_s_waitcnt(0);
         }
+    }
+    if (in_lds && status == 0) {   // replay the exchanges onto pi, in LDS
+        __builtin_amdgcn_s_waitcnt(0);
+        int32_t *Lpi = Lfam;
+        for (int k = lane; k < Rc; k += 64) Lpi[k] = ldc(&W.pi[k]);
+        for (int s0 = 0; s0 < nsw; s0 += 64) {
+            int a = 0, b = 0;
+            if (s0 + lane < nsw) {
+                a = ldc(&swaps[2 * (s0 + lane)]);
+                b = ldc(&swaps[2 * (s0 + lane) + 1]);
+            }
+            const int ns = min(64, nsw - s0);
+            for (int j = 0; j < ns; ++j) {
+                const int x = __shfl(a, j, 64), y = __shfl(b, j, 64);
+                if (lane == 0) {
+                    const int px = Lpi[x], py = Lpi[y];
+                    Lpi[x] = py;
+                    Lpi[y] = px;
+                }
+            }
+        }
+        for (int k = lane; k < Rc; k += 64) stc(&W.pi[k], Lpi[k]);
     }
     if (lane == 0) {
         stc(&W.hdr[0], status);
         stc(&W.hdr[1], nlist);
     }
+}
+
+hipError_t prepare_wang_lds(size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_wang_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 __device__ __forceinline__ bool wang_group_live(const Item &it, const RunInfo &R, const PopState &S)
@@ -2499,7 +2556,8 @@ hipError_t launch_dos_sample(const LaunchCtx &c)
 hipError_t launch_measure(const LaunchCtx &c)
 {
     if (c.any_wang && c.n_runs > 0) {
-        k_wang_pairs<<<c.n_runs, WANG_THREADS, 0, c.stream>>>(c.runs, c.st, c.run0);
+        k_wang_pairs<<<c.n_runs, WANG_THREADS, sizeof(int32_t) * (size_t)c.wang_lds_ints, c.stream>>>(
+            c.runs, c.st, c.run0, c.wang_lds_ints);
         PA_CHECK_LAUNCH();
         const int blocks = (c.n_items + 3) / 4;
         if (c.repr == PA_INT8)

@@ -18,6 +18,7 @@ struct LaunchCtx {
     int repr;
     bool any_multinomial;
     bool any_wang;                 // some run pairs replicas by permutations
+    int wang_lds_ints;             // LDS of the pairing repair (2 R_cap of the largest run that fits, or 0)
     bool any_exact_dos;            // some run is at theta = infinity
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
     const SweepItem *meas_items;   // device [n_meas_items]: groups per measure workgroup
@@ -50,5 +51,6 @@ int int8_tile_rows(int L);
 size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);
 int sweep_msc_resident(int threads, size_t lds);   // workgroups resident on the whole device, 0 on error
+hipError_t prepare_wang_lds(size_t bytes);
 
 }  // namespace pa

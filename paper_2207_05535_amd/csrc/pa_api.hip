@@ -365,6 +365,15 @@ void meas_items_of(const pa_run_desc &d, int run, int pop, std::vector<SweepItem
     for (int g = 0; g < groups_cap_of(d); g += gpw) out.push_back({run, pop, g, std::min(gpw, groups_cap_of(d) - g)});
 }
 
+int wang_lds_ints_of(const pa_run_desc *const *runs, int n, int lds_limit)
+{
+    int best = 0;
+    for (int r = 0; r < n; ++r)
+        if (is_wang(runs[r]->overlap) && 8 * (size_t)runs[r]->R_cap + 256 <= (size_t)lds_limit)
+            best = std::max(best, runs[r]->R_cap);
+    return 2 * best;
+}
+
 int default_groups(int L)
 {
     const int nh = L * L / 2;
@@ -603,6 +612,12 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
         std::vector<SweepItem> probe;
         size_t lds = 0;
         if (!plan_sweep(c, probe, lds)) return fail(PA_ERR_ARG);
+    }
+    if (c->any_wang) {
+        std::vector<const pa_run_desc *> dp(n_runs);
+        for (int r = 0; r < n_runs; ++r) dp[r] = &c->descs[r];
+        c->lc.wang_lds_ints = wang_lds_ints_of(dp.data(), n_runs, c->lds_limit);
+        if (prepare_wang_lds(sizeof(int32_t) * (size_t)c->lc.wang_lds_ints) != hipSuccess) return fail(PA_ERR_DEVICE);
     }
 
     hipStream_t s = c->stream;

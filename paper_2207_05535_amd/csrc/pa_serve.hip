@@ -306,6 +306,14 @@ pa_status rebuild(pa_server *s)
     c.npop_ctx = npop_ctx;
     c.any_multinomial = mn;
     c.any_wang = wang;
+    {
+        std::vector<const pa_run_desc *> dp;
+        for (int k = 0; k < s->max_slots; ++k)
+            if (s->slots[k].used) dp.push_back(&s->slots[k].d);
+        c.wang_lds_ints = wang_lds_ints_of(dp.data(), (int)dp.size(), s->lds_limit);
+        if (c.wang_lds_ints && prepare_wang_lds(sizeof(int32_t) * (size_t)c.wang_lds_ints) != hipSuccess)
+            return sfail(s);
+    }
     c.any_exact_dos = exact;
     c.sweep_items = (const SweepItem *)(s->base + s->sweep_off);
     c.n_sweep_items = (int)sweep.size();
@@ -530,6 +538,12 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     c.npop_ctx = npop;
     c.any_multinomial = d.resampling == PA_MULTINOMIAL;
     c.any_wang = is_wang(d.overlap);
+    {
+        const pa_run_desc *dp = &sl.d;
+        c.wang_lds_ints = wang_lds_ints_of(&dp, 1, s->lds_limit);
+        if (c.wang_lds_ints && prepare_wang_lds(sizeof(int32_t) * (size_t)c.wang_lds_ints) != hipSuccess)
+            return sfail(s);
+    }
     c.any_exact_dos = d.theta == PA_THETA_EXACT;
     if (launch_init(c, (const uint64_t *)(blk + b.dseed)) != hipSuccess || launch_measure(c) != hipSuccess)
         return sfail(s);

@@ -107,10 +107,12 @@ def test_large_families_leave_no_pairs(repr_, kind):
 
 @pytest.mark.parametrize("repr_", REPRS)
 @pytest.mark.parametrize("kind", [W.Q_WANG, W.Q_WANG_RDM])
-def test_full_size_spin_glass_pairing(repr_, kind):
-    """L = 32 +-J, R = 2 10^4, theta = 10, beta 0 -> 2.4 in 61 steps; every
-    fourth temperature is checked."""
-    L, R = 32, 20000
+@pytest.mark.parametrize("R", [20000, 24000])
+def test_full_size_spin_glass_pairing(repr_, kind, R):
+    """L = 32 +-J, R = 2 10^4 (the repair's labels fit in LDS) and 2.4 10^4
+    (they do not: the repair runs in global memory), theta = 10, beta 0 ->
+    2.4 in 61 steps; every fourth temperature is checked."""
+    L = 32
     N = L * L
     d = W.run_desc(L, W.EA_PMJ, seed=W.RUN_SEED_BASE + 0x5200 + kind, disorder_seed=W.DISORDER_SEED_BASE + 32,
                    R=R, theta=10, K=61, beta_f=2.4, resampling=W.MULTINOMIAL, overlap=kind, qhist=1)
