@@ -480,7 +480,8 @@ def cpu_baseline(desc, max_seconds=20.0):
         run.step(i)
         flips += int(run.obs()[0, i]["R_i"]) * d["theta"] * d["L"] ** 2
     dt = time.perf_counter() - t0
-    return dict(value=flips / dt / 1e9, unit="spin flips/ns", cores=1, kind="oracle",
+    return dict(value=flips / dt / 1e9, unit="spin flips/ns", cores=1, host_cores=os.cpu_count(),
+                kind="oracle",
                 sample=f"L=64 FM, R=2000 (of 100000), theta=10, temperature steps 1..{i} of the "
                        f"200-point schedule, whole steps (ii)-(v); {flips} flips in {dt:.1f} s")
 
@@ -620,6 +621,13 @@ def headline(desc, steps, warmup, args, only):
                      "peak": round(PEAK_LANE_OPS / 1e12, 4), "unit": "Tlane-op/s",
                      "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": traffic},
     }
+    # the same ceiling calibrated on the device: Philox calls back to back in
+    # registers (40 VALU instructions each), at the clock the chip holds
+    import paper_2207_05535_amd as pa
+    cal = pa.pa_calibrate_philox(4096)
+    line["roofline"]["calibrated_peak"] = round(40.0 * cal / 1e12, 4)
+    line["roofline"]["frac_of_calibrated"] = round(achieved / (40.0 * cal), 4)
+    line["roofline"]["philox_calls_per_s"] = cal
     if not args.no_plain and "plain" in only:
         p = run_plain(desc, steps, warmup, b["obs"][0, 0])
         N = desc["L"] ** 2

@@ -109,6 +109,16 @@ typedef struct {
  * and M^2 sums are zero and the configurations are not updated. */
 enum { PA_THETA_EXACT = -1 };
 
+/* Calibration of the integer-VALU ceiling (diagnostic; no context, no
+ * device memory): every lane of a grid that fills the device (2048
+ * workgroups of 256) runs two independent chains of calls_per_chain
+ * Philox4x32-10 calls in registers on hip_stream (NULL: the default
+ * stream); *calls_per_s receives the achieved rate, timed with HIP events.
+ * A call is 40 VALU instructions (10 rounds of two 32x32->64 multiplies
+ * and two three-input XORs), so 40 x *calls_per_s is the lane-op rate the
+ * sweep's Philox work can reach.  1 <= calls_per_chain <= 2^20. */
+pa_status pa_calibrate_philox(void *hip_stream, int32_t calls_per_chain, double *calls_per_s);
+
 /* Exact density of states of the periodic L x L ferromagnet (host
  * computation, no device): host_out[2m], host_out[2m + 1] receive the low
  * and high 64 bits of g_m, the number of configurations with

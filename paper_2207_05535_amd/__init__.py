@@ -86,6 +86,7 @@ def lib():
             "pa_read_state": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
             "pa_read_pairing": [vp, i32, vp, vp, vp],
             "pa_exact_dos": [i32, vp],
+            "pa_calibrate_philox": [vp, i32, vp],
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
             "pa_set_tuning": [vp, i32, i32, i32, i32],
@@ -215,6 +216,14 @@ def pa_read_obs(h, out):
 
 def pa_read_qhist(h, run, out):
     _chk("pa_read_qhist", lib().pa_read_qhist(h, run, _p(out)), h)
+
+
+def pa_calibrate_philox(calls_per_chain=4096, stream=None):
+    """Philox4x32-10 calls per second on the whole device, all in registers
+    (two independent chains per lane); 40 VALU instructions per call."""
+    out = C.c_double(0.0)
+    _chk("pa_calibrate_philox", lib().pa_calibrate_philox(stream, calls_per_chain, C.byref(out)))
+    return out.value
 
 
 def pa_exact_dos(L):

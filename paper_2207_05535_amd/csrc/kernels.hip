@@ -1907,6 +1907,30 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
     }
 }
 
+// Calibration: two independent chains of Philox calls per lane, all in
+// registers (the outputs feed the next call's counter); an empty statement
+// keeps the final values alive without a memory write.
+__global__ void __launch_bounds__(256) k_philox_rate(int calls, uint32_t k0, uint32_t k1)
+{
+    uint32_t a0 = threadIdx.x, a1 = blockIdx.x, a2 = 0, a3 = 1;
+    uint32_t b0 = threadIdx.x ^ 0x9E3779B9u, b1 = blockIdx.x, b2 = 2, b3 = 3;
+    for (int k = 0; k < calls; ++k) {
+        const u32x4 x = philox10(a0, a1, a2, a3, k0, k1);
+        const u32x4 y = philox10(b0, b1, b2, b3, k0, k1);
+        a0 = x.x; a1 = x.y; a2 = x.z; a3 = x.w;
+        b0 = y.x; b1 = y.y; b2 = y.z; b3 = y.w;
+    }
+    asm volatile("" ::"v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(b0), "v"(b1), "v"(b2), "v"(b3));
+}
+
+hipError_t launch_philox_rate(int calls, hipStream_t s, int *blocks, int *threads)
+{
+    *blocks = 2048;
+    *threads = 256;
+    k_philox_rate<<<*blocks, *threads, 0, s>>>(calls, 0x01234567u, 0x89ABCDEFu);
+    return hipGetLastError();
+}
+
 hipError_t prepare_wang_lds(size_t bytes)
 {
     if (bytes <= 65536) return hipSuccess;

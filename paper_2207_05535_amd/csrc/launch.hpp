@@ -52,5 +52,6 @@ size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);
 int sweep_msc_resident(int threads, size_t lds);   // workgroups resident on the whole device, 0 on error
 hipError_t prepare_wang_lds(size_t bytes);
+hipError_t launch_philox_rate(int calls, hipStream_t s, int *blocks, int *threads);
 
 }  // namespace pa

@@ -866,6 +866,26 @@ pa_status pa_read_qhist(pa_ctx *c, int32_t run, int32_t *host_out)
     return PA_OK;
 }
 
+pa_status pa_calibrate_philox(void *hip_stream, int32_t calls_per_chain, double *calls_per_s)
+{
+    if (calls_per_chain < 1 || calls_per_chain > (1 << 20) || !calls_per_s) return PA_ERR_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int blocks = 0, threads = 0;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    ok = ok && launch_philox_rate(1, s, &blocks, &threads) == hipSuccess;   // warm-up
+    ok = ok && hipEventRecord(e0, s) == hipSuccess;
+    ok = ok && launch_philox_rate(calls_per_chain, s, &blocks, &threads) == hipSuccess;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.f;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (!ok) return PA_ERR_DEVICE;
+    *calls_per_s = 2.0 * calls_per_chain * (double)blocks * threads / (ms * 1e-3);
+    return PA_OK;
+}
+
 pa_status pa_exact_dos(int32_t L, uint64_t *host_out)
 {
     if (L < 4 || L > 10 || (L & 1) || !host_out) return PA_ERR_ARG;

@@ -73,6 +73,14 @@ def test_workspace_size_rejects(bad):
     assert st == pa.PA_ERR_ARG
 
 
+def test_calibration_validates_before_the_device():
+    lib = pa.lib()
+    out = C.c_double(0.0)
+    assert lib.pa_calibrate_philox(None, 0, C.byref(out)) == pa.PA_ERR_ARG
+    assert lib.pa_calibrate_philox(None, (1 << 20) + 1, C.byref(out)) == pa.PA_ERR_ARG
+    assert lib.pa_calibrate_philox(None, 16, None) == pa.PA_ERR_ARG
+
+
 def test_exact_dos_validates_before_computing():
     lib = pa.lib()
     buf = np.zeros(2 * 145, np.uint64)
