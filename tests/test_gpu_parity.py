@@ -445,3 +445,37 @@ def test_tuning_shapes_do_not_change_results(threads, groups, dense, pooled):
         assert_obs_equal(obs[r, :orc.npop], orc.obs(), f"run {r}")
         assert_state_equal(ctx, orc, r, f"run {r} final")
     ctx.close()
+
+
+def test_sweep_statistics_are_shape_independent():
+    """The sweeps' counters (word-site updates, Philox calls, attempted flips)
+    are properties of the runs: a site makes exactly the calls up to the one
+    that decides its last undecided replica, whatever the representation,
+    launch shape, list scheme or tail.  Attempted flips equal
+    sum_i theta N R_i and word-sites sum_i theta N ceil(R_i / 64) over the
+    records, at every shape."""
+    runs = batch_runs()
+    say("sweep statistics across representations and shapes")
+    flips = words = 0
+    ctx = pa.Context(runs, "int8")
+    ctx.run(1, 16)
+    obs = ctx.obs()
+    for r, d in enumerate(runs):
+        for p in range(2 if d["overlap"] == W.Q_TWO_POP else 1):
+            Ri = obs[r, p, 1:]["R_i"].astype(np.int64)
+            flips += int((d["theta"] * d["L"] ** 2 * Ri).sum())
+            words += int((d["theta"] * d["L"] ** 2 * ((Ri + 63) // 64)).sum())
+    ref = ctx.stats()
+    ctx.close()
+    assert ref["flips"] == flips and ref["words"] == words, (ref, flips, words)
+    assert ref["calls"] > 0
+    for threads, groups, dense, pooled in [(64, 1, 0, 0), (256, 2, 3, 0), (1024, 1, 16, 0), (512, 1, 3, 0),
+                                           (64, 1, 0, 1), (1024, 2, 1, 1), (512, 1, 4, 1)]:
+        ctx = pa.Context(runs, "msc")
+        ctx.set_pooled(pooled)
+        for d in runs:
+            ctx.set_tuning(d["L"], threads, groups, dense)
+        ctx.run(1, 16)
+        got = ctx.stats()
+        ctx.close()
+        assert got == ref, (threads, groups, dense, pooled, got, ref)
