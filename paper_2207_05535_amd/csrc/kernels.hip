@@ -430,10 +430,15 @@ __global__ void __launch_bounds__(CH_THREADS) k_cnt_chunk(const ChunkItem *items
 // Multinomial draws: draw d picks the parent j with P_j <= t < P_j + X_j,
 // t = floor(v S_X / 2^64), v = o0 | o1 << 32 of Philox(seed; d, 0, i,
 // TAG_MN << 28 | pop << 24); P_j = base64[chunk] + chunk-local prefix.
+// CH_PER workgroups per chunk item: a run that fits one chunk is drawn by
+// the first of them alone; in larger runs each takes CH_THREADS draws, one
+// per thread (the searches are chains of dependent loads at scattered
+// addresses, so they are spread over as many compute units as possible).
 __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items, const RunInfo *runs,
                                                           const PopState *st)
 {
-    const ChunkItem it = items[blockIdx.x];
+    const int part = blockIdx.x % CH_PER;
+    const ChunkItem it = items[blockIdx.x / CH_PER];
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S) || R.resampling != PA_MULTINOMIAL) return;
@@ -450,6 +455,7 @@ __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items,
     if (R.R <= CH && Rp <= CH) {
         // the whole run in this workgroup: prefix and counts in LDS, the
         // counts are written out once (no global atomics)
+        if (part != 0) return;
         for (int j = threadIdx.x; j < Rp; j += CH_THREADS) {
             sP[j] = P[j];     // one chunk: base64[0] = 0
             sr[j] = 0;
@@ -481,28 +487,27 @@ __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items,
     if (staged)
         for (int k = threadIdx.x; k < nch; k += CH_THREADS) sB[k] = B[k];
     __syncthreads();
-    for (int q = 0; q < CH_PER; ++q) {
-        const int d = d0 + threadIdx.x + q * CH_THREADS;
-        if (d >= R.R) break;
-        const u32x4 o = philox10((uint32_t)d, 0, (uint32_t)S.i, c3, R.key0, R.key1);
-        const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
-        const uint64_t t = umul64hi(v, SX);
-        int klo = 0, khi = nch - 1;
-        while (klo < khi) {
-            const int mid = klo + ((khi - klo + 1) >> 1);
-            if ((staged ? sB[mid] : B[mid]) <= t) klo = mid;
-            else khi = mid - 1;
-        }
-        const uint64_t tl = t - (staged ? sB[klo] : B[klo]);
-        const uint64_t *Pk = P + (size_t)klo * CH;
-        int lo = 0, hi = min(CH, Rp - klo * CH) - 1;
-        while (lo < hi) {
-            const int mid = lo + ((hi - lo + 1) >> 1);
-            if (Pk[mid] <= tl) lo = mid;
-            else hi = mid - 1;
-        }
-        atomicAdd(&r[klo * CH + lo], 1);
+    // Fixed power-of-two steps: the largest index whose key is <= t,
+    // starting from index 0, whose key is 0.
+    const int d = d0 + part * CH_THREADS + (int)threadIdx.x;
+    if (d >= R.R) return;
+    const u32x4 o = philox10((uint32_t)d, 0, (uint32_t)S.i, c3, R.key0, R.key1);
+    const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
+    uint64_t t = umul64hi(v, SX);
+    int k = 0;
+    for (int step = nch > 1 ? 1 << (31 - __builtin_clz(nch - 1)) : 0; step > 0; step >>= 1) {
+        const int m = k + step;
+        if (m < nch && (staged ? sB[m] : B[m]) <= t) k = m;
     }
+    t -= staged ? sB[k] : B[k];
+    const uint64_t *Pk = P + (size_t)k * CH;
+    const int nk = min(CH, Rp - k * CH);
+    int lo = 0;
+    for (int step = CH / 2; step > 0; step >>= 1) {
+        const int m = lo + step;
+        if (m < nk && Pk[m] <= t) lo = m;
+    }
+    atomicAdd(&r[k * CH + lo], 1);
 }
 
 // Multinomial: chunk-local exclusive prefix of the counts r.
@@ -591,8 +596,12 @@ __global__ void k_cnt_finish(const RunInfo *runs, PopState *st)
     }
 }
 
-// Parent of every child slot c < R_i: the largest j with C_j <= c (then
-// r_j > 0), C_j = base32[chunk] + chunk-local prefix.
+// Parent of every child slot: parent j's r_j children occupy the slots
+// C_j .. C_j + r_j - 1 (C_j = base32[chunk] + chunk-local prefix), so each
+// parent writes its own.  A lane writes the first few; the slots of larger
+// families are written by the whole wavefront, one family at a time.
+constexpr int PARENT_LANE_MAX = 4;
+
 __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, const RunInfo *runs,
                                                         const PopState *st)
 {
@@ -600,55 +609,31 @@ __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, c
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
-    const int Rc = S.Rcur, Rp = S.Rprev;
-    const int c0 = it.chunk * CH;
-    if (c0 >= Rc) return;
+    const int Rp = S.Rprev;
+    const int j0 = it.chunk * CH;
+    if (j0 >= Rp) return;
+    const int lane = threadIdx.x & 63;
     const int32_t *C = R.C[it.pop];
-    const int32_t *B = R.base32[it.pop];
+    const int32_t *r = R.r[it.pop];
+    const int32_t base = R.base32[it.pop][it.chunk];
     int32_t *par = R.parent[it.pop];
-    if (Rp <= CH) {
-        // one chunk of parents (base32[0] = 0): search the prefix in LDS
-        __shared__ int32_t sC[CH];
-        for (int j = threadIdx.x; j < Rp; j += CH_THREADS) sC[j] = C[j];
-        __syncthreads();
-        for (int q = 0; q < CH_PER; ++q) {
-            const int c = c0 + threadIdx.x + q * CH_THREADS;
-            if (c >= Rc) break;
-            int lo = 0, hi = Rp - 1;
-            while (lo < hi) {
-                const int mid = lo + ((hi - lo + 1) >> 1);
-                if (sC[mid] <= c) lo = mid;
-                else hi = mid - 1;
-            }
-            par[c] = lo;
-        }
-        return;
-    }
-    // largest j with C_j <= c in two levels, as for the multinomial draws
-    const int nch = (Rp + CH - 1) / CH;
-    __shared__ int32_t sB[CH];
-    const bool staged = nch <= CH;
-    if (staged)
-        for (int k = threadIdx.x; k < nch; k += CH_THREADS) sB[k] = B[k];
-    __syncthreads();
+#pragma unroll
     for (int q = 0; q < CH_PER; ++q) {
-        const int c = c0 + threadIdx.x + q * CH_THREADS;
-        if (c >= Rc) break;
-        int klo = 0, khi = nch - 1;
-        while (klo < khi) {
-            const int mid = klo + ((khi - klo + 1) >> 1);
-            if ((staged ? sB[mid] : B[mid]) <= c) klo = mid;
-            else khi = mid - 1;
+        const int j = j0 + q * CH_THREADS + (int)threadIdx.x;
+        int rj = 0, cj = 0;
+        if (j < Rp) {
+            rj = r[j];
+            cj = base + C[j];
         }
-        const int cl = c - (staged ? sB[klo] : B[klo]);
-        const int32_t *Ck = C + (size_t)klo * CH;
-        int lo = 0, hi = min(CH, Rp - klo * CH) - 1;
-        while (lo < hi) {
-            const int mid = lo + ((hi - lo + 1) >> 1);
-            if (Ck[mid] <= cl) lo = mid;
-            else hi = mid - 1;
+        const int mine = min(rj, PARENT_LANE_MAX);
+        for (int m = 0; m < mine; ++m) par[cj + m] = j;
+        uint64_t big = __ballot(rj > PARENT_LANE_MAX);
+        while (big) {
+            const int src = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            const int bj = __shfl(j, src, 64), bc = __shfl(cj, src, 64), br = __shfl(rj, src, 64);
+            for (int m = PARENT_LANE_MAX + lane; m < br; m += 64) par[bc + m] = bj;
         }
-        par[c] = klo * CH + lo;
     }
 }
 
@@ -2480,7 +2465,7 @@ hipError_t launch_resample(const LaunchCtx &c)
     k_cnt_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
     if (c.any_multinomial) {
-        k_mn_draws<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
+        k_mn_draws<<<c.n_chunk_items * CH_PER, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
         PA_CHECK_LAUNCH();
         k_cnt_scan_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
         PA_CHECK_LAUNCH();
