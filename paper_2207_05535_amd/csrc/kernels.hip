@@ -84,36 +84,36 @@ __device__ __forceinline__ uint32_t lane_xor(uint32_t v)
     }
 }
 
-// One block-swap stage of the transpose for J < 32 with mask m (the bits a
-// lane without bit J keeps in each 32-bit half).  A lane keeps half of its
-// bits and needs the other half from lane ^ J; the half its partner needs
-// is packed into one 32-bit word, so each stage is one exchange.
+// One block-swap stage of the transpose for J < 32, on each 32-bit half:
+// m holds the bit positions without bit J.  A lane without bit J keeps
+// those and sends the others, moved down by J; its partner (lane ^ J) keeps
+// the others and sends those, moved up by J.  Both moves are one rotation
+// (right by J, or by 32 - J) followed by the kept-bits mask, since the bits
+// that wrap around land outside it; no branch on the lane's side.
 template <int J>
 __device__ __forceinline__ void transpose_stage(uint32_t &lo, uint32_t &hi, uint32_t m)
 {
-    const bool up = threadIdx.x & J;
-    const uint32_t send = up ? ((lo & m) | ((hi & m) << J)) : (((lo & ~m) >> J) | (hi & ~m));
-    const uint32_t r = lane_xor<J>(send);
-    if (up) {
-        lo = (lo & ~m) | (r & m);
-        hi = (hi & ~m) | ((r & ~m) >> J);
-    } else {
-        lo = (lo & m) | ((r & m) << J);
-        hi = (hi & m) | (r & ~m);
-    }
+    const uint32_t up = 0u - ((threadIdx.x / J) & 1u);   // all ones on lanes with bit J
+    const uint32_t keep = m ^ up;
+    const uint32_t sh = J + (up & (32u - 2u * J));
+    const uint32_t slo = __builtin_amdgcn_alignbit(lo, lo, sh) & keep;
+    const uint32_t shi = __builtin_amdgcn_alignbit(hi, hi, sh) & keep;
+    lo = (lo & keep) | lane_xor<J>(slo);
+    hi = (hi & keep) | lane_xor<J>(shi);
 }
 
 // 64 x 64 bit transpose across a wavefront: lane r holds row r (bit c =
 // element (r, c)); on return lane r holds column r.  Six block-swap stages
-// (distances 32, 16, 8, 4, 2, 1), one 32-bit exchange each.
+// (distances 32, 16, 8, 4, 2, 1): the first exchanges one 32-bit half, the
+// others exchange within each half.
 __device__ __forceinline__ uint64_t transpose64(uint64_t x)
 {
     uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
     {
         const bool up = threadIdx.x & 32;
         const uint32_t r = lane_xor<32>(up ? lo : hi);
-        if (up) lo = r;
-        else hi = r;
+        lo = up ? r : lo;
+        hi = up ? hi : r;
     }
     transpose_stage<16>(lo, hi, 0x0000FFFFu);
     transpose_stage<8>(lo, hi, 0x00FF00FFu);
@@ -731,13 +731,25 @@ __device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, 
     }
 }
 
+// Workgroup b of a launch runs on XCD b mod 8 (round-robin dispatch, one L2
+// per XCD).  The item taken by b gives every XCD a contiguous range of
+// items, so neighbouring items share their XCD's L2.  A bijection of
+// [0, n) for any n.
+__device__ __forceinline__ int xcd_item(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 // Workgroups of MEAS_WAVES wavefronts over the measure items: each group
-// gets meas_waves_per_group(N) wavefronts, which split its sites.
+// gets meas_waves_per_group(N) wavefronts, which split its sites.  The
+// children of neighbouring groups have parents in shared source groups, so
+// neighbouring items run on one XCD.
 template <int REPR>
 __global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, const RunInfo *runs,
                                                        const PopState *st)
 {
-    const SweepItem it = items[blockIdx.x];
+    const SweepItem it = items[xcd_item(blockIdx.x, gridDim.x)];
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
