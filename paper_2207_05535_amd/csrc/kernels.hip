@@ -2031,19 +2031,25 @@ __global__ void __launch_bounds__(CH_THREADS) k_meas_chunk(const ChunkItem *item
     }
     // families
     const int32_t *fam = R.fam[it.pop][S.cur];
-    if (threadIdx.x == 0) {
+    if (wv == 0) {
+        // first index with the label of replica j0 (labels ascend): a
+        // 64-way search by the whole wavefront, the first such index lying
+        // in [lo, hi] with fam[hi] equal to the label
         int fs = j0;
         if (j0 > 0 && fam[j0 - 1] == fam[j0]) {
             const int32_t f = fam[j0];
-            int lo = 0, hi = j0;   // first index with label f
+            int lo = 0, hi = j0 - 1;
             while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (fam[mid] < f) lo = mid + 1;
-                else hi = mid;
+                const int step = (hi - lo + 63) / 64;
+                const int p = lo + lane * step;
+                const int c = __popcll(__ballot(p < hi && fam[p] < f));   // probes below the first index
+                if (c == 0) break;   // fam[lo] is the label
+                lo += (c - 1) * step + 1;
+                hi = min(hi, lo - 1 + step);
             }
             fs = lo;
         }
-        first_start = fs;
+        if (lane == 0) first_start = fs;
     }
     const int jb = j0 + threadIdx.x * CH_PER;
     int32_t lab[CH_PER];
