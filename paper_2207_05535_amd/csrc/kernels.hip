@@ -430,15 +430,16 @@ __global__ void __launch_bounds__(CH_THREADS) k_cnt_chunk(const ChunkItem *items
 // Multinomial draws: draw d picks the parent j with P_j <= t < P_j + X_j,
 // t = floor(v S_X / 2^64), v = o0 | o1 << 32 of Philox(seed; d, 0, i,
 // TAG_MN << 28 | pop << 24); P_j = base64[chunk] + chunk-local prefix.
-// CH_PER workgroups per chunk item: a run that fits one chunk is drawn by
-// the first of them alone; in larger runs each takes CH_THREADS draws, one
-// per thread (the searches are chains of dependent loads at scattered
-// addresses, so they are spread over as many compute units as possible).
+// `split` workgroups per chunk item (1 or CH_PER): a run that fits one
+// chunk is drawn by the first of them alone; in larger runs each takes
+// CH_PER / split rounds of CH_THREADS draws, one per thread and round (the
+// searches are chains of dependent loads at scattered addresses, so with
+// split = CH_PER they are spread over as many compute units as possible).
 __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items, const RunInfo *runs,
-                                                          const PopState *st)
+                                                          const PopState *st, int split)
 {
-    const int part = blockIdx.x % CH_PER;
-    const ChunkItem it = items[blockIdx.x / CH_PER];
+    const int part = blockIdx.x % split;
+    const ChunkItem it = items[blockIdx.x / split];
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S) || R.resampling != PA_MULTINOMIAL) return;
@@ -489,25 +490,27 @@ __global__ void __launch_bounds__(CH_THREADS) k_mn_draws(const ChunkItem *items,
     __syncthreads();
     // Fixed power-of-two steps: the largest index whose key is <= t,
     // starting from index 0, whose key is 0.
-    const int d = d0 + part * CH_THREADS + (int)threadIdx.x;
-    if (d >= R.R) return;
-    const u32x4 o = philox10((uint32_t)d, 0, (uint32_t)S.i, c3, R.key0, R.key1);
-    const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
-    uint64_t t = umul64hi(v, SX);
-    int k = 0;
-    for (int step = nch > 1 ? 1 << (31 - __builtin_clz(nch - 1)) : 0; step > 0; step >>= 1) {
-        const int m = k + step;
-        if (m < nch && (staged ? sB[m] : B[m]) <= t) k = m;
+    for (int q = part; q < CH_PER; q += split) {
+        const int d = d0 + q * CH_THREADS + (int)threadIdx.x;
+        if (d >= R.R) break;
+        const u32x4 o = philox10((uint32_t)d, 0, (uint32_t)S.i, c3, R.key0, R.key1);
+        const uint64_t v = (uint64_t)o.x | ((uint64_t)o.y << 32);
+        uint64_t t = umul64hi(v, SX);
+        int k = 0;
+        for (int step = nch > 1 ? 1 << (31 - __builtin_clz(nch - 1)) : 0; step > 0; step >>= 1) {
+            const int m = k + step;
+            if (m < nch && (staged ? sB[m] : B[m]) <= t) k = m;
+        }
+        t -= staged ? sB[k] : B[k];
+        const uint64_t *Pk = P + (size_t)k * CH;
+        const int nk = min(CH, Rp - k * CH);
+        int lo = 0;
+        for (int step = CH / 2; step > 0; step >>= 1) {
+            const int m = lo + step;
+            if (m < nk && Pk[m] <= t) lo = m;
+        }
+        atomicAdd(&r[k * CH + lo], 1);
     }
-    t -= staged ? sB[k] : B[k];
-    const uint64_t *Pk = P + (size_t)k * CH;
-    const int nk = min(CH, Rp - k * CH);
-    int lo = 0;
-    for (int step = CH / 2; step > 0; step >>= 1) {
-        const int m = lo + step;
-        if (m < nk && Pk[m] <= t) lo = m;
-    }
-    atomicAdd(&r[k * CH + lo], 1);
 }
 
 // Multinomial: chunk-local exclusive prefix of the counts r.
@@ -2483,7 +2486,8 @@ hipError_t launch_resample(const LaunchCtx &c)
     k_cnt_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
     if (c.any_multinomial) {
-        k_mn_draws<<<c.n_chunk_items * CH_PER, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
+        k_mn_draws<<<c.n_chunk_items * c.mn_split, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st,
+                                                                              c.mn_split);
         PA_CHECK_LAUNCH();
         k_cnt_scan_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
         PA_CHECK_LAUNCH();

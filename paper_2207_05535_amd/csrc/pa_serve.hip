@@ -238,7 +238,7 @@ pa_status rebuild(pa_server *s)
 {
     size_t n_items = 0, n_chunks = 0, n_meas = 0;
     int hi = 0, npop_ctx = 1;
-    bool mn = false, wang = false, exact = false;
+    bool mn = false, wang = false, exact = false, mn_wide = false;
     std::vector<SweepItem> sweep;
     size_t lds = 0;
     for (int k = 0; k < s->max_slots; ++k) {
@@ -251,6 +251,7 @@ pa_status rebuild(pa_server *s)
         hi = k + 1;
         npop_ctx = std::max(npop_ctx, npop);
         mn = mn || sl.d.resampling == PA_MULTINOMIAL;
+        mn_wide = mn_wide || (sl.d.resampling == PA_MULTINOMIAL && sl.d.R > CH);
         wang = wang || is_wang(sl.d.overlap);
         exact = exact || sl.d.theta == PA_THETA_EXACT;
         if (s->repr == PA_MSC64) {
@@ -305,6 +306,7 @@ pa_status rebuild(pa_server *s)
     c.n_runs = hi;
     c.npop_ctx = npop_ctx;
     c.any_multinomial = mn;
+    c.mn_split = mn_wide ? CH_PER : 1;
     c.any_wang = wang;
     {
         std::vector<const pa_run_desc *> dp;
@@ -537,6 +539,7 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     c.n_runs = 1;
     c.npop_ctx = npop;
     c.any_multinomial = d.resampling == PA_MULTINOMIAL;
+    c.mn_split = d.resampling == PA_MULTINOMIAL && d.R > CH ? CH_PER : 1;
     c.any_wang = is_wang(d.overlap);
     {
         const pa_run_desc *dp = &sl.d;
