@@ -126,6 +126,67 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x)
 // Bit-sliced (vertical) counters: plane k holds bit k of 64 per-lane counts.
 constexpr int VB = 6;   // counts up to 63 per lane
 
+// Carry-save counting of a block of 16 sites per lane, Harley and Seal's
+// scheme in bit-sliced form: a three-input adder (sum = XOR, carry =
+// majority, one bitop3 each per 32 bits) folds each site's inputs into the
+// ones plane and passes its carry up; carries of equal weight wait for a
+// partner from a later site, so after the 16th site the planes ones, twos,
+// fours, eights and the sixteens are the binary digits of every lane's count.
+// The site index t must be a compile-time constant after unrolling (it
+// decides which carries pair up), and every block takes exactly 16 sites
+// (zero inputs for missing ones).
+constexpr int LUT_MAJ3 = lut3((LUT_A & LUT_B) | (LUT_A & LUT_C) | (LUT_B & LUT_C));
+
+__device__ __forceinline__ void csa(uint64_t &carry, uint64_t &sum, uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint64_t s = bop3<LUT_XOR3>(a, b, c);
+    carry = bop3<LUT_MAJ3>(a, b, c);
+    sum = s;
+}
+
+// One input per site: counts up to 16 in five planes.
+struct Csa1 {
+    uint64_t p1 = 0, p2 = 0, p4 = 0, p8 = 0, p16 = 0, w1 = 0, w2 = 0, w4 = 0, w8 = 0;
+    __device__ __forceinline__ void add(int t, uint64_t a)
+    {
+        if (!(t & 1)) { w1 = a; return; }
+        uint64_t c2, c4, c8;
+        csa(c2, p1, p1, w1, a);
+        if (!(t & 2)) { w2 = c2; return; }
+        csa(c4, p2, p2, w2, c2);
+        if (!(t & 4)) { w4 = c4; return; }
+        csa(c8, p4, p4, w4, c4);
+        if (!(t & 8)) { w8 = c8; return; }
+        csa(p16, p8, p8, w8, c8);
+    }
+    __device__ __forceinline__ void planes(uint64_t (&p)[VB]) const
+    {
+        p[0] = p1; p[1] = p2; p[2] = p4; p[3] = p8; p[4] = p16; p[5] = 0;
+    }
+};
+
+// Two inputs per site: counts up to 32 in six planes.
+struct Csa2 {
+    uint64_t p1 = 0, p2 = 0, p4 = 0, p8 = 0, s16a = 0, s16b = 0, w2 = 0, w4 = 0, w8 = 0;
+    __device__ __forceinline__ void add(int t, uint64_t a, uint64_t b)
+    {
+        uint64_t c2, c4, c8;
+        csa(c2, p1, p1, a, b);
+        if (!(t & 1)) { w2 = c2; return; }
+        csa(c4, p2, p2, w2, c2);
+        if (!(t & 2)) { w4 = c4; return; }
+        csa(c8, p4, p4, w4, c4);
+        if (!(t & 4)) { w8 = c8; return; }
+        csa((t & 8) ? s16b : s16a, p8, p8, w8, c8);
+    }
+    __device__ __forceinline__ void planes(uint64_t (&p)[VB]) const
+    {
+        p[0] = p1; p[1] = p2; p[2] = p4; p[3] = p8; p[4] = s16a ^ s16b; p[5] = s16a & s16b;
+    }
+};
+
+// Incremental form (a half-adder chain per input), used where fewer
+// registers matter more than fewer operations.
 __device__ __forceinline__ void vinc(uint64_t (&p)[VB], uint64_t x)
 {
 #pragma unroll
@@ -1352,7 +1413,7 @@ __device__ __forceinline__ uint64_t load_word(const uint8_t *buf, int g, int n, 
 // transposes, the wavefronts of a group are summed in LDS, the energies are
 // stored, and the group's integer sums go to its slot of the partial-sum
 // array; k_meas_chunk reduces those per chunk.
-template <int REPR, int LT>
+template <int REPR, int LT, bool WITH_Q>
 __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int sub, int wpg, bool live,
                                               const RunInfo &R, const PopState &S, const PopState *st,
                                               uint32_t (*red)[MEAS_WAVES][64])
@@ -1368,7 +1429,9 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     const uint8_t *pbuf = buf;
     int pg = 0, sh = 0;
     const int pgroups = R.groups_cap;
-    if (live && R.overlap == PA_Q_INDEX_SHIFT) {
+    if (!WITH_Q) {
+        // no run of the launch measures overlaps
+    } else if (live && R.overlap == PA_Q_INDEX_SHIFT) {
         const int h = Rc >> 1;
         const int lo = g * 64;
         if (lo < h) {
@@ -1422,60 +1485,99 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
         }
         return;
     }
-    uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
     uint32_t totU = 0, totD = 0, totH = 0, totK = 0;
     // every lane of the wavefront runs the same iterations (flushes are
-    // wave-wide); lanes past the last site only skip the work.  Counters are
-    // flushed after every 16 sites per lane (at most 2 per site: 32 < 2^VB);
-    // mode is uniform over the wavefront, so are the overlap flushes.
-    for (int b0 = 64 * sub; b0 < N; b0 += 16 * 64 * wpg) {
-        // sites per lane in this block of 16 (uniform): bounds the counts
-        const int tsites = min(16, (N - b0 + 64 * wpg - 1) / (64 * wpg));
+    // wave-wide).  Counts are flushed after every block of 16 sites per lane
+    // (at most 2 per site: 32 < 2^VB); mode is uniform over the wavefront, so
+    // are the overlap counts.
+    if constexpr (WITH_Q) {
+        // four counters: the incremental form keeps the loop within the
+        // registers of four wavefronts per SIMD
+        uint64_t cU[VB] = {}, cD[VB] = {}, cH[VB] = {}, cK[VB] = {};
+        for (int b0 = 64 * sub; b0 < N; b0 += 16 * 64 * wpg) {
+            // sites per lane in this block of 16 (uniform): bounds the counts
+            const int tsites = min(16, (N - b0 + 64 * wpg - 1) / (64 * wpg));
 #pragma unroll 4
-        for (int t = 0; t < 16; ++t) {
-            const int n = b0 + t * 64 * wpg + lane;
-            if (live && n < N) {
-                const int y = n / L, x = n - y * L;
-                const int nr = y * L + (x + 1 == L ? 0 : x + 1);
-                const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
-                const uint8_t jn = R.jbits[n];
-                const uint64_t w = load_word<REPR>(buf, g, n, N);
-                const uint64_t wr = load_word<REPR>(buf, g, nr, N);
-                const uint64_t wd = load_word<REPR>(buf, g, nd, N);
-                const uint64_t br = w ^ wr, bd = w ^ wd;
-                vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
-                vinc(cD, w);
-                if (mode) {
-                    uint64_t q, qr, qd;
-                    if (mode == 3) {
-                        const uint64_t *pw = (const uint64_t *)pbuf + (size_t)pg * N;
-                        q = pw[n];
-                        qr = pw[nr];
-                        qd = pw[nd];
-                    } else if (mode == 1 && sh) {
-                        const bool two = pg + 1 < pgroups;
-                        q = (load_word<REPR>(buf, pg, n, N) >> sh) |
-                            (two ? load_word<REPR>(buf, pg + 1, n, N) << (64 - sh) : 0ull);
-                        qr = (load_word<REPR>(buf, pg, nr, N) >> sh) |
-                             (two ? load_word<REPR>(buf, pg + 1, nr, N) << (64 - sh) : 0ull);
-                        qd = (load_word<REPR>(buf, pg, nd, N) >> sh) |
-                             (two ? load_word<REPR>(buf, pg + 1, nd, N) << (64 - sh) : 0ull);
-                    } else {
-                        q = load_word<REPR>(pbuf, pg, n, N);
-                        qr = load_word<REPR>(pbuf, pg, nr, N);
-                        qd = load_word<REPR>(pbuf, pg, nd, N);
+            for (int t = 0; t < 16; ++t) {
+                const int n = b0 + t * 64 * wpg + lane;
+                if (live && n < N) {
+                    const int y = n / L, x = n - y * L;
+                    const int nr = y * L + (x + 1 == L ? 0 : x + 1);
+                    const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
+                    const uint8_t jn = R.jbits[n];
+                    const uint64_t w = load_word<REPR>(buf, g, n, N);
+                    const uint64_t wr = load_word<REPR>(buf, g, nr, N);
+                    const uint64_t wd = load_word<REPR>(buf, g, nd, N);
+                    const uint64_t br = w ^ wr, bd = w ^ wd;
+                    vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
+                    vinc(cD, w);
+                    if (mode) {
+                        uint64_t q, qr, qd;
+                        if (mode == 3) {
+                            const uint64_t *pw = (const uint64_t *)pbuf + (size_t)pg * N;
+                            q = pw[n];
+                            qr = pw[nr];
+                            qd = pw[nd];
+                        } else if (mode == 1 && sh) {
+                            const bool two = pg + 1 < pgroups;
+                            q = (load_word<REPR>(buf, pg, n, N) >> sh) |
+                                (two ? load_word<REPR>(buf, pg + 1, n, N) << (64 - sh) : 0ull);
+                            qr = (load_word<REPR>(buf, pg, nr, N) >> sh) |
+                                 (two ? load_word<REPR>(buf, pg + 1, nr, N) << (64 - sh) : 0ull);
+                            qd = (load_word<REPR>(buf, pg, nd, N) >> sh) |
+                                 (two ? load_word<REPR>(buf, pg + 1, nd, N) << (64 - sh) : 0ull);
+                        } else {
+                            q = load_word<REPR>(pbuf, pg, n, N);
+                            qr = load_word<REPR>(pbuf, pg, nr, N);
+                            qd = load_word<REPR>(pbuf, pg, nd, N);
+                        }
+                        vinc(cH, w ^ q);
+                        vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
                     }
-                    vinc(cH, w ^ q);
-                    vinc2(cK, br ^ q ^ qr, bd ^ q ^ qd);
                 }
             }
+            const int p1 = planes_for(tsites), p2 = planes_for(2 * tsites);
+            totU += vflush(cU, p2);
+            totD += vflush(cD, p1);
+            if (mode) {
+                totH += vflush(cH, p1);
+                totK += vflush(cK, p2);
+            }
         }
-        const int p1 = planes_for(tsites), p2 = planes_for(2 * tsites);
-        totU += vflush(cU, p2);
-        totD += vflush(cD, p1);
-        if (mode) {
-            totH += vflush(cH, p1);
-            totK += vflush(cK, p2);
+    } else {
+        // energies and magnetisations only: carry-save counting
+        for (int b0 = 64 * sub; b0 < N; b0 += 16 * 64 * wpg) {
+            const int tsites = min(16, (N - b0 + 64 * wpg - 1) / (64 * wpg));
+            Csa2 cU;
+            Csa1 cD;
+            // two sites unrolled at a time (their loads in flight together);
+            // the carries of weight 4 and up pair up on uniform branches
+#pragma unroll 1
+            for (int t2 = 0; t2 < 16; t2 += 2)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = t2 + u;
+                const int n = b0 + t * 64 * wpg + lane;
+                uint64_t w = 0, ur = 0, ud = 0;   // zero inputs past the last site
+                if (live && n < N) {
+                    const int y = n / L, x = n - y * L;
+                    const int nr = y * L + (x + 1 == L ? 0 : x + 1);
+                    const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
+                    const uint8_t jn = R.jbits[n];
+                    w = load_word<REPR>(buf, g, n, N);
+                    const uint64_t wr = load_word<REPR>(buf, g, nr, N);
+                    const uint64_t wd = load_word<REPR>(buf, g, nd, N);
+                    ur = w ^ wr ^ ((jn & 1) ? ~0ull : 0ull);
+                    ud = w ^ wd ^ ((jn & 2) ? ~0ull : 0ull);
+                }
+                cU.add(t, ur, ud);
+                cD.add(t, w);
+            }
+            uint64_t pl[VB];
+            cU.planes(pl);
+            totU += vflush(pl, planes_for(2 * tsites));
+            cD.planes(pl);
+            totD += vflush(pl, planes_for(tsites));
         }
     }
     if (wpg > 1) {
@@ -1528,7 +1630,7 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     }
 }
 
-template <int REPR>
+template <int REPR, bool WITH_Q>
 __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items, const RunInfo *runs,
                                                           const PopState *st)
 {
@@ -1543,13 +1645,13 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
     const int g = it.group0 + k;
     const bool live = k < it.ngroups && g * 64 < S.Rcur;
     switch (R.L) {
-    case 8: measure_group<REPR, 8>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 16: measure_group<REPR, 16>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 24: measure_group<REPR, 24>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 32: measure_group<REPR, 32>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 48: measure_group<REPR, 48>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 64: measure_group<REPR, 64>(it, g, sub, wpg, live, R, S, st, red); break;
-    default: measure_group<REPR, 0>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 8: measure_group<REPR, 8, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 16: measure_group<REPR, 16, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 24: measure_group<REPR, 24, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 32: measure_group<REPR, 32, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 48: measure_group<REPR, 48, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 64: measure_group<REPR, 64, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    default: measure_group<REPR, 0, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
     }
 }
 
@@ -2600,10 +2702,16 @@ hipError_t launch_measure(const LaunchCtx &c)
         PA_CHECK_LAUNCH();
     }
     if (c.n_meas_items > 0) {
-        if (c.repr == PA_MSC64)
-            k_measure<PA_MSC64><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+        // the variant without overlap counters when no run measures overlaps
+        // (fewer registers live in the site loop)
+        if (c.repr == PA_MSC64 && c.any_overlap)
+            k_measure<PA_MSC64, true><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+        else if (c.repr == PA_MSC64)
+            k_measure<PA_MSC64, false><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+        else if (c.any_overlap)
+            k_measure<PA_INT8, true><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
         else
-            k_measure<PA_INT8><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+            k_measure<PA_INT8, false><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
         PA_CHECK_LAUNCH();
     }
     k_meas_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);

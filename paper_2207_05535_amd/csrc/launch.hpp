@@ -17,6 +17,7 @@ struct LaunchCtx {
     int run0, n_runs, npop_ctx;    // per-run launches cover runs [run0, run0 + n_runs)
     int repr;
     bool any_multinomial;
+    bool any_overlap = true;       // some run measures overlaps (index shift, two populations, pairing)
     int mn_split = CH_PER;         // workgroups per chunk of multinomial draws: CH_PER if a run spans chunks, else 1
     bool any_wang;                 // some run pairs replicas by permutations
     int wang_lds_ints;             // LDS of the pairing repair (2 R_cap of the largest run that fits, or 0)

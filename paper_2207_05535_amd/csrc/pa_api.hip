@@ -592,8 +592,11 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.repr = repr;
     c->lc.any_multinomial = c->any_multinomial;
     c->lc.mn_split = 1;
-    for (int r = 0; r < n_runs; ++r)
+    c->lc.any_overlap = false;
+    for (int r = 0; r < n_runs; ++r) {
         if (runs[r].resampling == PA_MULTINOMIAL && runs[r].R > CH) c->lc.mn_split = CH_PER;
+        if (runs[r].overlap != PA_Q_NONE) c->lc.any_overlap = true;
+    }
     c->lc.any_wang = c->any_wang;
     c->lc.any_exact_dos = c->any_exact_dos;
     c->lc.stats = at<unsigned long long>(c, Lo.stats);

@@ -238,7 +238,7 @@ pa_status rebuild(pa_server *s)
 {
     size_t n_items = 0, n_chunks = 0, n_meas = 0;
     int hi = 0, npop_ctx = 1;
-    bool mn = false, wang = false, exact = false, mn_wide = false;
+    bool mn = false, wang = false, exact = false, mn_wide = false, ovl = false;
     std::vector<SweepItem> sweep;
     size_t lds = 0;
     for (int k = 0; k < s->max_slots; ++k) {
@@ -252,6 +252,7 @@ pa_status rebuild(pa_server *s)
         npop_ctx = std::max(npop_ctx, npop);
         mn = mn || sl.d.resampling == PA_MULTINOMIAL;
         mn_wide = mn_wide || (sl.d.resampling == PA_MULTINOMIAL && sl.d.R > CH);
+        ovl = ovl || sl.d.overlap != PA_Q_NONE;
         wang = wang || is_wang(sl.d.overlap);
         exact = exact || sl.d.theta == PA_THETA_EXACT;
         if (s->repr == PA_MSC64) {
@@ -307,6 +308,7 @@ pa_status rebuild(pa_server *s)
     c.npop_ctx = npop_ctx;
     c.any_multinomial = mn;
     c.mn_split = mn_wide ? CH_PER : 1;
+    c.any_overlap = ovl;
     c.any_wang = wang;
     {
         std::vector<const pa_run_desc *> dp;
@@ -540,6 +542,7 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     c.npop_ctx = npop;
     c.any_multinomial = d.resampling == PA_MULTINOMIAL;
     c.mn_split = d.resampling == PA_MULTINOMIAL && d.R > CH ? CH_PER : 1;
+    c.any_overlap = d.overlap != PA_Q_NONE;
     c.any_wang = is_wang(d.overlap);
     {
         const pa_run_desc *dp = &sl.d;
