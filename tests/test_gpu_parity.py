@@ -479,3 +479,25 @@ def test_sweep_statistics_are_shape_independent():
         got = ctx.stats()
         ctx.close()
         assert got == ref, (threads, groups, dense, pooled, got, ref)
+
+
+@pytest.mark.parametrize("repr_", REPRS)
+def test_multichunk_and_small_runs_in_one_context(repr_):
+    """A run of several 2048-replica chunks next to single-chunk runs: the
+    multinomial draws of the large run spread over several workgroups per
+    chunk while the small runs draw in one, families crossing chunk
+    boundaries at low temperature; every record and the final state equal
+    the oracle's."""
+    runs = [W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x7100, R=5000, theta=2, K=14, beta_f=1.2),
+            W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x7101, R=300, theta=2, K=14, beta_f=1.2),
+            W.run_desc(6, W.FM, seed=W.RUN_SEED_BASE + 0x7102, R=2100, theta=1, K=14, beta_f=1.2,
+                       resampling=W.NEAREST_INT)]
+    say(f"multi-chunk and small runs {repr_}")
+    ctx = pa.Context(runs, repr_)
+    ctx.run(1, 14)
+    obs = ctx.obs()
+    for r, d in enumerate(runs):
+        orc = oracle.OracleRun(d).run_all()
+        assert_obs_equal(obs[r, :orc.npop], orc.obs(), f"run {r}")
+        assert_state_equal(ctx, orc, r, f"run {r} final")
+    ctx.close()
