@@ -132,9 +132,9 @@ constexpr int VB = 6;   // counts up to 63 per lane
 // ones plane and passes its carry up; carries of equal weight wait for a
 // partner from a later site, so after the 16th site the planes ones, twos,
 // fours, eights and the sixteens are the binary digits of every lane's count.
-// The site index t must be a compile-time constant after unrolling (it
-// decides which carries pair up), and every block takes exactly 16 sites
-// (zero inputs for missing ones).
+// The site index t (the same on every lane) decides which carries pair up;
+// every block takes exactly the 16 sites t = 0 .. 15 in order (zero inputs
+// for missing ones).
 constexpr int LUT_MAJ3 = lut3((LUT_A & LUT_B) | (LUT_A & LUT_C) | (LUT_B & LUT_C));
 
 __device__ __forceinline__ void csa(uint64_t &carry, uint64_t &sum, uint64_t a, uint64_t b, uint64_t c)
