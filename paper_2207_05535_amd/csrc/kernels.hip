@@ -1336,14 +1336,22 @@ __device__ __forceinline__ void sweep_dispatch(const SweepItem &it, const RunInf
     }
 }
 
+// LS < 0: any lattice size and model, chosen per item; otherwise every item
+// of the launch has L = LS and the model EA (a kernel of its own allocates
+// only the registers that one size needs).
+template <int LS, bool EA>
 __device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *runs, const PopState *st,
                                           uint64_t *lds, int dense, unsigned long long *stats)
 {
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S) || R.theta == 0) return;
-    if (R.model == PA_EA_PMJ) sweep_dispatch<true>(it, R, S, lds, dense, stats);
-    else sweep_dispatch<false>(it, R, S, lds, dense, stats);
+    if constexpr (LS >= 0) {
+        sweep_item<LS, EA>(it, R, S, lds, dense, stats);
+    } else {
+        if (R.model == PA_EA_PMJ) sweep_dispatch<true>(it, R, S, lds, dense, stats);
+        else sweep_dispatch<false>(it, R, S, lds, dense, stats);
+    }
 }
 
 // One workgroup per item, or (queue != nullptr) a persistent grid whose
@@ -1352,13 +1360,14 @@ __device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *ru
 // the next ticket, queue[1] counts workgroups that found the list empty; the
 // last of them resets both, so the next launch (or graph replay) starts
 // from zero without a separate clear.
+template <int LS, bool EA>
 __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int n_items, const RunInfo *runs,
                                                     const PopState *st, int dense, unsigned long long *stats,
                                                     unsigned int *queue)
 {
     extern __shared__ uint64_t lds[];
     if (queue == nullptr) {
-        sweep_one(items[blockIdx.x], runs, st, lds, dense, stats);
+        sweep_one<LS, EA>(items[blockIdx.x], runs, st, lds, dense, stats);
         return;
     }
     __shared__ unsigned int ticket;
@@ -1368,7 +1377,7 @@ __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int 
         __syncthreads();
         const unsigned int t = ticket;
         if (t >= (unsigned int)n_items) break;
-        sweep_one(items[t], runs, st, lds, dense, stats);
+        sweep_one<LS, EA>(items[t], runs, st, lds, dense, stats);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -2651,10 +2660,43 @@ size_t msc_lds_bytes(int N, int groups)
     return (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
 }
 
+// The sweep kernel for a launch: one compiled for a single (L, model) when
+// every run of the context has it, else the one that dispatches per item.
+using SweepKernel = void (*)(const SweepItem *, int, const RunInfo *, const PopState *, int, unsigned long long *,
+                             unsigned int *);
+
+SweepKernel msc_kernel(int L, int ea)
+{
+    switch (2 * L + (ea ? 1 : 0)) {
+    case 16: return k_sweep_msc<8, false>;
+    case 17: return k_sweep_msc<8, true>;
+    case 32: return k_sweep_msc<16, false>;
+    case 33: return k_sweep_msc<16, true>;
+    case 48: return k_sweep_msc<24, false>;
+    case 49: return k_sweep_msc<24, true>;
+    case 64: return k_sweep_msc<32, false>;
+    case 65: return k_sweep_msc<32, true>;
+    case 96: return k_sweep_msc<48, false>;
+    case 97: return k_sweep_msc<48, true>;
+    case 128: return k_sweep_msc<64, false>;
+    case 129: return k_sweep_msc<64, true>;
+    default: return k_sweep_msc<-1, false>;
+    }
+}
+
+bool msc_specialised(int L) { return L == 8 || L == 16 || L == 24 || L == 32 || L == 48 || L == 64; }
+
 hipError_t prepare_msc_lds(size_t bytes)
 {
     if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute((const void *)k_sweep_msc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    static const int Ls[] = {8, 16, 24, 32, 48, 64, 0};
+    for (int L : Ls)
+        for (int ea = 0; ea < 2; ++ea) {
+            const hipError_t e = hipFuncSetAttribute((const void *)msc_kernel(L, ea),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
 }
 
 hipError_t launch_sweep_msc(const LaunchCtx &c)
@@ -2662,16 +2704,17 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
     if (c.n_sweep_items == 0) return hipSuccess;
     const bool persistent = c.sweep_grid > 0 && c.sweep_grid < c.n_sweep_items;
     const int grid = persistent ? c.sweep_grid : c.n_sweep_items;
-    k_sweep_msc<<<grid, c.sweep_threads, c.sweep_lds, c.stream>>>(c.sweep_items, c.n_sweep_items, c.runs, c.st,
-                                                                 c.sweep_dense | (c.sweep_pooled << 8), c.stats,
-                                                                 persistent ? c.sweep_queue : nullptr);
+    msc_kernel(c.sweep_L, c.sweep_ea)<<<grid, c.sweep_threads, c.sweep_lds, c.stream>>>(
+        c.sweep_items, c.n_sweep_items, c.runs, c.st, c.sweep_dense | (c.sweep_pooled << 8), c.stats,
+        persistent ? c.sweep_queue : nullptr);
     return hipGetLastError();
 }
 
-int sweep_msc_resident(int threads, size_t lds)
+int sweep_msc_resident(int threads, size_t lds, int L, int ea)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_msc, threads, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, msc_kernel(L, ea), threads, lds) != hipSuccess)
+        return 0;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)

@@ -29,6 +29,7 @@ struct LaunchCtx {
     int n_sweep_items, sweep_threads, sweep_dense;
     int sweep_grid;                // > 0: persistent grid of this many workgroups
     int sweep_pooled;              // 1: sparse rounds over one list per workgroup
+    int sweep_L = 0, sweep_ea = 0;  // every run of the context has this L and model (0: mixed)
     unsigned int *sweep_queue;     // device [2] ticket counters of the persistent grid
     size_t sweep_lds;
     hipStream_t stream;
@@ -52,7 +53,8 @@ hipError_t launch_famstats(const LaunchCtx &c, const pa_obs *obs, int pop, int K
 int int8_tile_rows(int L);
 size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);
-int sweep_msc_resident(int threads, size_t lds);   // workgroups resident on the whole device, 0 on error
+int sweep_msc_resident(int threads, size_t lds, int L, int ea);   // workgroups resident on the device, 0 on error
+bool msc_specialised(int L);   // a sweep kernel compiled for this L alone exists
 hipError_t prepare_wang_lds(size_t bytes);
 hipError_t launch_philox_rate(int calls, hipStream_t s, int *blocks, int *threads);
 

@@ -442,7 +442,7 @@ pa_status upload_sweep_plan(pa_ctx *c)
     c->lc.sweep_grid = 0;
     c->lc.sweep_pooled = c->sweep_pooled ? 1 : 0;
     if (c->sweep_persistent) {
-        const int resident = sweep_msc_resident(c->sweep_threads, lds);
+        const int resident = sweep_msc_resident(c->sweep_threads, lds, c->lc.sweep_L, c->lc.sweep_ea);
         if (resident <= 0) return dev_fail(c);
         c->lc.sweep_grid = resident;
     }
@@ -593,10 +593,21 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.any_multinomial = c->any_multinomial;
     c->lc.mn_split = 1;
     c->lc.any_overlap = false;
+    int sweep_L = 0, sweep_model = -1;   // the one (L, model) of the runs that sweep, if they share it
+    bool mixed = false;
     for (int r = 0; r < n_runs; ++r) {
         if (runs[r].resampling == PA_MULTINOMIAL && runs[r].R > CH) c->lc.mn_split = CH_PER;
         if (runs[r].overlap != PA_Q_NONE) c->lc.any_overlap = true;
+        if (runs[r].theta <= 0) continue;
+        if (sweep_model < 0) {
+            sweep_L = runs[r].L;
+            sweep_model = runs[r].model;
+        } else if (runs[r].L != sweep_L || runs[r].model != sweep_model) {
+            mixed = true;
+        }
     }
+    c->lc.sweep_L = !mixed && sweep_model >= 0 && msc_specialised(sweep_L) ? sweep_L : 0;
+    c->lc.sweep_ea = c->lc.sweep_L && sweep_model == PA_EA_PMJ ? 1 : 0;
     c->lc.any_wang = c->any_wang;
     c->lc.any_exact_dos = c->any_exact_dos;
     c->lc.stats = at<unsigned long long>(c, Lo.stats);

@@ -329,7 +329,7 @@ pa_status rebuild(pa_server *s)
     if (s->repr == PA_MSC64 && !sweep.empty()) {
         if (prepare_msc_lds(lds) != hipSuccess) return sfail(s);
         if (s->persistent) {
-            const int resident = sweep_msc_resident(s->threads, lds);
+            const int resident = sweep_msc_resident(s->threads, lds, s->lc.sweep_L, s->lc.sweep_ea);
             if (resident <= 0) return sfail(s);
             c.sweep_grid = resident;
         }
