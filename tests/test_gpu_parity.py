@@ -501,3 +501,26 @@ def test_multichunk_and_small_runs_in_one_context(repr_):
         assert_obs_equal(obs[r, :orc.npop], orc.obs(), f"run {r}")
         assert_state_equal(ctx, orc, r, f"run {r} final")
     ctx.close()
+
+
+@pytest.mark.parametrize("L,model", [(8, W.FM), (16, W.EA_PMJ), (32, W.FM)])
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_single_size_kernel(L, model, persistent):
+    """A context whose runs share one lattice size and model launches the
+    sweep kernel compiled for that size: one workgroup per item or the
+    persistent grid, with two runs of different seeds and population sizes;
+    every record and the final states equal the oracle's."""
+    say(f"single-size sweep kernel L={L} model={model} persistent={persistent}")
+    runs = [W.run_desc(L, model, seed=W.RUN_SEED_BASE + 0x7200 + L, disorder_seed=7, R=300, theta=2, K=10,
+                       beta_f=1.0),
+            W.run_desc(L, model, seed=W.RUN_SEED_BASE + 0x7300 + L, disorder_seed=7, R=130, theta=3, K=10,
+                       beta_f=1.0, resampling=W.NEAREST_INT)]
+    ctx = pa.Context(runs, "msc")
+    ctx.set_persistent(persistent)
+    ctx.run(1, 10)
+    obs = ctx.obs()
+    for r, d in enumerate(runs):
+        orc = oracle.OracleRun(d).run_all()
+        assert_obs_equal(obs[r, :orc.npop], orc.obs(), f"run {r}")
+        assert_state_equal(ctx, orc, r, f"run {r} final")
+    ctx.close()
