@@ -27,7 +27,9 @@ Further workloads in the same JSON line (skipped with --quick):
   batched_4096 4096 independent FM runs, L in {8, 16, 24, 32} (1024 each),
                R = 2000, beta 0 -> 0.6 in 150 points, theta = 10, all in
                one context (one sweep launch per step), weighted averages
-               over the 1024 runs of each L in FP64 inside the timed region;
+               over the 1024 runs of each L in FP64 inside the timed region
+               (with cpu_baseline_many_runs: independent single-threaded
+               oracle processes, one per host core, on runs of this batch);
   serving      500 EA +-J requests arriving at Poisson rate 20/s, L uniform
                in {16, 24, 32, 48, 64}, R = 50000, beta 0 -> 3 in 201
                points, theta = 10, served by continuous batching with
@@ -486,6 +488,51 @@ def cpu_baseline(desc, max_seconds=20.0):
                        f"200-point schedule, whole steps (ii)-(v); {flips} flips in {dt:.1f} s")
 
 
+def _oracle_steps(job):
+    """One oracle run of a workload, whole temperature steps from i = 1 for
+    about max_seconds: (attempted flips, seconds, steps done)."""
+    desc, max_seconds = job
+    import oracle
+    run = oracle.OracleRun(desc)
+    t0 = time.perf_counter()
+    flips = 0
+    i = 0
+    while time.perf_counter() - t0 < max_seconds and i + 1 < desc["K"]:
+        i += 1
+        run.step(i)
+        flips += int(run.obs()[0, i]["R_i"]) * desc["theta"] * desc["L"] ** 2
+    return flips, time.perf_counter() - t0, i
+
+
+def cpu_baseline_many_runs(max_seconds=10.0):
+    """The oracle for the many-runs workload: P independent single-threaded
+    oracle processes on the host cores (P = the cores available, at most
+    16), each one run of the 4096-run batch (the four lattice sizes in turn)
+    for about max_seconds of whole temperature steps; flips of all processes
+    over the longest process time.  Processes are started fresh (spawn), so
+    none touches the GPU."""
+    import multiprocessing as mp
+    import workloads as W
+    runs = W.batched_fm_uneven()
+    P = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1))
+    by_L = {}
+    for d in runs:
+        by_L.setdefault(d["L"], d)
+    Ls = sorted(by_L)
+    jobs = [(by_L[Ls[p % len(Ls)]], max_seconds) for p in range(P)]
+    with mp.get_context("spawn").Pool(P) as pool:
+        res = pool.map(_oracle_steps, jobs)
+    flips = sum(r[0] for r in res)
+    secs = max(r[1] for r in res)
+    steps = [r[2] for r in res]
+    return dict(value=flips / secs / 1e9, unit="spin flips/ns", cores=P, host_cores=os.cpu_count(),
+                kind="oracle", processes=P,
+                sample=f"{P} independent oracle processes, each one run of the 4096-run workload (L cycling "
+                       f"over {Ls}, R=2000, theta=10, beta 0->0.6 in 150 points), whole steps (ii)-(v) from "
+                       f"i=1 for about {max_seconds:g} s (steps done {min(steps)}..{max(steps)}); "
+                       f"{flips} flips in {secs:.1f} s")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,6 +627,9 @@ def main():
     if not args.no_cpu_baseline and "headline" in only:
         log("cpu baseline: oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(desc)
+    if not args.no_cpu_baseline and "batched" in only:
+        log("cpu baseline for the many-runs workload: oracle processes on the host cores")
+        line["cpu_baseline_many_runs"] = cpu_baseline_many_runs()
     print(json.dumps(line), flush=True)
 
 
