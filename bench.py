@@ -228,6 +228,7 @@ def run_plain(desc, steps, warmup, obs_ref):
     sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     torch.cuda.synchronize()
+    st0 = pctx.stats()
     t0 = time.perf_counter()
     e0.record()
     for k, i in enumerate(range(1, K1)):
@@ -241,6 +242,7 @@ def run_plain(desc, steps, warmup, obs_ref):
     e1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    st1 = pctx.stats()
     for a, b in sev:
         sw.append(a.elapsed_time(b))
     obs_plain = pctx.obs()[0, 0].copy()
@@ -249,7 +251,8 @@ def run_plain(desc, steps, warmup, obs_ref):
     same_fp = bool(np.allclose(obs_plain["A"][:K1], obs_ref["A"][:K1], rtol=1e-12, atol=0))
     pctx.close()
     return dict(wall_s=t1 - t0, dev_s=e0.elapsed_time(e1) / 1e3, sweep_ms=sw,
-                bit_exact=bool(same and same_fp), free_energy=float(pw[0]["minus_beta_WF"][steps]))
+                bit_exact=bool(same and same_fp), free_energy=float(pw[0]["minus_beta_WF"][steps]),
+                calls=st1["calls"] - st0["calls"], words=st1["words"] - st0["words"])
 
 
 def workload_summary(b, steps, name):
@@ -691,6 +694,10 @@ def headline(desc, steps, warmup, args, only):
             "sweep_launch_avg_ms": round(plain_sweep_avg * 1e3, 4),
             "sweep_hbm_GBps": round(bytes_launch / plain_sweep_avg / 1e9, 1),
             "sweep_hbm_frac": round(bytes_launch / plain_sweep_avg / 1e9 / HBM_PEAK_GBS, 4),
+            # the same Philox and site-update work as the batched sweep, per
+            # colour launch, against the integer-VALU peak
+            "sweep_alu_frac": round((OPS_PER_CALL * p["calls"] + OPS_PER_WORD * p["words"])
+                                    / (steps * 2 * desc["theta"]) / plain_sweep_avg / PEAK_LANE_OPS, 4),
             "bit_exact_vs_batched": p["bit_exact"],
         }
         line["batched_over_plain"] = round(p["wall_s"] / b["wall_s"], 3)
