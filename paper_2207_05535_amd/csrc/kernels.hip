@@ -883,19 +883,18 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
     const uint8_t *jbits = R.jbits;
     const int chunks = nrow * L * 4;
     uint4 reg[I8_CMAX];
-    size_t off[I8_CMAX];
-#pragma unroll
-    for (int q = 0; q < I8_CMAX; ++q) {
-        const int c = tid + q * nthr;
+    // byte offset of chunk c inside the group's N * 64 bytes (recomputed at
+    // the store rather than held in registers)
+    auto off_of = [&](int c) {
         const int site = c >> 2, part = c & 3;
         const int rr = site / L, x = site - rr * L;
         int y = y0 - halo + rr;
         y = y < 0 ? y + L : (y >= L ? y - L : y);
-        off[q] = (size_t)(y * L + x) * 64 + part * 16;
-    }
+        return (uint32_t)(y * L + x) * 64u + (uint32_t)part * 16u;
+    };
 #pragma unroll
     for (int q = 0; q < I8_CMAX; ++q)
-        if (tid + q * nthr < chunks) reg[q] = *(const uint4 *)(base + off[q]);
+        if (tid + q * nthr < chunks) reg[q] = *(const uint4 *)(base + off_of(tid + q * nthr));
 #pragma unroll
     for (int q = 0; q < I8_CMAX; ++q) {
         const int c = tid + q * nthr;
@@ -940,7 +939,7 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
                     v.y ^= negmask4((f >> 4) & 15u);
                     v.z ^= negmask4((f >> 8) & 15u);
                     v.w ^= negmask4((f >> 12) & 15u);
-                    *(uint4 *)(base + off[q]) = v;
+                    *(uint4 *)(base + off_of(c)) = v;
                 }
             }
         }
@@ -948,9 +947,13 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
     flush_stats(stats, nwords, ncalls, nwords * lanes);
 }
 
-__global__ void __launch_bounds__(1024) k_sweep_int8(const RunInfo *runs, const PopState *st, int run, int pop,
-                                                     int s, int colour, int T, int ntiles,
-                                                     unsigned long long *stats)
+// THREADS: the workgroup size it is launched with (256, or 1024 for very
+// large lattices); the bound lets the 256-thread form keep its chunks and
+// the Philox state in registers instead of spilling them to scratch.
+template <int THREADS>
+__global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, const PopState *st, int run, int pop,
+                                                        int s, int colour, int T, int ntiles,
+                                                        unsigned long long *stats)
 {
     extern __shared__ uint64_t sm[];
     const RunInfo &R = runs[run];
@@ -2647,8 +2650,12 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
     for (int s = 0; s < theta; ++s)
         for (int colour = 0; colour < 2; ++colour)
             for (int p = 0; p < npop; ++p) {
-                k_sweep_int8<<<groups_cap * ntiles, threads, lds, c.stream>>>(c.runs, c.st, run, p, s, colour, T,
-                                                                              ntiles, c.stats);
+                if (threads == 256)
+                    k_sweep_int8<256><<<groups_cap * ntiles, threads, lds, c.stream>>>(c.runs, c.st, run, p, s,
+                                                                                       colour, T, ntiles, c.stats);
+                else
+                    k_sweep_int8<1024><<<groups_cap * ntiles, threads, lds, c.stream>>>(c.runs, c.st, run, p, s,
+                                                                                        colour, T, ntiles, c.stats);
                 PA_CHECK_LAUNCH();
             }
     return hipSuccess;
