@@ -74,10 +74,16 @@ def ensure_built():
 
 
 def kernel_source_hash():
+    """Hash of the device sources the HBM counters were taken on, with
+    comments and layout removed (an edit of a comment keeps the counters)."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "metropolis.hpp", "philox.hpp", "pa_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2207_05535_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2207_05535_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

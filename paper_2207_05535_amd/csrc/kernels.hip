@@ -1,14 +1,19 @@
 // kernels.hip -- HIP kernels of the population-annealing temperature step
 // for gfx950 (CDNA4, 64-wide wavefronts).
 //
-// Step (i)   k_init_couplings, k_init_spins           (Sec. II B, III A)
+// Step (i)   k_init_couplings, k_init_spins, k_init_fam (Sec. II B, III A)
 // Step (ii)  k_rw_chunk, k_rw_finish                   (Eqs. (QBoltz), (F))
 // Step (iii) k_cnt_chunk, k_mn_draws, k_cnt_scan_chunk, k_cnt_finish,
 //            k_parent, k_copy                          (Sec. II B, IV D, V A 1)
 // Step (iv)  k_sweep_int8 (one colour of one run per launch),
-//            k_sweep_msc (all runs, lattice in LDS for all theta sweeps)
-// Step (v)   k_measure, k_finalize                     (Eqs. (e)-(chi), Sec. III D)
-// Sec. IV    k_logw, k_wavg, k_wavg_cumsum
+//            k_sweep_msc (all runs, lattice in LDS for all theta sweeps;
+//            also compiled per lattice size and model), k_dos_sample (the
+//            theta = infinity limit, Sec. V B)
+// Step (v)   k_wang_pairs, k_wang_rows, k_wang_gather (permutation pairing,
+//            Sec. III D), k_measure, k_meas_chunk, k_finalize
+//                                                      (Eqs. (e)-(chi), Sec. III D)
+// Sec. IV    k_logw, k_qweights, k_wavg, k_wavg_cumsum, k_wqhist, k_famstats
+// Diagnostic k_philox_rate (integer-VALU calibration)
 //
 // Population-wide reductions and scans are split into fixed-size chunks of
 // CH replicas (one workgroup each) plus a single-workgroup pass over the
