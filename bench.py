@@ -571,7 +571,7 @@ def main():
     SEARCH_OUT[0] = os.path.abspath(args.tune_out)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs one population-annealing "
+        print("bench.py measures one GPU only: the library runs one population-annealing "
               "workload per GPU and uses no collectives; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
