@@ -857,8 +857,8 @@ __device__ __forceinline__ uint64_t jmask(uint8_t b, int bit) { return ((b >> bi
 // All of its 16-byte chunks are loaded first (consecutive lanes take
 // consecutive chunks, so the loads coalesce and are all in flight at once),
 // their sign bits are packed into an LDS bit-lattice (one 64-bit word per
-// site), the colour's sites are updated from the packed words, and each
-// lane XORs the flips of its chunks back and stores the chunks that change.
+// site), the colour's sites are updated from the packed words, and the
+// chunks that change are rebuilt from their signs and stored.
 constexpr int I8_CMAX = 12;   // 16-byte chunks held per thread
 
 __device__ __forceinline__ uint32_t signs16(const uint4 &v)
@@ -888,8 +888,7 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
     const uint8_t *jbits = R.jbits;
     const int chunks = nrow * L * 4;
     uint4 reg[I8_CMAX];
-    // byte offset of chunk c inside the group's N * 64 bytes (recomputed at
-    // the store rather than held in registers)
+    // byte offset of chunk c inside the group's N * 64 bytes
     auto off_of = [&](int c) {
         const int site = c >> 2, part = c & 3;
         const int rr = site / L, x = site - rr * L;
@@ -928,25 +927,24 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
         ++nwords;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < I8_CMAX; ++q) {
-        const int c = tid + q * nthr;
-        if (c < chunks) {
-            const int site = c >> 2, part = c & 3;
-            const int rr = site / L, x = site - rr * L;
-            const int yy = rr - halo;
+    // Store: one 16-byte chunk of a colour site per lane step (idx as in the
+    // update loop).  Spins are the canonical bytes +1 = 0x01, -1 = 0xFF, so a
+    // chunk is rebuilt from its packed sign bits and flips; the registers that
+    // held the loads are free during the update.
+    for (int k = tid; k < rows * half * 4; k += nthr) {
+        const int idx = k >> 2, part = k & 3;
+        const uint32_t f = (uint32_t)(fm[idx] >> (16 * part)) & 0xFFFFu;
+        if (f) {
+            const int yy = idx / half, m = idx - yy * half;
             const int y = y0 + yy;
-            if (yy >= 0 && yy < rows && ((x + y) & 1) == colour) {
-                const uint32_t f = (uint32_t)(fm[yy * half + (x >> 1)] >> (16 * part)) & 0xFFFFu;
-                if (f) {
-                    uint4 v = reg[q];
-                    v.x ^= negmask4(f & 15u);
-                    v.y ^= negmask4((f >> 4) & 15u);
-                    v.z ^= negmask4((f >> 8) & 15u);
-                    v.w ^= negmask4((f >> 12) & 15u);
-                    *(uint4 *)(base + off_of(c)) = v;
-                }
-            }
+            const int x = 2 * m + ((y + colour) & 1);
+            const uint32_t b = f ^ (uint32_t)pk16[((yy + halo) * L + x) * 4 + part];
+            uint4 v;
+            v.x = 0x01010101u ^ negmask4(b & 15u);
+            v.y = 0x01010101u ^ negmask4((b >> 4) & 15u);
+            v.z = 0x01010101u ^ negmask4((b >> 8) & 15u);
+            v.w = 0x01010101u ^ negmask4((b >> 12) & 15u);
+            *(uint4 *)(base + (uint32_t)(y * L + x) * 64u + (uint32_t)part * 16u) = v;
         }
     }
     flush_stats(stats, nwords, ncalls, nwords * lanes);
@@ -2626,9 +2624,6 @@ hipError_t launch_resample(const LaunchCtx &c)
 }
 
 
-// Rows per workgroup of the int8 sweep: the whole lattice when its chunks
-// fit in the registers of 1024 threads, else bands with a halo row on each
-// side.
 // Threads per workgroup of the plain sweep: 256, or 1024 when three rows of
 // a very large lattice would not fit in 256 threads' chunks.
 int int8_threads(int L) { return 3 * L * 4 <= 256 * I8_CMAX ? 256 : 1024; }
