@@ -358,7 +358,7 @@ def run_q_estimators(M=16, K=61):
 
 
 def run_theta_infinity(M=1024, R=1000, L=10, beta_f=0.44, K=45):
-    """The theta = infinity limit of Sec. V B beside finite theta: M runs of
+    """The theta = infinity limit of Sec. V C beside finite theta: M runs of
     the L = 10 ferromagnet per theta in one context (R = 1000, beta 0 ->
     0.44 in K points); the mean, variance and skewness of -beta F-hat over
     the runs at the last temperature, and its bias against the exact value

@@ -91,13 +91,13 @@ typedef struct {
     int32_t theta;          /* Metropolis sweeps per temperature, 0 <= theta < 2^24, or
                                PA_THETA_EXACT (see below) */
     int32_t K;              /* number of temperatures, K >= 2 */
-    const double *beta;     /* host [K]: schedule, beta[0] == 0, finite; copied */
+    const double *beta;     /* host [K]: schedule, beta[0] == 0, finite, non-decreasing; copied */
     int32_t resampling;     /* PA_MULTINOMIAL or PA_NEAREST_INT */
     int32_t overlap;        /* PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP, PA_Q_WANG or PA_Q_WANG_RDM */
     int32_t qhist;          /* 1: keep an overlap histogram per temperature */
 } pa_run_desc;
 
-/* theta = PA_THETA_EXACT is the theta = infinity limit of Sec. V B: step
+/* theta = PA_THETA_EXACT is the theta = infinity limit of Sec. V C: step
  * (iv) replaces every replica's energy by an independent draw from the
  * exact energy distribution g(E) exp(-beta_i E) / Z of the periodic
  * ferromagnet (model PA_FM, L <= 10, overlap PA_Q_NONE).  g comes from
@@ -257,7 +257,10 @@ pa_status pa_checkpoint(pa_ctx *ctx, void *host_buf, size_t *bytes);
 
 /* Restore a checkpoint taken from a context created with the same
  * descriptors and representation.  Continuing from it reproduces the
- * uninterrupted run bit for bit. */
+ * uninterrupted run bit for bit.  The checkpoint carries a hash of every run
+ * descriptor and schedule: a checkpoint of other runs (another seed, theta,
+ * model, schedule, ...) is rejected with PA_ERR_ARG and the context is left
+ * unchanged. */
 pa_status pa_restore(pa_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Launch-shape knobs of the batched sweep, chosen by the autotuner per

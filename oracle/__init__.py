@@ -86,6 +86,7 @@ def lib():
         L.or_get_pairing.argtypes = [vp, C.c_int, vp]
         L.or_get_pairing.restype = C.c_int
         L.or_weighted_average.argtypes = [vp, vp, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int, vp]
+        L.or_log_weights.argtypes = [vp, C.c_int, C.c_int, vp, C.c_int, vp]
         L.or_weighted_qhist.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp]
         L.or_family_stats.argtypes = [vp, vp, vp, C.c_int, vp]
         L.or_get_rho.argtypes = [vp, vp]
@@ -294,6 +295,20 @@ def weighted_average(obs_mk, beta, N, R, kind=0, obs_other=None):
                                    _ptr(out))
     if st:
         raise ValueError(f"or_weighted_average failed: {st}")
+    return out
+
+
+def log_weights(obs_mk, R, kind=0):
+    """The oracle's log free-energy weights a[m, i] of M runs (full weight,
+    kind 0, Eq. (appropriateWeight); simplified, kind 1, Eq. (simpleWeight));
+    NaN where a record's status is not OK."""
+    obs_mk = np.ascontiguousarray(obs_mk, dtype=OBS_DTYPE)
+    M, K = obs_mk.shape
+    R = np.ascontiguousarray(np.broadcast_to(np.asarray(R, np.int32), (M,)), dtype=np.int32)
+    out = np.zeros((M, K), np.float64)
+    st = lib().or_log_weights(_ptr(obs_mk), M, K, _ptr(R), int(kind), _ptr(out))
+    if st:
+        raise ValueError(f"or_log_weights failed: {st}")
     return out
 
 

@@ -238,7 +238,7 @@ void or_destroy(or_run *run)
 /* ------------------------------------------ theta = infinity limit -- */
 
 /* Exact density of states of the periodic L x L ferromagnet, the input of
- * the theta = infinity limit (Sec. V B: simple sampling of the exact energy
+ * the theta = infinity limit (Sec. V C: simple sampling of the exact energy
  * distribution): g[m] = number of configurations with E = -2N + 4m,
  * m = 0..N.  Written as Z = Tr T^L over rows, with integer weights in the
  * number u of unsatisfied bonds (E = -2N + 2u): a row s carries its
@@ -1058,6 +1058,22 @@ static double log_weight(const or_obs *om /* [K] of run m */, int i, int kind, i
     if (kind == 0)
         for (int k = 1; k <= i; k++) a += log((double)om[k - 1].R_i / (double)R);
     return a;
+}
+
+/* The log-weights a[m][i] that the weighted averages use (log_weight above),
+ * NaN for records whose status is not OK; kind as in or_weighted_average
+ * (bit 0: simplified).  Exported so that the tests can check the weights
+ * themselves: for the full weight, exp(a - ln R - N ln 2) is an unbiased
+ * estimate of Z(beta_i)/2^N (the population-size argument of Sec. IV A). */
+int or_log_weights(const or_obs *obs, int M, int K, const int32_t *R, int kind, double *out /* [M][K] */)
+{
+    if (M < 1 || K < 1 || !obs || !R || !out || kind < 0 || kind > 3) return OR_ERR_ARG;
+    for (int m = 0; m < M; m++)
+        for (int i = 0; i < K; i++) {
+            const or_obs *om = &obs[(size_t)m * K];
+            out[(size_t)m * K + i] = om[i].status == OR_OK ? log_weight(om, i, kind & 1, R[m]) : NAN;
+        }
+    return OR_OK;
 }
 
 /* Weighted averages over M runs (Sec. IV), for each temperature i.

@@ -8,7 +8,7 @@
 // Step (iv)  k_sweep_int8 (one colour of one run per launch),
 //            k_sweep_msc (all runs, lattice in LDS for all theta sweeps;
 //            also compiled per lattice size and model), k_dos_sample (the
-//            theta = infinity limit, Sec. V B)
+//            theta = infinity limit, Sec. V C)
 // Step (v)   k_wang_pairs, k_wang_rows, k_wang_gather (permutation pairing,
 //            Sec. III D), k_measure, k_meas_chunk, k_finalize
 //                                                      (Eqs. (e)-(chi), Sec. III D)
@@ -1672,7 +1672,7 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
 
 // ----------------------------------------------- theta = infinity draws
 //
-// Step (iv) in the theta = infinity limit (Sec. V B): every replica's energy
+// Step (iv) in the theta = infinity limit (Sec. V C): every replica's energy
 // is an independent draw from the exact distribution at beta_i.  One thread
 // per replica (a wavefront per replica group): a 64-bit Philox draw and a
 // binary search over the level thresholds C[i][0..N] (non-decreasing) for

@@ -22,14 +22,39 @@ using namespace pa;
 namespace {
 
 constexpr uint64_t CKPT_MAGIC = 0x50414d4933353558ull;  // "PAMI355X"
-constexpr uint32_t CKPT_VERSION = 1;
+constexpr uint32_t CKPT_VERSION = 2;
 
 struct CkptHeader {
     uint64_t magic;
     uint32_t version, repr;
     uint64_t ws_used;
     int32_t n_runs, i, phase, npop_ctx;
+    uint64_t desc_hash;     // of every run descriptor and schedule of the context
 };
+
+// FNV-1a over the fields of every run descriptor and its schedule: a
+// checkpoint restores only into a context built from the same runs.
+uint64_t descs_hash(const pa_ctx *c)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const uint8_t *b = (const uint8_t *)p;
+        for (size_t k = 0; k < n; ++k) {
+            h ^= b[k];
+            h *= 0x100000001b3ull;
+        }
+    };
+    for (int r = 0; r < c->n_runs; ++r) {
+        const pa_run_desc &d = c->descs[r];
+        const int32_t ints[] = {d.L, (int32_t)d.model, d.R, d.R_cap, d.theta, d.K, (int32_t)d.resampling,
+                                (int32_t)d.overlap, d.qhist};
+        mix(ints, sizeof(ints));
+        mix(&d.seed, sizeof(d.seed));
+        mix(&d.disorder_seed, sizeof(d.disorder_seed));
+        mix(c->betas[r].data(), sizeof(double) * c->betas[r].size());
+    }
+    return h;
+}
 
 bool same_table(const TableOff &t, int N, const pa_run_desc &d)
 {
@@ -59,6 +84,11 @@ bool desc_ok(const pa_run_desc &d, pa_repr repr)
     if (d.beta[0] != 0.0) return false;
     for (int i = 0; i < d.K; ++i)
         if (!std::isfinite(d.beta[i])) return false;
+    // annealing cools: a step with beta_i < beta_{i-1} would make the
+    // reweighting factors exp(-dbeta 4k) exceed one and overflow the 40-bit
+    // fixed-point table and the integer sums built from it
+    for (int i = 1; i < d.K; ++i)
+        if (d.beta[i] < d.beta[i - 1]) return false;
     const double N = (double)d.L * d.L;
     if (4.0 * N * N * (double)d.R_cap >= 4.0e18) return false;  // int64 sums of E^2, Q_l^2
     return true;
@@ -996,7 +1026,7 @@ pa_status pa_checkpoint(pa_ctx *c, void *host_buf, size_t *bytes)
     }
     if (*bytes < need) return PA_ERR_ARG;
     CkptHeader h = {CKPT_MAGIC, CKPT_VERSION, (uint32_t)c->repr, c->lo.total, c->n_runs, c->i, c->phase,
-                    c->lo.npop_ctx};
+                    c->lo.npop_ctx, descs_hash(c)};
     std::memcpy(host_buf, &h, sizeof(h));
     PA_HIP(c, hipMemcpyAsync((uint8_t *)host_buf + sizeof(h), c->ws, c->lo.total, hipMemcpyDeviceToHost, c->stream));
     PA_HIP(c, hipStreamSynchronize(c->stream));
@@ -1011,7 +1041,8 @@ pa_status pa_restore(pa_ctx *c, const void *host_buf, size_t bytes)
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof(h));
     if (h.magic != CKPT_MAGIC || h.version != CKPT_VERSION || h.repr != (uint32_t)c->repr ||
-        h.ws_used != c->lo.total || h.n_runs != c->n_runs || bytes < sizeof(h) + h.ws_used)
+        h.ws_used != c->lo.total || h.n_runs != c->n_runs || h.desc_hash != descs_hash(c) ||
+        bytes < sizeof(h) + h.ws_used)
         return PA_ERR_ARG;
     PA_HIP(c, hipMemcpyAsync(c->ws, (const uint8_t *)host_buf + sizeof(h), c->lo.total, hipMemcpyHostToDevice,
                              c->stream));

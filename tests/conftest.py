@@ -1,6 +1,12 @@
 import os
 import sys
 
+# The oracle is single-threaded; keep numpy's BLAS to one thread too, so that
+# parallel test workers do not oversubscribe the host (the transfer-matrix
+# references run many small eigenvalue problems).
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -12,5 +18,10 @@ if HERE not in sys.path:
 
 
 def pytest_configure(config):
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except ImportError:
+        pass
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C ABI on the GPU)")
     config.addinivalue_line("markers", "slow: long CPU statistical test")

@@ -65,6 +65,7 @@ def test_workspace_size_valid_and_monotone():
     dict(beta=[0.1, 0.2, 0.3]),            # beta_0 must be 0
     dict(beta=[0.0]),                      # K >= 2
     dict(beta=[0.0, float("nan")]),
+    dict(beta=[0.0, 0.3, 0.2, 0.4]),       # a schedule that heats is rejected
     dict(R=1 << 23, R_cap=1 << 23),
 ])
 def test_workspace_size_rejects(bad):

@@ -1,4 +1,4 @@
-"""GPU parity of the theta = infinity limit (Sec. V B) and the library's exact
+"""GPU parity of the theta = infinity limit (Sec. V C) and the library's exact
 density of states.
 
 * pa_exact_dos equals the oracle's density of states (computed by its own

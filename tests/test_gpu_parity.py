@@ -237,6 +237,13 @@ def test_checkpoint_restore_bit_exact(repr_):
     for i in range(9, 21):
         ctx2.step(i)
     assert ctx2.obs().tobytes() == first.tobytes()
+    # a context of other runs with the same workspace size refuses it
+    for other in (W.with_(d, seed=9), W.with_(d, theta=4), W.with_(d, beta_f=0.9)):
+        ctx3 = pa.Context([other], repr_)
+        with pytest.raises(pa.PAError) as e:
+            ctx3.restore(ck)
+        assert e.value.status == pa.PA_ERR_ARG
+        ctx3.close()
     ctx.close()
     ctx2.close()
 

@@ -1,4 +1,4 @@
-"""Oracle pins for the theta = infinity limit (Sec. V B), CPU only.
+"""Oracle pins for the theta = infinity limit (Sec. V C), CPU only.
 
 * The exact density of states of the periodic ferromagnet equals brute-force
   enumeration at L = 4, and at L = 6 and 8 reproduces Kaufman's closed-form

@@ -86,23 +86,29 @@ def test_weighted_variance_is_variance_of_weighted_moments():
     assert np.allclose(out["Wvar_c"], direct, rtol=1e-9, atol=1e-12)
 
 
-@pytest.mark.parametrize("model", [W.FM, W.EA_PMJ])
-def test_weighted_average_bias_vanishes_with_M(model):
+@pytest.mark.parametrize("model,resampling", [(W.FM, W.MULTINOMIAL), (W.EA_PMJ, W.MULTINOMIAL),
+                                               (W.FM, W.NEAREST_INT)])
+def test_weighted_average_bias_vanishes_with_M(model, resampling):
     """Sec. IV D: without equilibration (theta = 0, condition (d)) and with
     constant population size (multinomial, condition (c)), configurational
     weighted averages converge to the exact ensemble average as M grows,
     while the plain average over runs keeps the finite-R bias.  Pool of
-    runs partitioned into S groups of M (Sec. V A 2)."""
+    runs partitioned into S groups of M (Sec. V A 2).  With nearest-integer
+    resampling the population size fluctuates and the full weight of
+    Eq. (appropriateWeight) carries the R_{k-1}/R factors that keep the
+    same convergence."""
     L, R, K = 4, 4, 5
     beta_f = 0.3 if model == W.FM else 0.5
-    d = W.run_desc(L, model, seed=3131, disorder_seed=12, R=R, theta=0, K=K, beta_f=beta_f)
+    d = W.run_desc(L, model, seed=3131, disorder_seed=12, R=R, R_cap=16 * R if resampling else R, theta=0, K=K,
+                   beta_f=beta_f, resampling=resampling)
     pool = oracle.many_runs_obs(d, 60000)
     jR, jD = oracle.OracleRun(d).couplings()
     _, E, Mg = exact.enumerate_states(L, jR, jD)
     i = K - 1
     e_ex = exact.exact_from_enumeration(E, Mg, d["beta"][i], 16)["e"]
     lnZ_ex = exact.exact_from_enumeration(E, Mg, d["beta"][i], 16)["lnZ"]
-    e_runs = pool[:, i]["sumE"] / (16.0 * R)
+    alive = pool[:, i]["status"] == oracle.OK
+    e_runs = pool[alive, i]["sumE"] / (16.0 * pool[alive, i]["R_i"])
     plain_bias = e_runs.mean() - e_ex
     plain_err = e_runs.std() / math.sqrt(len(e_runs))
     assert abs(plain_bias) > 6 * plain_err         # finite R: PA alone is biased here

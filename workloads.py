@@ -31,7 +31,7 @@ Q_TWO_POP = 2
 Q_WANG = 3          # permutation pairing of Wang et al. (Sec. III D)
 Q_WANG_RDM = 4      # the same with a random search pattern
 
-THETA_EXACT = -1    # theta = infinity: energies drawn from the exact distribution (Sec. V B)
+THETA_EXACT = -1    # theta = infinity: energies drawn from the exact distribution (Sec. V C)
 
 RUN_SEED_BASE = 0x5EED_0000_0000
 DISORDER_SEED_BASE = 0xD150_0000_0000
