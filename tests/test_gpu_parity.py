@@ -287,6 +287,39 @@ def test_weighted_average_parity(repr_, kind):
     ctx.close()
 
 
+@pytest.mark.parametrize("M", [1024, 256])
+def test_weighted_average_parity_at_benchmark_groupings(M):
+    """The device's weighted averages over groups as large as the
+    benchmark's (4 groups of 1024 runs; 16 groups of 256), runs of different
+    target sizes, half of them nearest-integer (so the full weight's
+    R_{k-1}/R factors differ per run), both weight kinds, versus the oracle."""
+    n = 4096
+    say(f"weighted averages over groups of M={M} ({n} runs)")
+    runs = [W.run_desc(8, W.FM, seed=0x3A00 + m, R=40 + 8 * (m % 7), theta=1, K=9, beta_f=0.8,
+                       resampling=W.NEAREST_INT if m % 2 else W.MULTINOMIAL) for m in range(n)]
+    ctx = pa.Context(runs, "msc")
+    ctx.run(1, 9)
+    obs_dev = ctx.obs()[:, 0, :]
+    obs = np.empty_like(obs_dev)
+    for m, d in enumerate(runs):
+        obs[m] = oracle.OracleRun(d).run_all().obs()[0]
+    for f in INT_FIELDS:
+        assert np.array_equal(obs_dev[f], obs[f]), f
+    Rs = np.array([d["R"] for d in runs], np.int32)
+    for kind in (0, 1):
+        got = ctx.weighted_average(M, kind, 0)
+        assert got.shape[0] == n // M
+        for grp in range(n // M):
+            sl = slice(grp * M, (grp + 1) * M)
+            ref = oracle.weighted_average(obs[sl], runs[0]["beta"], 64, Rs[sl], kind)
+            assert np.array_equal(got[grp]["n_included"], ref["n_included"])
+            for f in pa.PA_WAVG_DTYPE.names:
+                if f in ("n_included", "_pad"):
+                    continue
+                assert close(got[grp][f], ref[f]), (kind, grp, f, got[grp][f], ref[f])
+    ctx.close()
+
+
 @pytest.mark.parametrize("overlap", [W.Q_INDEX_SHIFT, W.Q_TWO_POP])
 def test_weighted_overlap_distribution_and_family_stats_parity(overlap):
     """Eq. (W_conf_q) on the device, with every weight kind and the
@@ -510,7 +543,8 @@ def test_multichunk_and_small_runs_in_one_context(repr_):
     ctx.close()
 
 
-@pytest.mark.parametrize("L,model", [(8, W.FM), (16, W.EA_PMJ), (32, W.FM)])
+@pytest.mark.parametrize("L,model", [(8, W.FM), (16, W.EA_PMJ), (24, W.FM), (24, W.EA_PMJ), (32, W.FM),
+                                     (48, W.FM), (48, W.EA_PMJ), (64, W.EA_PMJ)])
 @pytest.mark.parametrize("persistent", [0, 1])
 def test_single_size_kernel(L, model, persistent):
     """A context whose runs share one lattice size and model launches the

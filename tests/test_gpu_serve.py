@@ -85,6 +85,37 @@ def test_each_request_same_alone_and_in_the_mix(repr_):
     srv.close()
 
 
+def test_serving_tuned_shapes_on_large_lattices():
+    """The launch shapes the serving benchmark loads (1024 threads, four
+    lockstep calls, two or three replica groups per workgroup at L = 64, 48)
+    on +-J requests of L = 48 and 64 next to smaller ones: each request's
+    records in the mix equal those of the same descriptor alone in a
+    context with default shapes, and the L = 48 and L = 64 requests equal
+    the oracle's."""
+    import os
+    cache = os.path.join(os.path.dirname(pa.__file__), "tuning_cache_serving.json")
+    say("serving mix with the serving tuning cache, L up to 64")
+    specs = [(64, 500, 8), (48, 700, 9), (16, 900, 10), (32, 600, 7), (64, 300, 6), (24, 800, 8)]
+    trace = []
+    for q, (L, R, K) in enumerate(specs):
+        d = W.run_desc(L, W.EA_PMJ, seed=W.RUN_SEED_BASE + 0x7400 + q, disorder_seed=W.DISORDER_SEED_BASE + 0x740 + q,
+                       R=R, theta=3, K=K, beta_f=2.0, overlap=W.Q_INDEX_SHIFT)
+        trace.append((0.0, d))
+    srv = Server(256 << 20, max_slots=3, repr_="msc", tuning_cache=cache)
+    rec, summary = replay(srv, trace, time_scale=0.0)
+    srv.close()
+    assert summary["peak_resident"] == 3
+    for q, (_, d) in enumerate(trace):
+        assert_same(rec[q]["obs"], alone(d, "msc"), f"request {q}")
+    for q in (0, 1):
+        d = trace[q][1]
+        o = oracle.OracleRun(d).run_all().obs()
+        got = rec[q]["obs"]
+        for f in INT_FIELDS:
+            assert np.array_equal(got[f][:, 0], o[f][0]), (q, f)
+        np.testing.assert_allclose(got["A"][:, 0], o["A"][0], rtol=1e-10, atol=1e-12)
+
+
 def test_request_in_the_mix_matches_the_oracle():
     say("serving mix vs oracle")
     trace = mixed_trace()
