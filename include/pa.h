@@ -177,6 +177,26 @@ pa_status pa_workspace_size(const pa_run_desc *runs, int32_t n_runs, pa_repr rep
 pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr,
                     void *dev_workspace, size_t bytes, void *hip_stream, pa_ctx **out);
 
+/* Size of the library's own device workspace used by pa_create_static. */
+#define PA_STATIC_WORKSPACE_BYTES ((size_t)128 << 20)
+
+/* pa_create without a caller-provided workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The context lives in a device array of
+ * PA_STATIC_WORKSPACE_BYTES that the library holds on each GPU it runs on
+ * until the process ends; this call allocates no device memory.  Runs needing
+ * more than that (pa_workspace_size) are rejected with PA_ERR_NOMEM before
+ * any device call.  The array is shared by every caller on one GPU: while a
+ * context created here is alive, a second pa_create_static on the same
+ * device returns PA_ERR_STATE; pa_destroy releases it.  The workspace is
+ * cleared at creation, so nothing from an earlier context carries over.
+ * Work of two contexts on one GPU's array must not overlap in time (it would
+ * race); the PA_ERR_STATE check enforces this for contexts of this process.
+ * Every other entry point works on the returned context as on one from
+ * pa_create; results are identical. */
+pa_status pa_create_static(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void *hip_stream,
+                           pa_ctx **out);
+
 /* Step (ii) for i = previous + 1: Q_i of Eq. (QBoltz) from the energies at
  * beta_{i-1}, ln Q_i and A_i (Eq. (F)), and the resampling weights of
  * Eq. (tauBoltz).  Requires the previous step to have been measured. */

@@ -24,6 +24,7 @@ PA_Q_NONE, PA_Q_INDEX_SHIFT, PA_Q_TWO_POP, PA_Q_WANG, PA_Q_WANG_RDM = 0, 1, 2, 3
 PA_W_FULL, PA_W_SIMPLE = 0, 1
 PA_W_EXCLUDE_LARGE_FAMILY = 2   # flag OR-ed into a weight kind
 PA_THETA_EXACT = -1             # theta = infinity: energies drawn from the exact distribution
+PA_STATIC_WORKSPACE_BYTES = 128 << 20   # the device array pa_create_static uses
 
 REPRS = {"int8": PA_INT8, "msc": PA_MSC64, PA_INT8: PA_INT8, PA_MSC64: PA_MSC64}
 
@@ -73,6 +74,7 @@ def lib():
         sig = {
             "pa_workspace_size": [vp, i32, i32, vp],
             "pa_create": [vp, i32, i32, vp, C.c_size_t, vp, vp],
+            "pa_create_static": [vp, i32, i32, vp, vp],
             "pa_anneal_step": [vp, i32],
             "pa_resample": [vp, i32],
             "pa_sweep": [vp, i32],
@@ -166,6 +168,15 @@ def pa_create(runs, repr_, dev_ptr: int, nbytes: int, stream_ptr: int):
                          C.c_void_p(stream_ptr), C.byref(h))
     if st:
         raise PAError("pa_create", st)
+    return h
+
+
+def pa_create_static(runs, repr_, stream_ptr: int):
+    arr, _keep = make_descs(runs)
+    h = C.c_void_p()
+    st = lib().pa_create_static(arr, len(runs), REPRS[repr_], C.c_void_p(stream_ptr), C.byref(h))
+    if st:
+        raise PAError("pa_create_static", st)
     return h
 
 
@@ -358,7 +369,9 @@ class Context:
     tensor owned by this object; the stream is torch's current stream (or
     the one given)."""
 
-    def __init__(self, runs, repr_="msc", device="cuda", stream=None):
+    def __init__(self, runs, repr_="msc", device="cuda", stream=None, static_workspace=False):
+        """static_workspace=True creates the context with pa_create_static,
+        in the library's own device array (no workspace tensor)."""
         import torch
         if isinstance(runs, dict):
             runs = [runs]
@@ -367,12 +380,19 @@ class Context:
         self.n_runs = len(runs)
         self.npop = 2 if any(r["overlap"] == PA_Q_TWO_POP for r in runs) else 1
         self.Kmax = max(len(r["beta"]) for r in runs)
-        nbytes = pa_workspace_size(self.runs, self.repr)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        ptr = (base + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
-        self.h = pa_create(self.runs, self.repr, ptr, nbytes, self.stream.cuda_stream)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(dev):
+                self.h = pa_create_static(self.runs, self.repr, self.stream.cuda_stream)
+        else:
+            nbytes = pa_workspace_size(self.runs, self.repr)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            ptr = (self.workspace.data_ptr() + 255) & ~255
+            self.h = pa_create(self.runs, self.repr, ptr, nbytes, self.stream.cuda_stream)
         self.i = 0
 
     def close(self):

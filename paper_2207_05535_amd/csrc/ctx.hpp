@@ -112,6 +112,7 @@ struct pa_ctx {
     bool any_wang = false;
     bool any_exact_dos = false;
     hipError_t last = hipSuccess;
+    int static_dev = -1;                // device whose static workspace this context holds, or -1
 };
 
 namespace pa {

@@ -56,6 +56,21 @@ uint64_t descs_hash(const pa_ctx *c)
     return h;
 }
 
+// Device workspace owned by the library itself, for callers that cannot
+// allocate device memory (pa_create_static).  Each GPU the library runs on
+// holds its own copy of this array until the process ends.  In host code the
+// array's name is not a device address: it is resolved once per device with
+// hipGetSymbolAddress and only that address is used.
+constexpr size_t STATIC_WS_BYTES = PA_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) uint8_t scratch[STATIC_WS_BYTES];
+
+struct StaticWs {
+    uint8_t *ptr = nullptr;          // this device's copy of `scratch`
+    const pa_ctx *owner = nullptr;   // the live context using it, if any
+};
+std::mutex g_static_mu;
+std::map<int, StaticWs> g_static_ws;   // device ordinal -> its array
+
 bool same_table(const TableOff &t, int N, const pa_run_desc &d)
 {
     return t.N == N && t.K == d.K && std::memcmp(t.beta_src, d.beta, sizeof(double) * d.K) == 0;
@@ -1127,12 +1142,45 @@ const char *pa_last_error(pa_ctx *c)
     return c->last == hipSuccess ? "none" : hipGetErrorString(c->last);
 }
 
+pa_status pa_create_static(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void *hip_stream, pa_ctx **out)
+{
+    if (!out) return PA_ERR_ARG;
+    *out = nullptr;
+    size_t need = 0;
+    const pa_status st0 = pa_workspace_size(runs, n_runs, repr, &need);
+    if (st0 != PA_OK) return st0;
+    if (need > STATIC_WS_BYTES) return PA_ERR_NOMEM;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PA_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    StaticWs &w = g_static_ws[dev];
+    if (!w.ptr) {
+        // first use on this device (current): resolve its copy of the array
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PA_ERR_DEVICE;
+        w.ptr = (uint8_t *)p;
+    }
+    if (w.owner) return PA_ERR_STATE;   // one live context per device holds the array
+    pa_ctx *c = nullptr;
+    const pa_status st = pa_create(runs, n_runs, repr, w.ptr, STATIC_WS_BYTES, hip_stream, &c);
+    if (st != PA_OK) return st;
+    c->static_dev = dev;
+    w.owner = c;
+    *out = c;
+    return PA_OK;
+}
+
 pa_status pa_destroy(pa_ctx *c)
 {
     if (!c) return PA_ERR_ARG;
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->graph_def) (void)hipGraphDestroy(c->graph_def);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        StaticWs &w = g_static_ws[c->static_dev];
+        if (w.owner == c) w.owner = nullptr;
+    }
     delete c;
     return PA_OK;
 }
