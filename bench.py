@@ -101,11 +101,6 @@ def measured_traffic(kernel, launches_units):
     return e.get("bytes_per_launch")
 
 
-def flips_of(obs_rows, desc, i0, i1):
-    """Attempted flips of steps i0 .. i1-1 of one population: theta R_i N each."""
-    return int(obs_rows["R_i"][i0:i1].sum()) * desc["theta"] * desc["L"] ** 2
-
-
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -139,69 +134,120 @@ def tune(ctx, mode):
     return ctx.autotune(steps=3, cache_path=TUNING_CACHE)
 
 
-def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True):
+def spread_steps(K, steps, block=5):
+    """`steps` temperature steps in blocks of `block` consecutive steps,
+    the blocks spread evenly over the whole schedule 1 .. K-1 (the first
+    block starts at 1, the last ends at K-1); all steps when
+    steps >= K - 1.  Returned as a list of blocks."""
+    if steps >= K - 1:
+        return [list(range(1, K))]
+    nb = max(1, -(-steps // block))
+    sizes = [steps // nb + (1 if b < steps % nb else 0) for b in range(nb)]
+    last_start = K - sizes[-1]
+    starts = [1 + round(b * (last_start - 1) / (nb - 1)) if nb > 1 else 1 for b in range(nb)]
+    return [list(range(st, st + sz)) for st, sz in zip(starts, sizes)]
+
+
+def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True, blocks=None):
     """Graph-replayed batched path over `steps` temperature steps (plus the
     weighted average over groups of M runs when M is given), timed with HIP
     events and the host clock; then the same steps eagerly with events
-    around every sweep launch (records must be identical)."""
+    around every sweep launch (records must be identical).
+
+    blocks: the temperature steps to time, as blocks of consecutive steps
+    spread over the schedule (None: steps 1 .. steps in one block).  Each
+    block is timed from a checkpoint taken in an untimed pass over the whole
+    schedule (which is also the warm-up): restore the state before the
+    block (untimed), synchronize, replay the block's steps from the step
+    graph, synchronize; the timed region is the sum of those intervals, the
+    weighted average after the last block included."""
+    import numpy as np
     import torch
 
     import paper_2207_05535_amd as pa
 
-    K1 = 1 + steps
     ctx = pa.Context(descs, "msc")
     tuned = tune(ctx, tune_mode)
     L0 = descs[0]["L"]
+    Kr = len(descs[0]["beta"])
+    if blocks is None:
+        blocks = [list(range(1, 1 + steps))]
+    timed = [i for blk in blocks for i in blk]
     ck = ctx.checkpoint()
-    ctx.run(1, 1 + warmup)                       # instantiates the step graph
+    before = {}
+    if blocks[0][0] == 1:
+        before[1] = ck
+    # untimed pass (warm-up; instantiates the step graph), keeping the state
+    # before each block (host copies of the workspace)
+    at = 1
+    for blk in blocks:
+        if blk[0] > at:
+            ctx.run(at, blk[0])
+            at = blk[0]
+        torch.cuda.synchronize()
+        if blk[0] not in before:
+            before[blk[0]] = ctx.checkpoint()
+    end = min(Kr, max(at + warmup, timed[-1] + 1))
+    if end > at:
+        ctx.run(at, end)
     torch.cuda.synchronize()
-    ctx.restore(ck)
-    torch.cuda.synchronize()
-    log(f"batched path: timing {steps} steps of {len(descs)} run(s)")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    ctx.run(1, K1)
-    wavg = ctx.weighted_average(M if M else 1, pa.PA_W_FULL, 0)   # Sec. IV, FP64 on the device
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    log(f"batched path: timing {len(timed)} steps of {len(descs)} run(s) in {len(blocks)} block(s)")
+    wall = 0.0
+    dev = 0.0
+    for k, blk in enumerate(blocks):
+        ctx.restore(before[blk[0]])
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        ctx.run(blk[0], blk[-1] + 1)
+        if k == len(blocks) - 1:
+            wavg = ctx.weighted_average(M if M else 1, pa.PA_W_FULL, 0)   # Sec. IV, FP64 on the device
+        ev1.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        dev += ev0.elapsed_time(ev1) / 1e3
     obs_graph = ctx.obs()
-    flips = sum(flips_of(obs_graph[r, p], descs[r], 1, K1)
+    flips = sum(int(obs_graph[r, p]["R_i"][i]) * descs[r]["theta"] * descs[r]["L"] ** 2
                 for r in range(len(descs)) for p in range(obs_graph.shape[1])
-                if p == 0 or descs[r]["overlap"] == pa.PA_Q_TWO_POP)
-    res = dict(wall_s=t1 - t0, dev_s=ev0.elapsed_time(ev1) / 1e3, flips=flips, wavg=wavg,
+                if p == 0 or descs[r]["overlap"] == pa.PA_Q_TWO_POP for i in timed)
+    res = dict(wall_s=wall, dev_s=dev, flips=flips, wavg=wavg, timed=timed, blocks=blocks,
                tuning=ctx.tuning(L0), tuned=tuned, obs=obs_graph)
     if per_kernel:
         log("batched path: per-kernel timing pass")
-        ctx.restore(ck)
-        torch.cuda.synchronize()
-        st0 = ctx.stats()
         sweep_ms, step_ms = [], []
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-                torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for k, i in enumerate(range(1, K1)):
-            a, b, c = evs[k]
-            a.record()
-            ctx.anneal_step(i)
-            ctx.resample(i)
-            b.record()
-            ctx.sweep(i)
-            c.record()
-            ctx.measure(i)
-        done = torch.cuda.Event(enable_timing=True)
-        done.record()
-        torch.cuda.synchronize()
-        for k in range(steps):
-            a, b, c = evs[k]
-            nxt = evs[k + 1][0] if k + 1 < steps else done
-            sweep_ms.append(b.elapsed_time(c))
-            step_ms.append(a.elapsed_time(nxt))
-        st1 = ctx.stats()
-        assert ctx.obs().tobytes() == obs_graph.tobytes(), "graph replay differs from eager steps"
-        res.update(sweep_ms=sweep_ms, step_ms=step_ms, words=st1["words"] - st0["words"],
-                   calls=st1["calls"] - st0["calls"], sweep_flips=st1["flips"] - st0["flips"])
+        words = calls = sweep_flips = 0
+        for blk in blocks:
+            ctx.restore(before[blk[0]])
+            torch.cuda.synchronize()
+            st0 = ctx.stats()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+                    torch.cuda.Event(enable_timing=True)) for _ in blk]
+            for k, i in enumerate(blk):
+                a, b, c = evs[k]
+                a.record()
+                ctx.anneal_step(i)
+                ctx.resample(i)
+                b.record()
+                ctx.sweep(i)
+                c.record()
+                ctx.measure(i)
+            done = torch.cuda.Event(enable_timing=True)
+            done.record()
+            torch.cuda.synchronize()
+            for k in range(len(blk)):
+                a, b, c = evs[k]
+                nxt = evs[k + 1][0] if k + 1 < len(blk) else done
+                sweep_ms.append(b.elapsed_time(c))
+                step_ms.append(a.elapsed_time(nxt))
+            st1 = ctx.stats()
+            words += st1["words"] - st0["words"]
+            calls += st1["calls"] - st0["calls"]
+            sweep_flips += st1["flips"] - st0["flips"]
+        got = ctx.obs()
+        same = all(np.array_equal(got[:, :, i], obs_graph[:, :, i]) for i in timed)
+        assert same, "graph replay differs from eager steps"
+        res.update(sweep_ms=sweep_ms, step_ms=step_ms, words=words, calls=calls, sweep_flips=sweep_flips)
     ctx.close()
     return res
 
@@ -213,52 +259,77 @@ def roofline_of(b, steps):
     return sweep_avg_s, achieved
 
 
-def run_plain(desc, steps, warmup, obs_ref):
+def run_plain(desc, timed, warmup, obs_ref):
+    """The plain path (int8, one colour of one run per launch, host-driven
+    steps) on the same temperature steps as the batched path: each timed
+    step from a checkpoint of an untimed pass (consecutive steps in one
+    interval); its records must equal the batched path's bit for bit."""
     import numpy as np
     import torch
 
     import paper_2207_05535_amd as pa
-    K1 = 1 + steps
     log("plain path: create")
     pctx = pa.Context([desc], "int8")
+    # untimed pass: warm-up, and the state before each run of consecutive timed steps
+    segs = []
+    for i in timed:
+        if segs and segs[-1][-1] == i - 1:
+            segs[-1].append(i)
+        else:
+            segs.append([i])
+    before = {}
     pck = pctx.checkpoint()
-    for i in range(1, 1 + warmup):
+    at = 1
+    for seg in segs:
+        while at < seg[0]:
+            pctx.step(at)
+            at += 1
+        torch.cuda.synchronize()
+        before[seg[0]] = pctx.checkpoint()
+    for i in range(at, 1 + max(warmup, 1)):
         pctx.step(i)
     torch.cuda.synchronize()
     pctx.restore(pck)
     del pck
     torch.cuda.synchronize()
-    log(f"plain path: timing {steps} steps")
+    log(f"plain path: timing {len(timed)} steps")
     sw = []
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
-    torch.cuda.synchronize()
-    st0 = pctx.stats()
-    t0 = time.perf_counter()
-    e0.record()
-    for k, i in enumerate(range(1, K1)):
-        pctx.anneal_step(i)
-        pctx.resample(i)
-        sev[k][0].record()
-        pctx.sweep(i)
-        sev[k][1].record()
-        pctx.measure(i)
-    pw = pctx.weighted_average(1, pa.PA_W_FULL, 0)
-    e1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st1 = pctx.stats()
-    for a, b in sev:
-        sw.append(a.elapsed_time(b))
+    wall = dev = 0.0
+    calls = words = 0
+    last = timed[-1]
+    for seg in segs:
+        pctx.restore(before[seg[0]])
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in seg]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        st0 = pctx.stats()
+        t0 = time.perf_counter()
+        e0.record()
+        for k, i in enumerate(seg):
+            pctx.anneal_step(i)
+            pctx.resample(i)
+            sev[k][0].record()
+            pctx.sweep(i)
+            sev[k][1].record()
+            pctx.measure(i)
+        if seg[-1] == last:
+            pw = pctx.weighted_average(1, pa.PA_W_FULL, 0)
+        e1.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        dev += e0.elapsed_time(e1) / 1e3
+        st1 = pctx.stats()
+        calls += st1["calls"] - st0["calls"]
+        words += st1["words"] - st0["words"]
+        for a, b in sev:
+            sw.append(a.elapsed_time(b))
     obs_plain = pctx.obs()[0, 0].copy()
     ints = [f for f in pa.PA_OBS_DTYPE.names if f not in ("lnQ", "A")]
-    same = all(np.array_equal(obs_plain[f][:K1], obs_ref[f][:K1]) for f in ints)
-    same_fp = bool(np.allclose(obs_plain["A"][:K1], obs_ref["A"][:K1], rtol=1e-12, atol=0))
+    same = all(np.array_equal(obs_plain[f][timed], obs_ref[f][timed]) for f in ints)
+    same_fp = bool(np.allclose(obs_plain["A"][timed], obs_ref["A"][timed], rtol=1e-12, atol=0))
     pctx.close()
-    return dict(wall_s=t1 - t0, dev_s=e0.elapsed_time(e1) / 1e3, sweep_ms=sw,
-                bit_exact=bool(same and same_fp), free_energy=float(pw[0]["minus_beta_WF"][steps]),
-                calls=st1["calls"] - st0["calls"], words=st1["words"] - st0["words"])
+    return dict(wall_s=wall, dev_s=dev, sweep_ms=sw, bit_exact=bool(same and same_fp),
+                free_energy=float(pw[0]["minus_beta_WF"][last]), calls=calls, words=words)
 
 
 def workload_summary(b, steps, name):
@@ -475,26 +546,37 @@ def run_bias_vs_M(P=30720, L=10, R=100, K=61, beta_f=0.6, thetas=(1, 5),
     return out
 
 
-def cpu_baseline(desc, max_seconds=20.0):
+def cpu_baseline(desc, sample_every=8):
     """The oracle (single-threaded C, as it stands) on a bounded sample of
-    the same workload: R = 2000 of the 1e5 replicas, the same lattice, theta
-    and schedule, whole temperature steps from i = 1 until ~max_seconds."""
+    the same workload at its full size: the L = 64 run with all R = 1e5
+    replicas is created (untimed), then temperature step 1 is timed --
+    reweighting and resampling, and the measurement, over the whole
+    population; the theta = 10 sweeps over every `sample_every`-th replica
+    group (the oracle sweeps group by group, so the time scales with the
+    number of groups) -- and the sweep time is scaled to all groups.
+    A whole step at this size takes minutes on one core."""
     import oracle
-    import workloads as W
-    d = W.with_(desc, R=2000, R_cap=2000)
-    run = oracle.OracleRun(d)
+    run = oracle.OracleRun(desc)
+    G = (desc["R"] + 63) // 64
+    groups = list(range(0, G, sample_every))
     t0 = time.perf_counter()
-    flips = 0
-    i = 0
-    while time.perf_counter() - t0 < max_seconds and i + 1 < d["K"]:
-        i += 1
-        run.step(i)
-        flips += int(run.obs()[0, i]["R_i"]) * d["theta"] * d["L"] ** 2
-    dt = time.perf_counter() - t0
-    return dict(value=flips / dt / 1e9, unit="spin flips/ns", cores=1, host_cores=os.cpu_count(),
+    run.anneal_step(1)
+    run.resample(1)
+    t1 = time.perf_counter()
+    run.sweep_groups(1, groups)
+    t2 = time.perf_counter()
+    run.measure(1)
+    t3 = time.perf_counter()
+    R1 = int(run.obs()[0, 1]["R_i"])
+    flips = R1 * desc["theta"] * desc["L"] ** 2
+    t_sweep = (t2 - t1) * G / len(groups)
+    t_step = (t1 - t0) + (t3 - t2) + t_sweep
+    return dict(value=flips / t_step / 1e9, unit="spin flips/ns", cores=1, host_cores=os.cpu_count(),
                 kind="oracle",
-                sample=f"L=64 FM, R=2000 (of 100000), theta=10, temperature steps 1..{i} of the "
-                       f"200-point schedule, whole steps (ii)-(v); {flips} flips in {dt:.1f} s")
+                sample=f"L=64 FM at full size (R=100000, N=4096, theta=10), temperature step 1: reweighting "
+                       f"and resampling ({t1 - t0:.2f} s) and measurement ({t3 - t2:.2f} s) over the whole "
+                       f"population, the sweeps over every {sample_every}th replica group ({len(groups)} of {G}, "
+                       f"{t2 - t1:.1f} s) scaled to all groups; {flips} flips in {t_step:.1f} s (scaled)")
 
 
 def _oracle_steps(job):
@@ -644,7 +726,10 @@ def main():
 
 def headline(desc, steps, warmup, args, only):
     log(f"headline: L={desc['L']} R={desc['R']}")
-    b = time_batched([desc], steps, warmup, args.tune)
+    blocks = spread_steps(desc["K"], steps)
+    timed = [i for blk in blocks for i in blk]
+    steps = len(timed)
+    b = time_batched([desc], steps, warmup, args.tune, blocks=blocks)
     value = b["flips"] / b["wall_s"] / 1e9
     sweep_avg_s, achieved = roofline_of(b, steps)
     traffic = measured_traffic("k_sweep_msc", steps)
@@ -665,6 +750,12 @@ def headline(desc, steps, warmup, args, only):
             "workload": "2D Ising ferromagnet L=64 periodic, R=100000, beta 0->0.6 in 200 points, "
                         "theta=10, multinomial resampling (199 temperature steps)",
             "L": 64, "R": 100000, "theta": 10, "K": 200, "steps_timed": steps,
+            "timed_steps": ["%d..%d" % (blk[0], blk[-1]) for blk in blocks],
+            "timed_betas": [[round(desc["beta"][blk[0]], 4), round(desc["beta"][blk[-1]], 4)] for blk in blocks],
+            "timing": ("each block of consecutive steps replayed from the step graph, starting from a "
+                       "checkpoint of an untimed pass over the whole schedule, synchronised before and "
+                       "after; the timed region is the sum of those intervals")
+                      if len(blocks) > 1 else "one interval",
             "path": "batched: 64 replicas per u64 word, lattice in LDS for all sweeps, "
                     "graph-replayed steps",
         },
@@ -688,7 +779,7 @@ def headline(desc, steps, warmup, args, only):
     line["roofline"]["frac_of_calibrated"] = round(achieved / (40.0 * cal), 4)
     line["roofline"]["philox_calls_per_s"] = cal
     if not args.no_plain and "plain" in only:
-        p = run_plain(desc, steps, warmup, b["obs"][0, 0])
+        p = run_plain(desc, timed, warmup, b["obs"][0, 0])
         N = desc["L"] ** 2
         plain_sweep_avg = sum(p["sweep_ms"]) / len(p["sweep_ms"]) / 1e3 / (2 * desc["theta"])
         # algorithmic bytes per int8 colour launch: read every site of the

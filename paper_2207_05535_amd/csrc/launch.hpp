@@ -3,9 +3,22 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "pa_internal.hpp"
 
 namespace pa {
+
+// One launch of the batched sweep: the items of one (lattice size, model)
+// class, swept by the kernel compiled for that class (L = 0: the kernel
+// that dispatches per item, for the sizes without one of their own).
+struct SweepClass {
+    int first, count;   // items [first, first + count) of the sweep list
+    int L, ea;
+    int grid;           // > 0: persistent grid of this many workgroups
+    size_t lds;
+};
+constexpr int MAX_SWEEP_CLASSES = 16;
 
 struct LaunchCtx {
     const RunInfo *runs;      // device [n_runs]
@@ -25,13 +38,12 @@ struct LaunchCtx {
     unsigned long long *stats;   // device [NSTAT] work counters of the sweeps
     const SweepItem *meas_items;   // device [n_meas_items]: groups per measure workgroup
     int n_meas_items;
-    const SweepItem *sweep_items;  // device [n_sweep_items]
+    const SweepItem *sweep_items;  // device [n_sweep_items], grouped by class
     int n_sweep_items, sweep_threads, sweep_dense;
-    int sweep_grid;                // > 0: persistent grid of this many workgroups
     int sweep_pooled;              // 1: sparse rounds over one list per workgroup
-    int sweep_L = 0, sweep_ea = 0;  // every run of the context has this L and model (0: mixed)
+    int n_sweep_classes = 0;       // launches of the batched sweep, one per class
+    SweepClass sweep_cls[MAX_SWEEP_CLASSES];
     unsigned int *sweep_queue;     // device [2] ticket counters of the persistent grid
-    size_t sweep_lds;
     hipStream_t stream;
 };
 
@@ -55,6 +67,15 @@ size_t msc_lds_bytes(int N, int groups);
 hipError_t prepare_msc_lds(size_t bytes);
 int sweep_msc_resident(int threads, size_t lds, int L, int ea);   // workgroups resident on the device, 0 on error
 bool msc_specialised(int L);   // a sweep kernel compiled for this L alone exists
+// The launches of the batched sweep for these items (already largest
+// first): drops the items of runs without Metropolis sweeps (run_L[r] = 0:
+// theta = 0 or the theta = infinity limit) and fills cls with the classes
+// to launch (run_L[r], run_ea[r]: run r's lattice size and model).  Returns
+// the number of classes (at most MAX_SWEEP_CLASSES), or -1 on error.
+int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, const std::vector<int> &run_ea,
+                  SweepClass *cls);
+// Persistent grids of the classes (threads per workgroup as launched).
+bool sweep_class_grids(SweepClass *cls, int n, int threads, bool persistent);
 hipError_t prepare_wang_lds(size_t bytes);
 hipError_t launch_philox_rate(int calls, hipStream_t s, int *blocks, int *threads);
 

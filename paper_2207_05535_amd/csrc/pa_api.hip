@@ -475,22 +475,27 @@ pa_status upload_sweep_plan(pa_ctx *c)
     std::vector<SweepItem> items;
     size_t lds = 0;
     if (!plan_sweep(c, items, lds)) return PA_ERR_ARG;
+    std::vector<int> run_L(c->n_runs), run_ea(c->n_runs);
+    for (int r = 0; r < c->n_runs; ++r) {
+        run_L[r] = c->descs[r].theta > 0 ? c->descs[r].L : 0;
+        run_ea[r] = c->descs[r].model == PA_EA_PMJ;
+    }
+    SweepClass cls[MAX_SWEEP_CLASSES];
+    const int ncls = sweep_classes(items, run_L, run_ea, cls);
+    if (ncls < 0) return PA_ERR_ARG;
     if (prepare_msc_lds(lds) != hipSuccess) return dev_fail(c);
-    PA_HIP(c, hipMemcpyAsync(at<SweepItem>(c, c->lo.sweep_items), items.data(), sizeof(SweepItem) * items.size(),
-                             hipMemcpyHostToDevice, c->stream));
+    if (!items.empty())
+        PA_HIP(c, hipMemcpyAsync(at<SweepItem>(c, c->lo.sweep_items), items.data(),
+                                 sizeof(SweepItem) * items.size(), hipMemcpyHostToDevice, c->stream));
     PA_HIP(c, hipStreamSynchronize(c->stream));
+    if (!sweep_class_grids(cls, ncls, c->sweep_threads, c->sweep_persistent)) return dev_fail(c);
     c->lc.sweep_items = at<SweepItem>(c, c->lo.sweep_items);
     c->lc.n_sweep_items = (int)items.size();
     c->lc.sweep_threads = c->sweep_threads;
     c->lc.sweep_dense = c->sweep_dense;
-    c->lc.sweep_lds = lds;
-    c->lc.sweep_grid = 0;
     c->lc.sweep_pooled = c->sweep_pooled ? 1 : 0;
-    if (c->sweep_persistent) {
-        const int resident = sweep_msc_resident(c->sweep_threads, lds, c->lc.sweep_L, c->lc.sweep_ea);
-        if (resident <= 0) return dev_fail(c);
-        c->lc.sweep_grid = resident;
-    }
+    c->lc.n_sweep_classes = ncls;
+    std::copy(cls, cls + ncls, c->lc.sweep_cls);
     return PA_OK;
 }
 
@@ -638,26 +643,15 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.any_multinomial = c->any_multinomial;
     c->lc.mn_split = 1;
     c->lc.any_overlap = false;
-    int sweep_L = 0, sweep_model = -1;   // the one (L, model) of the runs that sweep, if they share it
-    bool mixed = false;
     for (int r = 0; r < n_runs; ++r) {
         if (runs[r].resampling == PA_MULTINOMIAL && runs[r].R > CH) c->lc.mn_split = CH_PER;
         if (runs[r].overlap != PA_Q_NONE) c->lc.any_overlap = true;
-        if (runs[r].theta <= 0) continue;
-        if (sweep_model < 0) {
-            sweep_L = runs[r].L;
-            sweep_model = runs[r].model;
-        } else if (runs[r].L != sweep_L || runs[r].model != sweep_model) {
-            mixed = true;
-        }
     }
-    c->lc.sweep_L = !mixed && sweep_model >= 0 && msc_specialised(sweep_L) ? sweep_L : 0;
-    c->lc.sweep_ea = c->lc.sweep_L && sweep_model == PA_EA_PMJ ? 1 : 0;
     c->lc.any_wang = c->any_wang;
     c->lc.any_exact_dos = c->any_exact_dos;
     c->lc.stats = at<unsigned long long>(c, Lo.stats);
     c->lc.sweep_queue = at<unsigned int>(c, Lo.queue);
-    c->lc.sweep_grid = 0;
+    c->lc.n_sweep_classes = 0;
     c->lc.stream = c->stream;
 
     auto fail = [&](pa_status s) {

@@ -271,6 +271,17 @@ pa_status rebuild(pa_server *s)
         const long wb = (long)b.ngroups * s->slots[b.run].d.L * s->slots[b.run].d.L;
         return wa > wb;
     });
+    // lattice size and model of each slot's run, for the per-class sweep launches
+    std::vector<int> run_L(std::max(hi, 1), 0), run_ea(std::max(hi, 1), 0);
+    for (int k = 0; k < hi; ++k)
+        if (s->slots[k].used) {
+            run_L[k] = s->slots[k].d.theta > 0 ? s->slots[k].d.L : 0;
+            run_ea[k] = s->slots[k].d.model == PA_EA_PMJ;
+        }
+    if (s->repr == PA_MSC64) {
+        SweepClass probe[MAX_SWEEP_CLASSES];
+        if (sweep_classes(sweep, run_L, run_ea, probe) < 0) return PA_ERR_ARG;   // orders the list by class
+    }
     if (!grow(s, s->items_off, s->items_cap, sizeof(Item) * std::max<size_t>(n_items, 1)) ||
         !grow(s, s->chunks_off, s->chunks_cap, sizeof(ChunkItem) * std::max<size_t>(n_chunks, 1)) ||
         !grow(s, s->sweep_off, s->sweep_cap, sizeof(SweepItem) * std::max<size_t>(sweep.size(), 1)) ||
@@ -323,16 +334,15 @@ pa_status rebuild(pa_server *s)
     c.n_sweep_items = (int)sweep.size();
     c.sweep_threads = s->threads;
     c.sweep_dense = s->dense;
-    c.sweep_lds = lds;
-    c.sweep_grid = 0;
     c.sweep_pooled = s->pooled ? 1 : 0;
+    c.n_sweep_classes = 0;
     if (s->repr == PA_MSC64 && !sweep.empty()) {
         if (prepare_msc_lds(lds) != hipSuccess) return sfail(s);
-        if (s->persistent) {
-            const int resident = sweep_msc_resident(s->threads, lds, s->lc.sweep_L, s->lc.sweep_ea);
-            if (resident <= 0) return sfail(s);
-            c.sweep_grid = resident;
-        }
+        const int ncls = sweep_classes(sweep, run_L, run_ea, c.sweep_cls);
+        if (ncls < 0) return PA_ERR_ARG;
+        if (!sweep_class_grids(c.sweep_cls, ncls, s->threads, s->persistent)) return sfail(s);
+        c.n_sweep_classes = ncls;
+        c.n_sweep_items = (int)sweep.size();
     }
     s->dirty = false;
     return PA_OK;

@@ -12,7 +12,7 @@ density of states.
 * At L = 10 and R = 2 10^4 the drawn energies pass a chi-square test against
   the exact distribution at every checked temperature.
 * theta = infinity runs batched with Metropolis runs give each run's own
-  oracle records.
+  oracle records, also beside runs that all share one other lattice size.
 """
 import sys
 
@@ -133,6 +133,29 @@ def test_batched_with_metropolis_runs(repr_):
     for r, d in enumerate(runs):
         orc = oracle.OracleRun(d).run_all()
         assert_obs_equal(got[r, 0], orc.obs()[0], f"run {r}")
+    ctx.close()
+
+
+def test_beside_runs_of_one_other_size():
+    """Metropolis runs that share one lattice size and model (the sweep
+    kernel compiled for L = 32) beside theta = infinity runs of other sizes:
+    the theta = infinity runs take no part in the sweep launch, and every
+    run's records and final state equal the oracle's."""
+    say("theta = infinity beside single-size Metropolis runs")
+    runs = [W.run_desc(32, W.FM, seed=W.RUN_SEED_BASE + 0x6400, R=200, theta=2, K=8, beta_f=0.8),
+            W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x6401, R=300, theta=W.THETA_EXACT, K=8, beta_f=0.8),
+            W.run_desc(32, W.FM, seed=W.RUN_SEED_BASE + 0x6402, R=130, theta=1, K=8, beta_f=0.8,
+                       resampling=W.NEAREST_INT),
+            W.run_desc(6, W.FM, seed=W.RUN_SEED_BASE + 0x6403, R=90, theta=W.THETA_EXACT, K=8, beta_f=0.8)]
+    ctx = pa.Context(runs, "msc")
+    ctx.run(1, 8)
+    got = ctx.obs()
+    for r, d in enumerate(runs):
+        orc = oracle.OracleRun(d).run_all()
+        assert_obs_equal(got[r, 0], orc.obs()[0], f"run {r}")
+        _, Eo, fo, _ = orc.state(0)
+        _, Eg, fg, _ = ctx.state(r, 0)
+        assert np.array_equal(Eg, Eo) and np.array_equal(fg, fo), f"run {r}"
     ctx.close()
 
 
