@@ -837,8 +837,8 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, c
 
 // The sweep kernels' exact work counters: one set of atomics per
 // wavefront, into a slot chosen by workgroup and wavefront.
-__device__ __forceinline__ void flush_stats(unsigned long long *stats, uint32_t words, uint32_t calls,
-                                            uint32_t flips)
+__device__ __forceinline__ void flush_stats(unsigned long long *stats, uint64_t words, uint32_t calls,
+                                            uint64_t flips)
 {
     const unsigned long long w = wave_sum<unsigned long long>(words);
     const unsigned long long c = wave_sum<unsigned long long>(calls);
@@ -1055,6 +1055,78 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
     }
 }
 
+// Sparse rounds of one wavefront as a stream (lattices of at most 4096
+// sites): its undecided sites form a queue in a ring of `cap` slots (its
+// own range of the lists; an entry is LDS word << 16 | its next call << 12 |
+// site).  Every round takes the next 64 entries, whatever call each is at,
+// makes that call, and appends the sites still undecided at the tail with
+// their next call, so rounds stay full until fewer than 64 entries remain;
+// those then run all their remaining calls without being written back.
+// Each site keeps the plain most-significant-first comparison of its own
+// bit planes; only the order of the work changes.
+__device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en, int cnt,
+                                                  int cap, int N, int group0, const Thresholds &Th, uint32_t i,
+                                                  uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = __lanemask_lt();
+    int left = cnt;          // entries in the queue
+    int hs = 0, ts = cnt;    // slots of the head and of the tail (ts < cap unless the ring is full)
+    if (ts >= cap) ts -= cap;
+    while (left > 64) {
+        int slot = hs + lane;
+        if (slot >= cap) slot -= cap;
+        uint64_t und4 = e4[slot], und8 = e8[slot], acc = 0;
+        const uint32_t pk = en[slot];
+        const int addr = (int)(pk >> 16);
+        const uint32_t c = (pk >> 12) & 15u;
+        const uint32_t g = (uint32_t)(group0 + addr / N);
+        draw_call_lane(c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFu, g, i, c3, key0, key1);
+        wcalls += 64;
+        if (acc) lat[addr] ^= acc;
+        const bool more = (und4 | und8) != 0 && c < 15u;
+        const uint64_t need = __ballot(more);
+        if (more) {
+            int out = ts + __popcll(need & lt_mask);
+            if (out >= cap) out -= cap;
+            e4[out] = und4;
+            e8[out] = und8;
+            en[out] = (pk & 0xFFFF0FFFu) | ((c + 1u) << 12);
+        }
+        const int nn = __popcll(need);
+        ts += nn;
+        if (ts >= cap) ts -= cap;
+        hs += 64;
+        if (hs >= cap) hs -= cap;
+        left += nn - 64;
+    }
+    uint64_t und4 = 0, und8 = 0, acc = 0;
+    int addr = 0;
+    uint32_t n = 0, g = 0, c = 16;
+    if (lane < left) {
+        int slot = hs + lane;
+        if (slot >= cap) slot -= cap;
+        und4 = e4[slot];
+        und8 = e8[slot];
+        const uint32_t pk = en[slot];
+        addr = (int)(pk >> 16);
+        c = (pk >> 12) & 15u;
+        n = pk & 0xFFFu;
+        g = (uint32_t)(group0 + addr / N);
+    }
+    for (;;) {
+        const bool live = (und4 | und8) != 0 && c < 16u;
+        const uint64_t lv = __ballot(live);
+        if (lv == 0) break;
+        wcalls += (uint32_t)__popcll(lv);
+        if (live) {
+            draw_call_lane(c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
+            ++c;
+        }
+    }
+    if (acc) lat[addr] ^= acc;
+}
+
 // Sparse rounds over one list shared by the workgroup (ctl[h & 1] entries,
 // appended by every wavefront in the dense rounds): each round takes the
 // list in passes of one wavefront-load per wavefront; after a pass the
@@ -1167,6 +1239,9 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     int *ctl = (int *)(jb + N);                           // pooled list counts [2], pass counts [2][16]
     const bool pool = (mode >> 8) & 1;
     const int dense = mode & 0xFF;
+    // the streamed sparse rounds keep each entry's next call in its site
+    // word's top bits (sites < 4096); calls 0 .. 15 only
+    const bool stream = !pool && N <= 4096 && dense < 16;
     uint64_t *base = (uint64_t *)R.spins[pop][S.cur] + (size_t)group0 * N;
     for (int u = tid; u < G * N; u += T) {
         const int gs = u / N, n = u - gs * N;
@@ -1199,7 +1274,6 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int upw = (units + nw - 1) / nw;
     const int ub = min(units, wv * upw), ue = min(units, ub + upw);
     const uint64_t lt_mask = __lanemask_lt();
-    uint32_t nwords = 0, nflips = 0;
     uint32_t wcalls = 0;   // Philox calls of this wavefront (uniform)
     if (tid == 0) ctl[0] = ctl[1] = 0;
     for (int s = 0; s < theta; ++s) {
@@ -1233,8 +1307,6 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     acc = sc.flip;
                     und4 = sc.one & valid;
                     und8 = sc.zero & valid;
-                    nflips += (uint32_t)__popcll(valid);
-                    ++nwords;
                 }
                 for (int c = 0; c < dense; ++c) {
                     const uint64_t live = __ballot((und4 | und8) != 0);
@@ -1255,7 +1327,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     const int slot = base_slot + __popcll(need & lt_mask);
                     e4[slot] = und4;
                     e8[slot] = und8;
-                    en[slot] = ((uint32_t)addr << 16) | n;
+                    en[slot] = ((uint32_t)addr << 16) | (stream ? (uint32_t)dense << 12 : 0u) | n;
                 }
                 cnt += __popcll(need);
             };
@@ -1315,6 +1387,9 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
             if (pool)
                 sweep_sparse_pooled(lat, e4, e8, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
                                     wcalls);
+            else if (stream)
+                sweep_stream_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, ue - ub, N, group0, Th, (uint32_t)i, c3,
+                                  key0, key1, wcalls);
             else
                 sweep_sparse_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, dense, N, group0, Th, (uint32_t)i, c3, key0,
                                   key1, wcalls);
@@ -1326,7 +1401,15 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
         const int y = n / L, x = n - y * L;
         base[u] = lat[(size_t)gs * N + ((x + y) & 1) * nh + y * half + (x >> 1)];
     }
-    flush_stats(stats, nwords, lane == 0 ? wcalls : 0u, nflips);
+    // word-site updates and attempted flips of this wavefront's range, in
+    // closed form: theta sweeps x 2 colours x its units, 64 replicas each
+    // except the valid ones of the last group
+    const int mine = max(ue - ub, 0);
+    const int nlast = max(ue - max(ub, (G - 1) * nh), 0);   // its units in the last group
+    const uint64_t nwords = (uint64_t)theta * 2u * (uint64_t)mine;
+    const uint64_t nflips =
+        (uint64_t)theta * 2u * ((uint64_t)(mine - nlast) * 64u + (uint64_t)nlast * (uint64_t)__popcll(vlast));
+    flush_stats(stats, lane == 0 ? nwords : 0ull, lane == 0 ? wcalls : 0u, lane == 0 ? nflips : 0ull);
 }
 
 template <bool EA>

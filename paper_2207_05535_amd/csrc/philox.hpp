@@ -43,11 +43,14 @@ __device__ __forceinline__ uint64_t bop3(uint64_t a, uint64_t b, uint64_t c)
 
 constexpr int LUT_XOR3 = lut3(LUT_A ^ LUT_B ^ LUT_C);   // 0x96
 
-__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                          uint32_t k1)
+// Rounds FIRST .. 9 of Philox4x32-10 on counter (c0..c3) with the key of
+// round FIRST.
+template <int FIRST>
+__device__ __forceinline__ u32x4 philox10_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1)
 {
 #pragma unroll
-    for (int round = 0; round < 10; ++round) {
+    for (int round = FIRST; round < 10; ++round) {
         uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         if (round == 9) {
@@ -68,6 +71,38 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         k1 += 0xBB67AE85u;
     }
     return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1)
+{
+    return philox10_rounds<0>(c0, c1, c2, c3, k0, k1);
+}
+
+// The same generator for the Metropolis draws: there the odd counter words
+// of round 0 (the replica group and the tag word) and of round 1 (the low
+// half of the product of the temperature index) are the same for every call
+// of a site and often for the whole workgroup, so they are mixed with the key
+// first, as a separate XOR that the compiler moves out of the call loops;
+// rounds 2-9 are those of philox10.  (A chain of independent calls, as in the
+// calibration, is better served by philox10's three-input XORs.)
+__device__ __forceinline__ u32x4 philox10_sweep(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        const uint32_t x1 = c1 ^ k0, x3 = c3 ^ k1;
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ x1;
+        c2 = (uint32_t)(p0 >> 32) ^ x3;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    const u32x4 r = philox10_rounds<2>(c0, c1, c2, c3, k0, k1);
+    return r;
 }
 
 }  // namespace pa
