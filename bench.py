@@ -112,6 +112,8 @@ def percentile(xs, q):
 
 
 TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache.json")
+# shapes tuned on the two-population +-J workload (L = 32 shared with the FM runs of the batch otherwise)
+TWO_POP_TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache_two_pop.json")
 # shapes tuned on a context like the serving stream (+-J, L in {16,24,32,48,64}, R = 5e4)
 SERVING_TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache_serving.json")
 
@@ -119,7 +121,7 @@ SERVING_TUNING_CACHE = os.path.join(ROOT, "paper_2207_05535_amd", "tuning_cache_
 SEARCH_OUT = [os.path.join(os.getcwd(), "tuning_cache_search.json")]
 
 
-def tune(ctx, mode):
+def tune(ctx, mode, cache=None):
     """Applies autotuned launch shapes: from the committed cache if it holds
     every L of the context, else by a search on the context's own next
     steps (its state is left unchanged).  mode "search" searches afresh and
@@ -131,7 +133,7 @@ def tune(ctx, mode):
         if d:
             os.makedirs(d, exist_ok=True)
         return ctx.autotune(steps=3, cache_path=SEARCH_OUT[0])
-    return ctx.autotune(steps=3, cache_path=TUNING_CACHE)
+    return ctx.autotune(steps=3, cache_path=cache or TUNING_CACHE)
 
 
 def spread_steps(K, steps, block=5):
@@ -148,7 +150,7 @@ def spread_steps(K, steps, block=5):
     return [list(range(st, st + sz)) for st, sz in zip(starts, sizes)]
 
 
-def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True, blocks=None):
+def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True, blocks=None, cache=None):
     """Graph-replayed batched path over `steps` temperature steps (plus the
     weighted average over groups of M runs when M is given), timed with HIP
     events and the host clock; then the same steps eagerly with events
@@ -167,7 +169,7 @@ def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True, block
     import paper_2207_05535_amd as pa
 
     ctx = pa.Context(descs, "msc")
-    tuned = tune(ctx, tune_mode)
+    tuned = tune(ctx, tune_mode, cache)
     L0 = descs[0]["L"]
     Kr = len(descs[0]["beta"])
     if blocks is None:
@@ -686,7 +688,7 @@ def main():
     if "two_pop" in only:
         d3 = W.ea_L32_two_pop()
         log("two-population EA: L=32, 2 x 200000 replicas")
-        b3 = time_batched([d3], xs(d3["K"]), warmup, args.tune)
+        b3 = time_batched([d3], xs(d3["K"]), warmup, args.tune, cache=TWO_POP_TUNING_CACHE)
         line["two_pop_ea"] = workload_summary(
             b3, xs(d3["K"]), "EA +-J L=32, two populations of R=200000 on one disorder sample, "
                              "beta 0->3 in 301 points, theta=10, q and link overlap between populations")
