@@ -77,6 +77,8 @@ def lib():
         L.or_reweight_X.restype = C.c_uint64
         L.or_sweep_draw.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.or_sweep_draw.restype = C.c_uint32
+        L.or_set_dos.argtypes = [vp, vp]
+        L.or_set_dos.restype = C.c_int
         L.or_exact_dos.argtypes = [C.c_int, vp]
         L.or_exact_dos.restype = C.c_int
         L.or_random_permutation.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int, vp]
@@ -123,6 +125,13 @@ class OracleRun:
         info = np.zeros(6, np.int32)
         lib().or_get_info(self._h, _ptr(info))
         self.N, self.npop, self.K = int(info[2]), int(info[3]), int(info[4])
+        if desc["theta"] == -1 and desc["L"] > 8:
+            # theta = infinity beyond the C transfer matrix's range: the
+            # density of states of the product formula (oracle/dos.py)
+            from .dos import fm_dos_doubles
+            gd = np.ascontiguousarray(fm_dos_doubles(desc["L"]), dtype=np.float64)
+            if lib().or_set_dos(self._h, _ptr(gd)) != OK:
+                raise ValueError("oracle rejected the density of states")
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -52,7 +52,9 @@ typedef struct {
     int32_t R_cap;          /* capacity (>= R) */
     int32_t theta;          /* sweeps per temperature; -1: theta = infinity, the
                                energies drawn from the exact distribution
-                               at beta_i (ferromagnet, L <= 8, no overlaps) */
+                               at beta_i (ferromagnet, L <= 30, no overlaps;
+                               for L > 8 the density of states is supplied
+                               with or_set_dos) */
     int32_t K;              /* number of temperatures beta[0..K-1] */
     const double *beta;     /* annealing schedule, beta[0] = 0 */
     int32_t resampling;     /* 0 = multinomial, 1 = nearest integer */
@@ -303,13 +305,12 @@ int or_exact_dos(int L, uint64_t *out /* [N+1][2]: low, high 64 bits of g[m] */)
  * 64-bit draw v selects the smallest m with v < C_m, or m = N if there is
  * none, so level m is drawn with probability w_m / S_N up to 2^-64 per
  * level. */
-static void dos_table(const uint64_t *g2, int N, double beta, uint64_t *C)
+static void dos_table(const double *gd /* g_m rounded to the nearest double */, int N, double beta, uint64_t *C)
 {
     double *S = (double *)malloc(sizeof(double) * (N + 1));
     double acc = 0.0;
     for (int m = 0; m <= N; m++) {
-        u128 gm = ((u128)g2[2 * m + 1] << 64) | g2[2 * m];
-        acc += (double)gm * exp(-4.0 * beta * (double)m);
+        acc += gd[m] * exp(-4.0 * beta * (double)m);
         S[m] = acc;
     }
     for (int m = 0; m <= N; m++) {
@@ -317,6 +318,19 @@ static void dos_table(const uint64_t *g2, int N, double beta, uint64_t *C)
         C[m] = q >= 1.0 ? UINT64_MAX : (uint64_t)ldexp(q, 64);
     }
     free(S);
+}
+
+/* The density of states of a theta = infinity run, g_m rounded to the
+ * nearest double (m = 0..N): builds the energy draw tables of every
+ * temperature.  Needed before the first step for L > 8. */
+int or_set_dos(or_run *run, const double *gd)
+{
+    if (!run || !gd || run->d.theta != -1) return OR_ERR_ARG;
+    const int N = run->N;
+    free(run->dosC);
+    run->dosC = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)run->d.K * (N + 1));
+    for (int k = 0; k < run->d.K; k++) dos_table(gd, N, run->beta[k], &run->dosC[(size_t)k * (N + 1)]);
+    return OR_OK;
 }
 
 /* Step (iv) at theta = infinity: every replica's energy is replaced by an
@@ -352,7 +366,7 @@ or_run *or_create(const or_desc *d)
         d->R_cap >= (1 << 23))
         return NULL;
     if (d->resampling == 0 && d->R_cap != d->R) return NULL;
-    if (d->theta == -1 && (d->model != 0 || d->L > 8 || d->overlap != 0)) return NULL;
+    if (d->theta == -1 && (d->model != 0 || d->L > 30 || d->overlap != 0)) return NULL;
     or_run *run = (or_run *)calloc(1, sizeof(or_run));
     run->d = *d;
     run->N = d->L * d->L;
@@ -415,12 +429,15 @@ or_run *or_create(const or_desc *d)
         }
     }
     run->obs = (or_obs *)calloc((size_t)run->npop * d->K, sizeof(or_obs));
-    if (d->theta == -1) {
+    if (d->theta == -1 && L <= 8) {
+        /* L <= 8: the density of states of the transfer matrix above;
+         * larger L: supplied with or_set_dos before the first step */
         uint64_t *g2 = (uint64_t *)malloc(sizeof(uint64_t) * 2 * (N + 1));
+        double *gd = (double *)malloc(sizeof(double) * (N + 1));
         or_exact_dos(L, g2);
-        run->dosC = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)d->K * (N + 1));
-        for (int k = 0; k < d->K; k++) dos_table(g2, N, run->beta[k], &run->dosC[(size_t)k * (N + 1)]);
-        free(g2);
+        for (int m = 0; m <= N; m++) gd[m] = (double)(((u128)g2[2 * m + 1] << 64) | g2[2 * m]);
+        or_set_dos(run, gd);
+        free(g2); free(gd);
     }
     run->rho = (double *)malloc(sizeof(double) * run->npop * d->K);
     for (int k = 0; k < run->npop * d->K; k++) run->rho[k] = NAN;
@@ -647,6 +664,7 @@ int or_sweep(or_run *run, int i)
     for (int p = 0; p < run->npop; p++) {
         if (run->pop[p].status != OR_OK) continue;
         if (run->d.theta == -1) {
+            if (!run->dosC) return OR_ERR_STATE;   /* no density of states supplied */
             dos_sample(run, p, i);
             continue;
         }

@@ -4,6 +4,10 @@
   enumeration at L = 4, and at L = 6 and 8 reproduces Kaufman's closed-form
   partition function (written independently in tests/exact.py) to 25 digits
   at several temperatures; it sums to 2^N.
+* The density of states of the product formula (oracle/dos.py), which the
+  theta = infinity limit uses beyond L = 8, equals the transfer matrix's at
+  L = 4, 6, 8, and at L = 10, 12, 16 sums to 2^N, is symmetric and
+  reproduces Kaufman's partition function to 25 digits.
 * A theta = infinity run draws every replica's energy from the exact
   distribution at beta_i: the population's energy histogram after the draw
   passes a chi-square test against g(E) exp(-beta E) / Z.
@@ -49,12 +53,35 @@ def test_dos_reproduces_kaufman(L):
             assert abs(mp.log(Z) - ref) < mp.mpf(10) ** -25 * abs(ref), (L, beta)
 
 
-def test_theta_infinity_draws_the_exact_energy_law():
+def test_product_formula_dos_equals_transfer_matrix():
+    from oracle import dos
+    for L in (4, 6, 8):
+        assert list(dos.fm_dos(L)) == oracle.exact_dos(L), L
+
+
+@pytest.mark.parametrize("L", [10, 12, 16])
+def test_product_formula_dos_reproduces_kaufman(L):
+    import mpmath as mp
+    from oracle import dos
+    g = list(dos.fm_dos(L))
+    N = L * L
+    assert sum(g) == 2 ** N and min(g) >= 0
+    assert g == g[::-1]
+    assert g[0] == 2 and g[1] == 0 and g[2] == 2 * N     # ground states; one flipped spin costs 4 bonds
+    with mp.workdps(60):
+        for beta in (0.05, 0.3, 0.4407, 0.6, 1.2):
+            Z = mp.fsum(mp.mpf(gm) * mp.exp(-mp.mpf(beta) * (-2 * N + 4 * m)) for m, gm in enumerate(g))
+            ref = exact.kaufman_lnZ(L, beta, dps=60)
+            assert abs(mp.log(Z) - ref) < mp.mpf(10) ** -25 * abs(ref), (L, beta)
+
+
+@pytest.mark.parametrize("L,R", [(4, 20000), (16, 20000)])
+def test_theta_infinity_draws_the_exact_energy_law(L, R):
     from scipy import stats
-    L, R = 4, 20000
-    d = W.run_desc(L, W.FM, seed=0x1F0, R=R, theta=THETA_INF, K=5, beta_f=0.8)
+    from oracle import dos
+    d = W.run_desc(L, W.FM, seed=0x1F0 + L, R=R, theta=THETA_INF, K=5, beta_f=0.8 if L == 4 else 0.44)
     run = oracle.OracleRun(d)
-    g = np.array(oracle.exact_dos(L), np.float64)
+    g = np.array(dos.fm_dos_doubles(L), np.float64)
     Es = energies(L)
     for i in range(1, d["K"]):
         run.step(i)
@@ -88,7 +115,7 @@ def test_theta_infinity_free_energy_unbiased():
 
 
 def test_theta_infinity_rejected_outside_its_domain():
-    for bad in (dict(model=W.EA_PMJ), dict(L=10), dict(overlap=W.Q_INDEX_SHIFT)):
+    for bad in (dict(model=W.EA_PMJ), dict(L=32), dict(overlap=W.Q_INDEX_SHIFT)):
         kw = dict(L=4, model=W.FM, overlap=W.Q_NONE)
         kw.update(bad)
         d = W.run_desc(kw["L"], kw["model"], R=10, theta=THETA_INF, K=3, beta_f=0.5, overlap=kw["overlap"])
