@@ -100,8 +100,9 @@ typedef struct {
 /* theta = PA_THETA_EXACT is the theta = infinity limit of Sec. V C: step
  * (iv) replaces every replica's energy by an independent draw from the
  * exact energy distribution g(E) exp(-beta_i E) / Z of the periodic
- * ferromagnet (model PA_FM, L <= 10, overlap PA_Q_NONE).  g comes from
- * pa_exact_dos; the draw of replica j is v = o0 | o1 << 32 of
+ * ferromagnet (model PA_FM, L <= 30, overlap PA_Q_NONE).  g comes from
+ * pa_exact_dos_wide, each g_m rounded to the nearest double (ties to
+ * even); the draw of replica j is v = o0 | o1 << 32 of
  * Philox(seed; j, 0, i, 7 << 28 | pop << 24), and the level is the smallest
  * m with v < C_m, C_m = floor(2^64 S_m / S_N) (2^64 - 1 where S_m = S_N),
  * S_m = sum_{k <= m} (double)g_k exp(-4 beta_i k) in FP64 in increasing k;
@@ -119,11 +120,20 @@ enum { PA_THETA_EXACT = -1 };
  * sweep's Philox work can reach.  1 <= calls_per_chain <= 2^20. */
 pa_status pa_calibrate_philox(void *hip_stream, int32_t calls_per_chain, double *calls_per_s);
 
-/* Exact density of states of the periodic L x L ferromagnet (host
- * computation, no device): host_out[2m], host_out[2m + 1] receive the low
- * and high 64 bits of g_m, the number of configurations with
- * E = -2N + 4m, m = 0..N (N = L^2).  L even, 4 <= L <= 10 (PA_ERR_ARG
- * otherwise).  Used by the theta = infinity limit; cached per L. */
+/* Exact density of states of the periodic L x L ferromagnet, the exact
+ * energy distribution of the theta = infinity limit (Sec. V C; the paper
+ * takes Beale's exact distribution): g_m, the number of configurations with
+ * E = -2N + 4m, m = 0..N (N = L^2), from Kaufman's closed form for the
+ * torus written as an integer polynomial in exp(-2 beta), evaluated exactly
+ * modulo primes and rebuilt by the Chinese remainder theorem (host
+ * computation, no device; cached per L).  host_out: [N + 1][limbs]
+ * little-endian 64-bit limbs of each g_m; limbs >= N/64 + 1.  L even,
+ * 4 <= L <= 30, else PA_ERR_ARG; PA_ERR_NUMERIC if the counts fail their
+ * checks (sum 2^N, no odd number of unsatisfied bonds). */
+pa_status pa_exact_dos_wide(int32_t L, int32_t limbs, uint64_t *host_out);
+
+/* The same for 4 <= L <= 10 in two limbs: host_out[2m], host_out[2m + 1]
+ * receive the low and high 64 bits of g_m. */
 pa_status pa_exact_dos(int32_t L, uint64_t *host_out);
 
 /* One record per (run, population, temperature i): integer sums over the

@@ -88,6 +88,7 @@ def lib():
             "pa_read_state": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
             "pa_read_pairing": [vp, i32, vp, vp, vp],
             "pa_exact_dos": [i32, vp],
+            "pa_exact_dos_wide": [i32, i32, vp],
             "pa_calibrate_philox": [vp, i32, vp],
             "pa_checkpoint": [vp, vp, vp],
             "pa_restore": [vp, vp, C.c_size_t],
@@ -238,12 +239,15 @@ def pa_calibrate_philox(calls_per_chain=4096, stream=None):
 
 
 def pa_exact_dos(L):
-    """Exact density of states of the periodic L x L ferromagnet (L <= 10):
-    g[m] = number of configurations with E = -2N + 4m, as Python ints."""
+    """Exact density of states of the periodic L x L ferromagnet (even L,
+    4 <= L <= 30): g[m] = number of configurations with E = -2N + 4m, as
+    Python ints (pa_exact_dos_wide)."""
     N = L * L
-    raw = np.zeros(2 * (N + 1), np.uint64)
-    _chk("pa_exact_dos", lib().pa_exact_dos(L, _p(raw)))
-    return [int(raw[2 * m]) | (int(raw[2 * m + 1]) << 64) for m in range(N + 1)]
+    limbs = N // 64 + 1
+    raw = np.zeros((N + 1) * limbs, np.uint64)
+    _chk("pa_exact_dos_wide", lib().pa_exact_dos_wide(L, limbs, _p(raw)))
+    raw = raw.reshape(N + 1, limbs)
+    return [sum(int(raw[m, w]) << (64 * w) for w in range(limbs)) for m in range(N + 1)]
 
 
 def pa_read_pairing(h, run, out):

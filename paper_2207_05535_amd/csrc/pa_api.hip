@@ -91,7 +91,7 @@ bool desc_ok(const pa_run_desc &d, pa_repr repr)
     if (d.overlap < PA_Q_NONE || d.overlap > PA_Q_WANG_RDM) return false;
     if (d.qhist != 0 && d.qhist != 1) return false;
     if (d.theta == PA_THETA_EXACT) {
-        if (d.model != PA_FM || d.L > 10 || d.overlap != PA_Q_NONE) return false;
+        if (d.model != PA_FM || d.L > 30 || d.overlap != PA_Q_NONE) return false;
     } else if (d.theta < 0 || d.theta >= (1 << 24)) {
         return false;
     }
@@ -240,75 +240,224 @@ namespace {
 
 using u128 = unsigned __int128;
 
-// Exact density of states of the periodic L x L ferromagnet by the row
-// transfer matrix, Z = Tr T^L with T(s, s') = y^(h(s') + d(s, s')), y
-// counting unsatisfied bonds (h: within a row, periodic; d: the Hamming
-// distance of two neighbouring rows).  The trace runs over the first row;
-// rows related by a cyclic shift or a global flip have the same diagonal
-// element, so one row per class is propagated and weighted by the class
-// size.  The Hamming factor is a product over columns of [[1, y], [y, 1]],
-// applied in place to each pair of rows that differ in one column.  Counts
-// are exact in 128 bits for L <= 10.  Returns the coefficients of y^u,
-// u = 0..2N (odd u never occurs on the periodic lattice).
-std::vector<u128> fm_dos_by_transfer(int L)
+// Exact density of states of the periodic L x L ferromagnet (the energy
+// distribution that the theta = infinity limit samples).  Kaufman's closed
+// form for the torus, written as a polynomial in y = exp(-2 beta), has the
+// exact integer counts as coefficients (Beale's route):
+//   sum_u g_u y^u = (Q_00 + Q_01 + Q_10 + Q_11) / 2,
+// u the number of unsatisfied bonds (E = -2N + 2u), Q_ab the product over
+// the momenta p = pi (2k + a) / L, q = pi (2l + b) / L, taken once per pair
+// {(p, q), (-p, -q)}, of (1 + y^2)^2 - 2y (1 - y^2)(cos p + cos q), and, for
+// a momentum equal to its own negative (p, q in {0, pi}), of the square
+// roots 1 - 2y - y^2 (p = q = 0), 1 + 2y - y^2 (p = q = pi), 1 + y^2.
+// The product is exact modulo primes P = 1 (mod 2L), in which the 2L-th
+// roots of unity, and so the cosines (z^j + z^-j) / 2, exist; enough primes
+// for 2^N, and the counts are rebuilt by the Chinese remainder theorem.
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((u128)a * b % p); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p)
 {
-    const int N = L * L, S = 1 << L, D = 2 * N + 1, mask = S - 1;
-    auto rot = [&](int s) { return ((s << 1) | (s >> (L - 1))) & mask; };
-    auto hrow = [&](int s) { return __builtin_popcount((unsigned)(s ^ rot(s))); };
-    std::vector<int> weight(S, 0);
-    for (int s = 0; s < S; ++s) {
-        int rep = s;
-        for (int f = 0; f < 2; ++f) {
-            int t = f ? (~s & mask) : s;
-            for (int k = 0; k < L; ++k, t = rot(t)) rep = std::min(rep, t);
-        }
-        ++weight[rep];
+    uint64_t r = 1;
+    a %= p;
+    for (; e; e >>= 1, a = mulmod(a, a, p))
+        if (e & 1) r = mulmod(r, a, p);
+    return r;
+}
+
+// Deterministic Miller-Rabin for n < 2^64 (these twelve bases suffice).
+bool is_prime(uint64_t n)
+{
+    if (n < 2) return false;
+    for (uint64_t q : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull})
+        if (n % q == 0) return n == q;
+    uint64_t d = n - 1;
+    int r = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++r;
     }
-    std::vector<u128> cur((size_t)S * D), total(D, 0);
-    for (int s1 = 0; s1 < S; ++s1) {
-        if (weight[s1] == 0) continue;
-        std::fill(cur.begin(), cur.end(), (u128)0);
-        cur[(size_t)s1 * D + hrow(s1)] = 1;
-        for (int r = 0; r < L; ++r) {
-            for (int b = 0; b < L; ++b) {   // bonds to the next row (the first row after the last)
-                const int bit = 1 << b;
-                for (int s = 0; s < S; ++s) {
-                    if (s & bit) continue;
-                    u128 *a = &cur[(size_t)s * D], *c = &cur[(size_t)(s | bit) * D];
-                    for (int u = D - 1; u >= 1; --u) {
-                        const u128 au = a[u] + c[u - 1], cu = c[u] + a[u - 1];
-                        a[u] = au;
-                        c[u] = cu;
+    for (uint64_t a : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 17ull, 19ull, 23ull, 29ull, 31ull, 37ull}) {
+        uint64_t x = powmod(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int k = 1; k < r && comp; ++k) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) comp = false;
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+// The counts g_u mod P, u = 0 .. 2N.
+std::vector<uint64_t> dos_mod(int L, uint64_t P)
+{
+    const int N = L * L, J = 2 * L;
+    // a primitive 2L-th root of unity
+    std::vector<int> pf;
+    for (int q = 2, m = J; m > 1; ++q)
+        if (m % q == 0) {
+            pf.push_back(q);
+            while (m % q == 0) m /= q;
+        }
+    uint64_t z = 0;
+    for (uint64_t a = 2; !z; ++a) {
+        const uint64_t c = powmod(a, (P - 1) / J, P);
+        bool prim = true;
+        for (int q : pf) prim = prim && powmod(c, J / q, P) != 1;
+        if (prim) z = c;
+    }
+    const uint64_t inv2 = (P + 1) / 2;
+    std::vector<uint64_t> cs(J);
+    for (int j = 0; j < J; ++j)
+        cs[j] = mulmod((powmod(z, j, P) + powmod(z, (uint64_t)(J - j) % J, P)) % P, inv2, P);
+    const uint64_t two = 2 % P, minus = P - 1, minus2 = P - 2;
+    std::vector<uint64_t> total(2 * N + 1, 0), Q;
+    std::vector<char> done((size_t)J * J);
+    auto mul = [&](const uint64_t *f, int nf) {   // Q *= f (nf coefficients), in place from the top
+        const int d = (int)Q.size();
+        Q.resize(d + nf - 1, 0);
+        for (int i = d + nf - 2; i >= 0; --i) {
+            u128 acc = 0;
+            for (int t = 0; t < nf; ++t)
+                if (i - t >= 0 && i - t < d) acc += (u128)Q[i - t] * f[t] % P;
+            Q[i] = (uint64_t)(acc % P);
+        }
+    };
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            Q.assign(1, 1);
+            std::fill(done.begin(), done.end(), 0);
+            for (int k = 0; k < L; ++k)
+                for (int l = 0; l < L; ++l) {
+                    const int jp = (2 * k + a) % J, jq = (2 * l + b) % J;
+                    if (done[(size_t)jp * J + jq]) continue;
+                    const int np = (J - jp) % J, nq = (J - jq) % J;
+                    done[(size_t)jp * J + jq] = done[(size_t)np * J + nq] = 1;
+                    if (np == jp && nq == jq) {   // p, q in {0, pi}: the square root
+                        const bool p0 = jp == 0, q0 = jq == 0;
+                        uint64_t r[3];
+                        if (p0 && q0) { r[0] = 1; r[1] = minus2; r[2] = minus; }           // 1 - 2y - y^2
+                        else if (!p0 && !q0) { r[0] = 1; r[1] = two; r[2] = minus; }       // 1 + 2y - y^2
+                        else { r[0] = 1; r[1] = 0; r[2] = 1; }                             // 1 + y^2
+                        mul(r, 3);
+                        continue;
                     }
+                    const uint64_t sum = (cs[jp] + cs[jq]) % P, s2 = mulmod(two, sum, P);
+                    const uint64_t f[5] = {1, (P - s2) % P, two, s2, 1};   // 1 - 2sy + 2y^2 + 2sy^3 + y^4
+                    mul(f, 5);
                 }
-            }
-            if (r == L - 1) break;
-            for (int s = 0; s < S; ++s) {   // the new row's own bonds
-                const int k = hrow(s);
-                if (k == 0) continue;
-                u128 *a = &cur[(size_t)s * D];
-                for (int u = D - 1; u >= 0; --u) a[u] = u >= k ? a[u - k] : 0;
-            }
+            for (int u = 0; u <= 2 * N; ++u) total[u] = (total[u] + Q[u]) % P;
         }
-        for (int u = 0; u < D; ++u) total[u] += (u128)weight[s1] * cur[(size_t)s1 * D + u];
-    }
+    for (auto &v : total) v = mulmod(v, inv2, P);
     return total;
 }
 
-// g_m for E = -2N + 4m, m = 0..N, cached per L.
-const std::vector<u128> &fm_dos(int L)
+// Multi-limb unsigned integers, little-endian 64-bit limbs.
+using Big = std::vector<uint64_t>;
+
+void big_mul_add(Big &x, uint64_t m, uint64_t a)   // x = x m + a
+{
+    u128 carry = a;
+    for (auto &w : x) {
+        const u128 t = (u128)w * m + carry;
+        w = (uint64_t)t;
+        carry = t >> 64;
+    }
+    if (carry) x.push_back((uint64_t)carry);
+}
+
+// g_m for E = -2N + 4m, m = 0 .. N (exact), or empty if a check fails.
+std::vector<Big> fm_dos_exact(int L)
+{
+    const int N = L * L;
+    const int nprimes = (N + 2) / 61 + 2;   // product of primes > 2^(61 nprimes) > 2^(N + 2)
+    std::vector<uint64_t> primes;
+    const uint64_t J = 2 * (uint64_t)L;
+    for (uint64_t k = ((1ull << 62) - 1) / J; primes.size() < (size_t)nprimes && k > 0; --k)
+        if (is_prime(k * J + 1)) primes.push_back(k * J + 1);
+    std::vector<std::vector<uint64_t>> res;
+    for (uint64_t P : primes) res.push_back(dos_mod(L, P));
+    // Garner: mixed-radix digits v_i, then x = v_0 + p_0 (v_1 + p_1 (v_2 + ...))
+    const int k = (int)primes.size();
+    std::vector<uint64_t> inv((size_t)k * k, 0);   // inv[i k + j] = p_j^-1 mod p_i
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < i; ++j) inv[(size_t)i * k + j] = powmod(primes[j] % primes[i], primes[i] - 2, primes[i]);
+    std::vector<Big> g(N + 1);
+    Big sum;
+    for (int u = 0; u <= 2 * N; ++u) {
+        std::vector<uint64_t> v(k);
+        for (int i = 0; i < k; ++i) {
+            uint64_t x = res[i][u];
+            for (int j = 0; j < i; ++j)
+                x = mulmod((x + primes[i] - v[j] % primes[i]) % primes[i], inv[(size_t)i * k + j], primes[i]);
+            v[i] = x;
+        }
+        Big x{v[k - 1]};
+        for (int i = k - 2; i >= 0; --i) big_mul_add(x, primes[i], v[i]);
+        while (x.size() > 1 && x.back() == 0) x.pop_back();
+        if (u & 1) {
+            if (x.size() != 1 || x[0] != 0) return {};   // odd u never occurs on the torus
+            continue;
+        }
+        g[u / 2] = x;
+        // running sum for the check sum_m g_m = 2^N
+        if (sum.size() < x.size()) sum.resize(x.size(), 0);
+        u128 carry = 0;
+        for (size_t w = 0; w < sum.size(); ++w) {
+            const u128 t = (u128)sum[w] + (w < x.size() ? x[w] : 0) + carry;
+            sum[w] = (uint64_t)t;
+            carry = t >> 64;
+        }
+        if (carry) sum.push_back((uint64_t)carry);
+    }
+    Big want((size_t)N / 64 + 1, 0);
+    want[N / 64] = 1ull << (N % 64);
+    while (sum.size() > 1 && sum.back() == 0) sum.pop_back();
+    while (want.size() > 1 && want.back() == 0) want.pop_back();
+    if (sum != want) return {};
+    return g;
+}
+
+// g_m, cached per L (empty if L is outside 4..30, odd, or a check failed).
+const std::vector<Big> &fm_dos(int L)
 {
     static std::mutex mu;
-    static std::map<int, std::vector<u128>> cache;
+    static std::map<int, std::vector<Big>> cache;
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(L);
     if (it == cache.end()) {
-        const std::vector<u128> byu = fm_dos_by_transfer(L);
-        std::vector<u128> g(L * L + 1);
-        for (int m = 0; m <= L * L; ++m) g[m] = byu[2 * m];
+        std::vector<Big> g;
+        if (L >= 4 && L <= 30 && (L & 1) == 0) g = fm_dos_exact(L);
         it = cache.emplace(L, std::move(g)).first;
     }
     return it->second;
+}
+
+// The nearest double to a multi-limb integer (ties to even).
+double big_to_double(const Big &x)
+{
+    int top = (int)x.size() - 1;
+    while (top > 0 && x[top] == 0) --top;
+    if (top == 0) return (double)x[0];   // one limb: the conversion rounds to nearest
+    const int hb = 63 - __builtin_clzll(x[top]);   // highest set bit within the top limb
+    const int msb = 64 * top + hb;                  // of the whole number
+    // the 64 bits below and including the highest set bit, and a sticky bit
+    const int lo = msb - 63;
+    auto bit_word = [&](int from) -> uint64_t {      // 64 bits starting at bit `from`
+        const int w = from / 64, o = from % 64;
+        uint64_t v = x[w] >> o;
+        if (o && w + 1 < (int)x.size()) v |= x[w + 1] << (64 - o);
+        return v;
+    };
+    const uint64_t t = bit_word(lo);
+    bool sticky = false;
+    for (int w = 0; w < lo / 64 && !sticky; ++w) sticky = x[w] != 0;
+    if (!sticky && lo % 64) sticky = (x[lo / 64] & ((1ull << (lo % 64)) - 1)) != 0;
+    uint64_t mant = t >> 11;   // 53 bits
+    const uint64_t rem = t & 0x7FF, half = 0x400;
+    if (rem > half || (rem == half && (sticky || (mant & 1)))) ++mant;
+    return std::ldexp((double)mant, lo + 11);
 }
 
 }  // namespace
@@ -317,15 +466,17 @@ namespace pa {
 
 bool dos_thresholds(const pa_run_desc &d, std::vector<uint64_t> &out)
 {
-    if (d.L < 4 || d.L > 10 || (d.L & 1)) return false;
+    const std::vector<Big> &g = fm_dos(d.L);
+    if (g.empty()) return false;
     const int N = d.L * d.L;
-    const std::vector<u128> &g = fm_dos(d.L);
+    std::vector<double> gd(N + 1);
+    for (int m = 0; m <= N; ++m) gd[m] = big_to_double(g[m]);
     out.assign((size_t)d.K * (N + 1), 0);
     std::vector<double> S(N + 1);
     for (int i = 0; i < d.K; ++i) {
         double acc = 0.0;
         for (int m = 0; m <= N; ++m) {
-            acc += (double)g[m] * std::exp(-4.0 * d.beta[i] * (double)m);
+            acc += gd[m] * std::exp(-4.0 * d.beta[i] * (double)m);
             S[m] = acc;
         }
         for (int m = 0; m <= N; ++m) {
@@ -942,15 +1093,20 @@ pa_status pa_calibrate_philox(void *hip_stream, int32_t calls_per_chain, double 
     return PA_OK;
 }
 
+pa_status pa_exact_dos_wide(int32_t L, int32_t limbs, uint64_t *host_out)
+{
+    if (L < 4 || L > 30 || (L & 1) || !host_out || limbs < L * L / 64 + 1) return PA_ERR_ARG;
+    const std::vector<Big> &g = fm_dos(L);
+    if (g.empty()) return PA_ERR_NUMERIC;
+    for (int m = 0; m <= L * L; ++m)
+        for (int w = 0; w < limbs; ++w) host_out[(size_t)m * limbs + w] = w < (int)g[m].size() ? g[m][w] : 0;
+    return PA_OK;
+}
+
 pa_status pa_exact_dos(int32_t L, uint64_t *host_out)
 {
     if (L < 4 || L > 10 || (L & 1) || !host_out) return PA_ERR_ARG;
-    const std::vector<u128> &g = fm_dos(L);
-    for (int m = 0; m <= L * L; ++m) {
-        host_out[2 * m] = (uint64_t)g[m];
-        host_out[2 * m + 1] = (uint64_t)(g[m] >> 64);
-    }
-    return PA_OK;
+    return pa_exact_dos_wide(L, 2, host_out);
 }
 
 pa_status pa_read_pairing(pa_ctx *c, int32_t run, int32_t *host_pairs, int32_t *status, int32_t *R_i)

@@ -59,7 +59,7 @@ def test_workspace_size_valid_and_monotone():
 
 @pytest.mark.parametrize("bad", [
     dict(L=7), dict(L=2), dict(L=2048), dict(theta=-2), dict(R=0), dict(R_cap=10),
-    dict(theta=-1, model=1), dict(theta=-1, L=12), dict(theta=-1, overlap=1),   # theta = infinity: FM, L <= 10, no q
+    dict(theta=-1, model=1), dict(theta=-1, L=32), dict(theta=-1, overlap=1),   # theta = infinity: FM, L <= 30, no q
     dict(R_cap=2000),                      # multinomial needs R_cap == R
     dict(model=3), dict(resampling=5), dict(overlap=7), dict(qhist=2),
     dict(beta=[0.1, 0.2, 0.3]),            # beta_0 must be 0
@@ -88,6 +88,21 @@ def test_exact_dos_validates_before_computing():
     for L in (2, 3, 12):
         assert lib.pa_exact_dos(L, buf.ctypes.data) == pa.PA_ERR_ARG
     assert lib.pa_exact_dos(8, None) == pa.PA_ERR_ARG
+    wide = np.zeros(16 * 1025, np.uint64)
+    for L, limbs in ((32, 17), (7, 2), (16, 4), (16, 0)):     # L even <= 30; limbs >= N/64 + 1
+        assert lib.pa_exact_dos_wide(L, limbs, wide.ctypes.data) == pa.PA_ERR_ARG
+    assert lib.pa_exact_dos_wide(16, 5, None) == pa.PA_ERR_ARG
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 12, 16])
+def test_library_dos_equals_oracle(L):
+    """The library's density of states (modular product formula, host code)
+    equals the oracle's (transfer matrix for L <= 8, high-precision product
+    formula beyond) exactly."""
+    from oracle import dos
+    import oracle
+    ref = oracle.exact_dos(L) if L <= 8 else list(dos.fm_dos(L))
+    assert pa.pa_exact_dos(L) == ref
 
 
 def test_msc_lattice_limit():

@@ -2,15 +2,17 @@
 density of states.
 
 * pa_exact_dos equals the oracle's density of states (computed by its own
-  transfer matrix) for L = 4, 6, 8; at L = 10, beyond the oracle's range, it
-  sums to 2^N, is symmetric, and reproduces Kaufman's partition function
-  (tests/exact.py) to 25 digits.
+  transfer matrix) for L = 4, 6, 8; at L = 10 it sums to 2^N, is symmetric,
+  and reproduces Kaufman's partition function (tests/exact.py) to 25 digits.
+  (The CPU tests compare it with the oracle's product formula up to L = 16.)
 * theta = infinity runs step by step against the oracle (both spin layouts,
   both resampling kinds, several replica groups with a ragged last one):
   records, energies, family labels and counts bit-exact; ln Q and A within
   1e-10.
-* At L = 10 and R = 2 10^4 the drawn energies pass a chi-square test against
-  the exact distribution at every checked temperature.
+* At L = 10 and 16 with R = 2 10^4 the drawn energies pass a chi-square test
+  against the exact distribution at every checked temperature; at L = 16 the
+  run of Fig. 9 (R = 2 10^4, beta up to 0.44) is stepwise bit-exact against
+  the oracle.
 * theta = infinity runs batched with Metropolis runs give each run's own
   oracle records, also beside runs that all share one other lattice size.
 """
@@ -71,10 +73,13 @@ def test_library_dos():
 
 @pytest.mark.parametrize("repr_", REPRS)
 @pytest.mark.parametrize("resampling", [W.NEAREST_INT, W.MULTINOMIAL])
-def test_stepwise_parity(repr_, resampling):
-    say(f"theta = infinity stepwise {repr_} resampling={resampling}")
-    d = W.run_desc(8, W.FM, seed=W.RUN_SEED_BASE + 0x6100 + resampling, R=700, theta=W.THETA_EXACT, K=21,
-                   beta_f=1.0, resampling=resampling)
+@pytest.mark.parametrize("L,R,K,beta_f", [(8, 700, 21, 1.0), (16, 20000, 89, 0.44)])
+def test_stepwise_parity(repr_, resampling, L, R, K, beta_f):
+    """Step by step against the oracle; L = 16 at R = 2e4 up to beta = 0.44
+    in steps of 0.005 is the setting of Fig. 9."""
+    say(f"theta = infinity stepwise {repr_} resampling={resampling} L={L} R={R}")
+    d = W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x6100 + resampling + L, R=R, theta=W.THETA_EXACT, K=K,
+                   beta_f=beta_f, resampling=resampling)
     orc = oracle.OracleRun(d)
     ctx = pa.Context([d], repr_)
     assert_obs_equal(ctx.obs()[0, 0, 0], orc.obs()[0, 0], "i=0")
@@ -82,7 +87,7 @@ def test_stepwise_parity(repr_, resampling):
         orc.step(i)
         ctx.step(i)
         assert_obs_equal(ctx.obs()[0, 0, i], orc.obs()[0, i], f"i={i}")
-        if i % 5 == 0 or i == d["K"] - 1:
+        if i % 5 == 0 or i == d["K"] - 1 or L == 16 and i % 11 == 0:
             _, Eo, fo, _ = orc.state(0)
             _, Eg, fg, rg = ctx.state(0, 0)
             assert np.array_equal(Eg, Eo) and np.array_equal(fg, fo), f"i={i}"
@@ -90,12 +95,13 @@ def test_stepwise_parity(repr_, resampling):
     ctx.close()
 
 
-def test_full_size_L10_energy_law():
+@pytest.mark.parametrize("L", [10, 16])
+def test_full_size_energy_law(L):
     from scipy import stats
-    L, R = 10, 20000
+    R = 20000
     N = L * L
-    d = W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x6200, R=R, theta=W.THETA_EXACT, K=31, beta_f=0.6)
-    say("theta = infinity L=10 R=2e4 energy law")
+    d = W.run_desc(L, W.FM, seed=W.RUN_SEED_BASE + 0x6200 + L, R=R, theta=W.THETA_EXACT, K=31, beta_f=0.6)
+    say(f"theta = infinity L={L} R=2e4 energy law")
     g = np.array([float(x) for x in pa.pa_exact_dos(L)])
     Es = np.array([-2 * N + 4 * m for m in range(N + 1)])
     ctx = pa.Context([d], "msc")
