@@ -784,15 +784,22 @@ def headline(desc, steps, warmup, args, only):
         p = run_plain(desc, timed, warmup, b["obs"][0, 0])
         N = desc["L"] ** 2
         plain_sweep_avg = sum(p["sweep_ms"]) / len(p["sweep_ms"]) / 1e3 / (2 * desc["theta"])
-        # algorithmic bytes per int8 colour launch: read every site of the
-        # run once (both colours, 1 byte per spin), write the updated colour
-        bytes_launch = 1.5 * N * desc["R"]
+        # algorithmic bytes per int8 colour launch: 2 bytes per attempted
+        # flip (read and write the updated spin), N / 2 sites of R replicas
+        bytes_launch = 2.0 * (N // 2) * desc["R"]
+        # what any one-colour launch must move at least: every spin byte of
+        # the run (the colour and its neighbours), then the updated colour
+        floor_launch = 1.5 * N * desc["R"]
+        traffic_int8 = measured_traffic("k_sweep_int8", 1)
         line["plain_int8"] = {
             "flips_per_ns": round(b["flips"] / p["wall_s"] / 1e9, 3),
             "ms_per_step": round(p["wall_s"] * 1e3 / steps, 4),
             "sweep_launch_avg_ms": round(plain_sweep_avg * 1e3, 4),
             "sweep_hbm_GBps": round(bytes_launch / plain_sweep_avg / 1e9, 1),
             "sweep_hbm_frac": round(bytes_launch / plain_sweep_avg / 1e9 / HBM_PEAK_GBS, 4),
+            "one_colour_floor_GBps": round(floor_launch / plain_sweep_avg / 1e9, 1),
+            "traffic": traffic_int8,
+            "traffic_GBps": (round(traffic_int8 / plain_sweep_avg / 1e9, 1) if traffic_int8 else None),
             # the same Philox and site-update work as the batched sweep, per
             # colour launch, against the integer-VALU peak
             "sweep_alu_frac": round((OPS_PER_CALL * p["calls"] + OPS_PER_WORD * p["words"])
