@@ -309,17 +309,8 @@ __global__ void k_init_spins(const Item *items, const RunInfo *runs)
         if (REPR == PA_MSC64) {
             ((uint64_t *)R.spins[it.pop][0])[site] = plane;
         } else {
-            uint4 v[4];
-            const uint32_t lo = (uint32_t)plane, hi = (uint32_t)(plane >> 32);
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t bits = (q < 2 ? lo : hi) >> (16 * (q & 1));
-                v[q].x = 0x01010101u ^ negmask4(bits & 15u);
-                v[q].y = 0x01010101u ^ negmask4((bits >> 4) & 15u);
-                v[q].z = 0x01010101u ^ negmask4((bits >> 8) & 15u);
-                v[q].w = 0x01010101u ^ negmask4((bits >> 12) & 15u);
-            }
             uint4 *dst = (uint4 *)(R.spins[it.pop][0] + site * 64);
-            for (int q = 0; q < 4; ++q) dst[q] = v[q];
+            for (int q = 0; q < 4; ++q) dst[q] = spins16((uint32_t)(plane >> (16 * q)) & 0xFFFFu);
         }
     }
 }
@@ -864,12 +855,20 @@ __device__ __forceinline__ uint64_t jmask(uint8_t b, int bit) { return ((b >> bi
 // chunks that change are rebuilt from their signs and stored.
 constexpr int I8_CMAX = 12;   // 16-byte chunks held per thread
 
-__device__ __forceinline__ uint32_t signs16(const uint4 &v)
+// Rows per workgroup of the plain sweep: the whole lattice if its chunks fit
+// in `threads` threads' registers, else the largest divisor T of L whose
+// T + 2 rows (with halos) fit.
+constexpr int int8_rows_for(int L, int threads)
 {
-    return signs4(v.x) | (signs4(v.y) << 4) | (signs4(v.z) << 8) | (signs4(v.w) << 12);
+    const int cap = threads * I8_CMAX;
+    if (L * L * 4 <= cap) return L;
+    int best = 1;
+    for (int T = 1; T < L; ++T)
+        if (L % T == 0 && (T + 2) * L * 4 <= cap) best = T;
+    return best;
 }
 
-template <int LT>
+template <int LT, int THREADS>
 __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState &S, int pop, int g, int tile,
                                                 int s, int colour, int T, uint64_t *sm, unsigned long long *stats)
 {
@@ -880,7 +879,8 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
     const int rows = min(T, L - y0);
     const int halo = rows == L ? 0 : 1;
     const int nrow = rows + 2 * halo;
-    const int nthr = blockDim.x, tid = threadIdx.x;
+    constexpr int nthr = THREADS;
+    const int tid = threadIdx.x;
     uint64_t *packed = sm;                              // [nrow][L]
     uint64_t *fm = sm + (size_t)nrow * L;               // [rows][half]
     uint16_t *pk16 = (uint16_t *)packed;
@@ -899,9 +899,18 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
         y = y < 0 ? y + L : (y >= L ? y - L : y);
         return (uint32_t)(y * L + x) * 64u + (uint32_t)part * 16u;
     };
+    // Every load is issued before the first use, with no branch around any
+    // of them (a branch would make each load wait for its registers at the
+    // join): lanes past the last chunk load that chunk again, in bounds.  For
+    // a lattice size known here the tile and so the number of loads per
+    // thread are compile-time constants.
+    constexpr int QN = LT ? (((LT == int8_rows_for(LT, THREADS) ? LT : int8_rows_for(LT, THREADS) + 2) * LT * 4 +
+                              THREADS - 1) / THREADS)
+                          : I8_CMAX;
+    static_assert(QN <= I8_CMAX, "tile chunks exceed the registers held per thread");
 #pragma unroll
-    for (int q = 0; q < I8_CMAX; ++q)
-        if (tid + q * nthr < chunks) reg[q] = *(const uint4 *)(base + off_of(tid + q * nthr));
+    for (int q = 0; q < QN; ++q)
+        reg[q] = *(const uint4 *)(base + off_of(min(tid + q * nthr, chunks - 1)));
 #pragma unroll
     for (int q = 0; q < I8_CMAX; ++q) {
         const int c = tid + q * nthr;
@@ -942,11 +951,7 @@ __device__ __forceinline__ void sweep_int8_tile(const RunInfo &R, const PopState
             const int y = y0 + yy;
             const int x = 2 * m + ((y + colour) & 1);
             const uint32_t b = f ^ (uint32_t)pk16[((yy + halo) * L + x) * 4 + part];
-            uint4 v;
-            v.x = 0x01010101u ^ negmask4(b & 15u);
-            v.y = 0x01010101u ^ negmask4((b >> 4) & 15u);
-            v.z = 0x01010101u ^ negmask4((b >> 8) & 15u);
-            v.w = 0x01010101u ^ negmask4((b >> 12) & 15u);
+            const uint4 v = spins16(b);
             *(uint4 *)(base + (uint32_t)(y * L + x) * 64u + (uint32_t)part * 16u) = v;
         }
     }
@@ -968,13 +973,13 @@ __global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, con
     const int g = blockIdx.x / ntiles, tile = blockIdx.x - g * ntiles;
     if (g * 64 >= S.Rcur) return;
     switch (R.L) {
-    case 8: sweep_int8_tile<8>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
-    case 16: sweep_int8_tile<16>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
-    case 24: sweep_int8_tile<24>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
-    case 32: sweep_int8_tile<32>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
-    case 48: sweep_int8_tile<48>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
-    case 64: sweep_int8_tile<64>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
-    default: sweep_int8_tile<0>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 8: sweep_int8_tile<8, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 16: sweep_int8_tile<16, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 24: sweep_int8_tile<24, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 32: sweep_int8_tile<32, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 48: sweep_int8_tile<48, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    case 64: sweep_int8_tile<64, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
+    default: sweep_int8_tile<0, THREADS>(R, S, pop, g, tile, s, colour, T, sm, stats); break;
     }
 }
 
@@ -2714,17 +2719,7 @@ hipError_t launch_resample(const LaunchCtx &c)
 // a very large lattice would not fit in 256 threads' chunks.
 int int8_threads(int L) { return 3 * L * 4 <= 256 * I8_CMAX ? 256 : 1024; }
 
-// Rows per workgroup: the whole lattice if its chunks fit, else the largest
-// divisor T of L whose T + 2 rows (with halos) fit.
-int int8_tile_rows(int L)
-{
-    const int cap = int8_threads(L) * I8_CMAX;
-    if (L * L * 4 <= cap) return L;
-    int best = 1;
-    for (int T = 1; T < L; ++T)
-        if (L % T == 0 && (T + 2) * L * 4 <= cap) best = T;
-    return best;
-}
+int int8_tile_rows(int L) { return int8_rows_for(L, int8_threads(L)); }
 
 hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_cap, int npop, int theta)
 {

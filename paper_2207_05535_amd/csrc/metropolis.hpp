@@ -158,48 +158,44 @@ __device__ __forceinline__ Thresholds thresholds_of(const uint64_t *tabT, int i)
     return T;
 }
 
-// Sign bits of 64 int8 spins (+1 = 0x01, -1 = 0xFF) packed into one word:
-// bit b = 1 iff byte b is negative.
-__device__ __forceinline__ uint32_t signs4(uint32_t d)
+// Sign bits of 16 int8 spins (+1 = 0x01, -1 = 0xFF; four bytes per 32-bit
+// lane of v, byte k of v.x first): bit k = 1 iff byte k is negative.  Each
+// byte's bit 7 is isolated (0x80 or 0) and weighted by a power of two in an
+// unsigned 4-byte dot product, so two dwords give 128 x (their 8 bits).
+__device__ __forceinline__ uint32_t signs16(const uint4 &v)
 {
-    return ((d >> 7) & 1u) | ((d >> 14) & 2u) | ((d >> 21) & 4u) | ((d >> 28) & 8u);
+    uint32_t lo = __builtin_amdgcn_udot4(v.x & 0x80808080u, 0x08040201u, 0u, false);
+    lo = __builtin_amdgcn_udot4(v.y & 0x80808080u, 0x80402010u, lo, false);
+    uint32_t hi = __builtin_amdgcn_udot4(v.z & 0x80808080u, 0x08040201u, 0u, false);
+    hi = __builtin_amdgcn_udot4(v.w & 0x80808080u, 0x80402010u, hi, false);
+    return (lo >> 7) | ((hi >> 7) << 8);
 }
 
 __device__ __forceinline__ uint64_t pack64(const uint4 v[4])
 {
-    uint32_t lo = 0, hi = 0;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        lo |= signs4(v[q].x) << (16 * q) | signs4(v[q].y) << (16 * q + 4) |
-              signs4(v[q].z) << (16 * q + 8) | signs4(v[q].w) << (16 * q + 12);
-        hi |= signs4(v[q + 2].x) << (16 * q) | signs4(v[q + 2].y) << (16 * q + 4) |
-              signs4(v[q + 2].z) << (16 * q + 8) | signs4(v[q + 2].w) << (16 * q + 12);
-    }
-    return (uint64_t)lo | ((uint64_t)hi << 32);
+    return (uint64_t)(signs16(v[0]) | (signs16(v[1]) << 16)) |
+           ((uint64_t)(signs16(v[2]) | (signs16(v[3]) << 16)) << 32);
 }
 
-// XOR mask that negates the bytes whose bit is set in the 4-bit group f4:
-// 0x01 <-> 0xFF is an XOR with 0xFE.
-__device__ __forceinline__ uint32_t negmask4(uint32_t f4)
+// Four canonical spin bytes from 4 sign bits f4 (bit k set: byte k = 0xFF,
+// else 0x01).  The multiply by 2^0 + 2^7 + 2^14 + 2^21 moves bit k to bit 8k
+// among terms at pairwise distinct positions (no carries); each selected bit
+// then becomes 0xFE + 0x01 in its byte.
+__device__ __forceinline__ uint32_t spins4(uint32_t f4)
 {
-    const uint32_t e = (f4 & 1u) | ((f4 & 2u) << 7) | ((f4 & 4u) << 14) | ((f4 & 8u) << 21);
-    return (e << 8) - (e << 1);
+    const uint32_t e = (f4 * 0x00204081u) & 0x01010101u;
+    return e * 0xFEu + 0x01010101u;
 }
 
-__device__ __forceinline__ void apply64(uint4 v[4], uint64_t F)
+// 16 canonical spin bytes from 16 sign bits (the inverse of signs16).
+__device__ __forceinline__ uint4 spins16(uint32_t b)
 {
-    const uint32_t lo = (uint32_t)F, hi = (uint32_t)(F >> 32);
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        v[q].x ^= negmask4((lo >> (16 * q)) & 15u);
-        v[q].y ^= negmask4((lo >> (16 * q + 4)) & 15u);
-        v[q].z ^= negmask4((lo >> (16 * q + 8)) & 15u);
-        v[q].w ^= negmask4((lo >> (16 * q + 12)) & 15u);
-        v[q + 2].x ^= negmask4((hi >> (16 * q)) & 15u);
-        v[q + 2].y ^= negmask4((hi >> (16 * q + 4)) & 15u);
-        v[q + 2].z ^= negmask4((hi >> (16 * q + 8)) & 15u);
-        v[q + 2].w ^= negmask4((hi >> (16 * q + 12)) & 15u);
-    }
+    uint4 v;
+    v.x = spins4(b & 15u);
+    v.y = spins4((b >> 4) & 15u);
+    v.z = spins4((b >> 8) & 15u);
+    v.w = spins4((b >> 12) & 15u);
+    return v;
 }
 
 }  // namespace pa
