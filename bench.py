@@ -214,7 +214,7 @@ def time_batched(descs, steps, warmup, tune_mode, M=None, per_kernel=True, block
                 for r in range(len(descs)) for p in range(obs_graph.shape[1])
                 if p == 0 or descs[r]["overlap"] == pa.PA_Q_TWO_POP for i in timed)
     res = dict(wall_s=wall, dev_s=dev, flips=flips, wavg=wavg, timed=timed, blocks=blocks,
-               tuning=ctx.tuning(L0), tuned=tuned, obs=obs_graph)
+               tuning=dict(ctx.tuning(L0), chunks=ctx.sweep_chunks()), tuned=tuned, obs=obs_graph)
     if per_kernel:
         log("batched path: per-kernel timing pass")
         sweep_ms, step_ms = [], []

@@ -310,6 +310,26 @@ pa_status pa_set_tuning(pa_ctx *ctx, int32_t L, int32_t threads, int32_t groups_
  * the same largest-first order).  Results never depend on it. */
 pa_status pa_set_persistent(pa_ctx *ctx, int32_t on);
 
+/* Sweep chunks on the persistent grid: chunks = K > 1 splits every item of
+ * the batched sweep into K items of consecutive sweeps (chunk c takes sweeps
+ * c theta / K .. (c + 1) theta / K - 1 of its replica groups), listed all
+ * first chunks first; a chunk waits on the device until the previous chunk
+ * of its groups has stored their lattices.  With every item taking about the
+ * same time, a launch of n items on S resident workgroups lasts about
+ * ceil(n / S) item times; chunks bring that down to ceil(n K / S) / K at the
+ * cost of loading and storing each lattice K - 1 more times, which for
+ * small items can outweigh the gain.  1 <= chunks <= 4 fixes K (default 1;
+ * pa_autotune searches it); chunks = 0 chooses K per plan from the estimate
+ * above.  Chunks apply only where the persistent grid is used
+ * (pa_set_persistent, and more items than resident workgroups).  Results
+ * never depend on it.  PA_ERR_ARG outside 0..4, PA_ERR_STATE between the
+ * calls of a temperature step. */
+pa_status pa_set_sweep_chunks(pa_ctx *ctx, int32_t chunks);
+
+/* Chunks per item of the current sweep plan (host *out: 1 when items are
+ * whole). */
+pa_status pa_get_sweep_chunks(pa_ctx *ctx, int32_t *out);
+
 /* Sparse rounds of the batched sweep: on = 1 pools the sites still
  * undecided after the lockstep calls into one list per workgroup, so the
  * compacted rounds run on full wavefronts; on = 0 keeps one list per
@@ -327,7 +347,8 @@ pa_status pa_get_tuning(pa_ctx *ctx, int32_t L, int32_t *threads, int32_t *group
  * to the remaining schedule) real temperature steps of this context for
  * each candidate launch shape, timing the sweep launches with HIP events:
  * first threads x dense_calls x persistent x pooled with the current groups per L,
- * then groups per workgroup one L at a time (heaviest L first).  Every
+ * then groups per workgroup one L at a time (heaviest L first), then, with a
+ * persistent grid, 2..4 chunks of sweeps per item.  Every
  * candidate's records and exact work counters must hash to the starting
  * shape's value; one that differs is rejected (counted in *n_rejected, which
  * is 0 unless a kernel is wrong).  The fastest accepted shape is applied and
@@ -345,7 +366,9 @@ pa_status pa_autotune(pa_ctx *ctx, int32_t steps, const char *cache_path, int32_
 /* Exact work counters of the sweep kernels since pa_create: host_out[3] =
  * {site updates of 64-replica words, Philox4x32-10 calls, attempted
  * single-spin flips}.  Used to express sweep throughput against the
- * integer-ALU roofline. */
+ * integer-ALU roofline.  Returns PA_ERR_STATE (counters still written) if a
+ * sweep chunk ever gave up waiting for the chunk before it (see
+ * pa_set_sweep_chunks): the steps since then are not to be trusted. */
 pa_status pa_read_stats(pa_ctx *ctx, uint64_t *host_out);
 
 /* ------------------------------------------------------------------ serving

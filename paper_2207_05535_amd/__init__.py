@@ -96,6 +96,8 @@ def lib():
             "pa_set_persistent": [vp, i32],
             "pa_get_tuning": [vp, i32, vp, vp, vp, vp, vp],
             "pa_set_pooled": [vp, i32],
+            "pa_set_sweep_chunks": [vp, i32],
+            "pa_get_sweep_chunks": [vp, vp],
             "pa_autotune": [vp, i32, C.c_char_p, vp, vp],
             "pa_read_stats": [vp, vp],
             "pa_destroy": [vp],
@@ -283,6 +285,16 @@ def pa_set_persistent(h, on):
 
 def pa_set_pooled(h, on):
     _chk("pa_set_pooled", lib().pa_set_pooled(h, int(on)), h)
+
+
+def pa_set_sweep_chunks(h, chunks):
+    _chk("pa_set_sweep_chunks", lib().pa_set_sweep_chunks(h, int(chunks)), h)
+
+
+def pa_get_sweep_chunks(h):
+    v = C.c_int32(0)
+    _chk("pa_get_sweep_chunks", lib().pa_get_sweep_chunks(h, C.byref(v)), h)
+    return v.value
 
 
 def pa_get_tuning(h, L):
@@ -493,6 +505,14 @@ class Context:
 
     def set_pooled(self, on):
         pa_set_pooled(self.h, on)
+
+    def set_sweep_chunks(self, chunks):
+        """Chunks of sweeps per item on the persistent grid (0: chosen per plan)."""
+        pa_set_sweep_chunks(self.h, chunks)
+
+    def sweep_chunks(self):
+        """Chunks per item of the current sweep plan (1: whole items)."""
+        return pa_get_sweep_chunks(self.h)
 
     def tuning(self, L):
         return pa_get_tuning(self.h, L)

@@ -46,7 +46,8 @@ struct TableOff {
 struct Layout {
     std::vector<RunOff> runs;
     std::vector<TableOff> tables;
-    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items, queue, meas_items;
+    size_t runinfo, popstate, items, chunk_items, obs, dseed, logw, wavg, stats, sweep_items, queue, meas_items,
+        sweep_flags;
     size_t qw, famst, wq;   // overlap weights, family statistics, weighted overlap distributions
     int n_items, n_chunk_items, n_meas_items, npop_ctx, Kmax, maxN;
     size_t total;
@@ -107,6 +108,7 @@ struct pa_ctx {
     int sweep_dense = 3;                // Philox calls every site makes in lockstep
     bool sweep_persistent = false;      // persistent grid with a ticket queue
     bool sweep_pooled = false;          // sparse rounds over one list per workgroup
+    int sweep_chunks = 1;               // chunks of sweeps per item on the persistent grid, 0: chosen per plan
     std::map<int, int> groups_per_wg;   // L -> replica groups per workgroup of the batched sweep
     bool any_multinomial = false;
     bool any_wang = false;

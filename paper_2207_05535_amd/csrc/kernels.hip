@@ -1232,6 +1232,10 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int group0 = __builtin_amdgcn_readfirstlane(item.group0);
     const int pop = __builtin_amdgcn_readfirstlane(item.pop);
     const int theta = __builtin_amdgcn_readfirstlane(R.theta);
+    // this item's sweeps (a chunk of them, or all theta)
+    const int nchunk = max(1, __builtin_amdgcn_readfirstlane(item.nchunk));
+    const int chunk = __builtin_amdgcn_readfirstlane(item.chunk);
+    const int s_begin = chunk * theta / nchunk, s_end = (chunk + 1) * theta / nchunk;
     const uint32_t key0 = __builtin_amdgcn_readfirstlane(R.key0), key1 = __builtin_amdgcn_readfirstlane(R.key1);
     const int G = min(__builtin_amdgcn_readfirstlane(item.ngroups), (Rc + 63) / 64 - group0);
     if (G <= 0) return;
@@ -1281,7 +1285,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const uint64_t lt_mask = __lanemask_lt();
     uint32_t wcalls = 0;   // Philox calls of this wavefront (uniform)
     if (tid == 0) ctl[0] = ctl[1] = 0;
-    for (int s = 0; s < theta; ++s) {
+    for (int s = s_begin; s < s_end; ++s) {
         const uint32_t c3 = c3p | (uint32_t)s;
         for (int colour = 0; colour < 2; ++colour) {
             const int h = 2 * s + colour;   // half-sweep index: its list count is ctl[h & 1]
@@ -1407,13 +1411,14 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
         base[u] = lat[(size_t)gs * N + ((x + y) & 1) * nh + y * half + (x >> 1)];
     }
     // word-site updates and attempted flips of this wavefront's range, in
-    // closed form: theta sweeps x 2 colours x its units, 64 replicas each
-    // except the valid ones of the last group
+    // closed form: the item's sweeps x 2 colours x its units, 64 replicas
+    // each except the valid ones of the last group
     const int mine = max(ue - ub, 0);
     const int nlast = max(ue - max(ub, (G - 1) * nh), 0);   // its units in the last group
-    const uint64_t nwords = (uint64_t)theta * 2u * (uint64_t)mine;
+    const uint64_t nsw = (uint64_t)(s_end - s_begin);
+    const uint64_t nwords = nsw * 2u * (uint64_t)mine;
     const uint64_t nflips =
-        (uint64_t)theta * 2u * ((uint64_t)(mine - nlast) * 64u + (uint64_t)nlast * (uint64_t)__popcll(vlast));
+        nsw * 2u * ((uint64_t)(mine - nlast) * 64u + (uint64_t)nlast * (uint64_t)__popcll(vlast));
     flush_stats(stats, lane == 0 ? nwords : 0ull, lane == 0 ? wcalls : 0u, lane == 0 ? nflips : 0ull);
 }
 
@@ -1457,30 +1462,74 @@ __device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *ru
 // the next ticket, queue[1] counts workgroups that found the list empty; the
 // last of them resets both, so the next launch (or graph replay) starts
 // from zero without a separate clear.
+//
+// Sweep chunks (persistent grid only): an item may cover a part of its
+// groups' theta sweeps.  The list holds every first chunk before any second
+// one, and so on, so the chunk an item depends on was taken from the queue
+// earlier, by a workgroup that is running or done.  When a chunk has stored
+// its lattices, its workgroup publishes (launch generation << 4 | chunk + 1)
+// in the groups' flag slot; the next chunk waits for that value before it
+// loads them.  queue[2] is the launch generation: every workgroup reads it
+// before taking a ticket, and the last one to leave increments it, so
+// values left by earlier launches or graph replays never match.  The wait
+// ends because the producer holds an earlier ticket; it is bounded all the
+// same, and a wait that runs out is counted in the stall counter (the
+// results of that step are then not trustworthy, and reading the work
+// counters reports it).
+constexpr unsigned int SWEEP_WAIT_SPINS = 1u << 22;
+
 template <int LS, bool EA>
 __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int n_items, const RunInfo *runs,
                                                     const PopState *st, int dense, unsigned long long *stats,
-                                                    unsigned int *queue)
+                                                    unsigned int *queue, unsigned int *flags)
 {
     extern __shared__ uint64_t lds[];
     if (queue == nullptr) {
         sweep_one<LS, EA>(items[blockIdx.x], runs, st, lds, dense, stats);
         return;
     }
-    __shared__ unsigned int ticket;
+    __shared__ unsigned int ticket, gen;
+    if (threadIdx.x == 0) gen = __hip_atomic_load(&queue[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) ticket = atomicAdd(&queue[0], 1u);
         __syncthreads();
         const unsigned int t = ticket;
         if (t >= (unsigned int)n_items) break;
-        sweep_one<LS, EA>(items[t], runs, st, lds, dense, stats);
+        const SweepItem it = items[t];
+        if (it.chunk > 0) {
+            if (threadIdx.x == 0) {
+                const unsigned int want = (gen << 4) | (unsigned int)it.chunk;
+                unsigned int spins = 0;
+                while (__hip_atomic_load(&flags[it.base], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != want) {
+                    if (++spins == SWEEP_WAIT_SPINS) {
+                        atomicAdd(&stats[ST_STALL], 1ull);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            __syncthreads();
+        }
+        sweep_one<LS, EA>(it, runs, st, lds, dense, stats);
+        if (it.chunk + 1 < it.nchunk) {
+            // every wavefront waits for its own lattice stores (a barrier
+            // alone does not), so that the release by the first thread,
+            // which writes this XCD's L2 back, covers all of them
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&flags[it.base], (gen << 4) | (unsigned int)(it.chunk + 1), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     if (threadIdx.x == 0) {
         __threadfence();
         if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
             atomicExch(&queue[0], 0u);
             atomicExch(&queue[1], 0u);
+            atomicAdd(&queue[2], 1u);
         }
     }
 }
@@ -2751,7 +2800,7 @@ size_t msc_lds_bytes(int N, int groups)
 // The sweep kernel for a launch: one compiled for a single (L, model) when
 // every run of the context has it, else the one that dispatches per item.
 using SweepKernel = void (*)(const SweepItem *, int, const RunInfo *, const PopState *, int, unsigned long long *,
-                             unsigned int *);
+                             unsigned int *, unsigned int *);
 
 SweepKernel msc_kernel(int L, int ea)
 {
@@ -2800,10 +2849,13 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
         const SweepClass &q = c.sweep_cls[k];
         if (q.count == 0) continue;
         const bool persistent = q.grid > 0 && q.grid < q.count;
+        // chunked items wait on one another, which only the ticket order of
+        // the persistent grid makes safe
+        if (q.nchunk > 1 && !persistent) return hipErrorInvalidConfiguration;
         const int grid = persistent ? q.grid : q.count;
         msc_kernel(q.L, q.ea)<<<grid, c.sweep_threads, q.lds, c.stream>>>(
             c.sweep_items + q.first, q.count, c.runs, c.st, c.sweep_dense | (c.sweep_pooled << 8), c.stats,
-            persistent ? c.sweep_queue : nullptr);
+            persistent ? c.sweep_queue : nullptr, c.sweep_flags);
         PA_CHECK_LAUNCH();
     }
     return hipSuccess;
@@ -2838,6 +2890,45 @@ int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, 
         C.lds = std::max(C.lds, msc_lds_bytes(L * L, it.ngroups));
     }
     return 1;
+}
+
+int sweep_chunks_auto(int n, int slots)
+{
+    // makespan in units of one whole item when every item takes the same
+    // time: ceil(n K / slots) rounds of 1/K each, plus a small cost per
+    // extra chunk for loading and storing the lattices once more
+    if (slots <= 0 || n <= slots) return 1;
+    int best = 1;
+    double best_t = 1e300;
+    for (int K = 1; K <= MAX_SWEEP_CHUNKS; ++K) {
+        const double t = (double)((n * (long)K + slots - 1) / slots) / K + 0.03 * (K - 1);
+        if (t < best_t - 1e-9) {
+            best_t = t;
+            best = K;
+        }
+    }
+    return best;
+}
+
+int expand_sweep_chunks(std::vector<SweepItem> &items, SweepClass &cls, int K)
+{
+    cls.nchunk = 1;
+    if (K <= 1 || cls.count == 0) return 0;
+    if (K > MAX_SWEEP_CHUNKS || cls.first != 0 || cls.count != (int)items.size()) return -1;
+    const int n = cls.count;
+    std::vector<SweepItem> out((size_t)n * K);
+    for (int c = 0; c < K; ++c)
+        for (int b = 0; b < n; ++b) {
+            SweepItem it = items[b];
+            it.chunk = c;
+            it.nchunk = K;
+            it.base = b;
+            out[(size_t)c * n + b] = it;
+        }
+    items.swap(out);
+    cls.count = n * K;
+    cls.nchunk = K;
+    return 0;
 }
 
 bool sweep_class_grids(SweepClass *cls, int n, int threads, bool persistent)

@@ -17,6 +17,7 @@ struct SweepClass {
     int L, ea;
     int grid;           // > 0: persistent grid of this many workgroups
     size_t lds;
+    int nchunk = 1;     // > 1: items split into this many chunks of sweeps (persistent grid only)
 };
 constexpr int MAX_SWEEP_CLASSES = 16;
 
@@ -43,7 +44,8 @@ struct LaunchCtx {
     int sweep_pooled;              // 1: sparse rounds over one list per workgroup
     int n_sweep_classes = 0;       // launches of the batched sweep, one per class
     SweepClass sweep_cls[MAX_SWEEP_CLASSES];
-    unsigned int *sweep_queue;     // device [2] ticket counters of the persistent grid
+    unsigned int *sweep_queue;     // device [4]: ticket counters of the persistent grid, launch generation
+    unsigned int *sweep_flags = nullptr;   // device [n_items]: completed sweep chunk of each item's groups
     hipStream_t stream;
 };
 
@@ -76,6 +78,13 @@ int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, 
                   SweepClass *cls);
 // Persistent grids of the classes (threads per workgroup as launched).
 bool sweep_class_grids(SweepClass *cls, int n, int threads, bool persistent);
+// Chunks of sweeps per item for a persistent launch of n items on `slots`
+// resident workgroups: 1 when every item gets a workgroup at once, else the
+// count that least quantises the launch into rounds.
+int sweep_chunks_auto(int n, int slots);
+// Replaces the (single) class's items by K chunks of each, all first chunks
+// first; 0 on success, -1 if the class does not cover the whole list.
+int expand_sweep_chunks(std::vector<SweepItem> &items, SweepClass &cls, int K);
 hipError_t prepare_wang_lds(size_t bytes);
 hipError_t launch_philox_rate(int calls, hipStream_t s, int *blocks, int *threads);
 

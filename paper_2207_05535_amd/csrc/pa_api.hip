@@ -166,7 +166,7 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     Lo.popstate = P.take(sizeof(PopState) * n_runs * MAX_POP);
     Lo.dseed = P.take(sizeof(uint64_t) * n_runs);
     Lo.stats = P.take(STAT_BYTES);
-    Lo.queue = P.take(sizeof(uint32_t) * 2);
+    Lo.queue = P.take(sizeof(uint32_t) * 4);
     Lo.n_items = 0;
     Lo.n_chunk_items = 0;
     Lo.n_meas_items = 0;
@@ -178,7 +178,11 @@ Layout plan(const pa_run_desc *runs, int n_runs, pa_repr repr)
     }
     Lo.items = P.take(sizeof(Item) * Lo.n_items);
     Lo.meas_items = P.take(sizeof(SweepItem) * Lo.n_meas_items);
-    Lo.sweep_items = P.take(sizeof(SweepItem) * Lo.n_items);
+    // the batched sweep's list: up to MAX_SWEEP_CHUNKS chunks of every item,
+    // and one completion flag per item
+    const size_t chunks_max = repr == PA_MSC64 ? MAX_SWEEP_CHUNKS : 1;
+    Lo.sweep_items = P.take(sizeof(SweepItem) * Lo.n_items * chunks_max);
+    Lo.sweep_flags = P.take(sizeof(uint32_t) * (repr == PA_MSC64 ? Lo.n_items : 1));
     Lo.chunk_items = P.take(sizeof(ChunkItem) * Lo.n_chunk_items);
     Lo.obs = P.take(sizeof(pa_obs) * (size_t)Lo.Kmax * n_runs * Lo.npop_ctx);
     Lo.logw = P.take(sizeof(double) * (size_t)Lo.Kmax * n_runs);
@@ -635,12 +639,17 @@ pa_status upload_sweep_plan(pa_ctx *c)
     const int ncls = sweep_classes(items, run_L, run_ea, cls);
     if (ncls < 0) return PA_ERR_ARG;
     if (prepare_msc_lds(lds) != hipSuccess) return dev_fail(c);
+    if (!sweep_class_grids(cls, ncls, c->sweep_threads, c->sweep_persistent)) return dev_fail(c);
+    if (ncls == 1 && cls[0].grid > 0 && cls[0].grid < cls[0].count) {
+        const int K = c->sweep_chunks > 0 ? c->sweep_chunks : sweep_chunks_auto(cls[0].count, cls[0].grid);
+        if (expand_sweep_chunks(items, cls[0], K) != 0) return PA_ERR_ARG;
+    }
     if (!items.empty())
         PA_HIP(c, hipMemcpyAsync(at<SweepItem>(c, c->lo.sweep_items), items.data(),
                                  sizeof(SweepItem) * items.size(), hipMemcpyHostToDevice, c->stream));
     PA_HIP(c, hipStreamSynchronize(c->stream));
-    if (!sweep_class_grids(cls, ncls, c->sweep_threads, c->sweep_persistent)) return dev_fail(c);
     c->lc.sweep_items = at<SweepItem>(c, c->lo.sweep_items);
+    c->lc.sweep_flags = at<unsigned int>(c, c->lo.sweep_flags);
     c->lc.n_sweep_items = (int)items.size();
     c->lc.sweep_threads = c->sweep_threads;
     c->lc.sweep_dense = c->sweep_dense;
@@ -678,7 +687,9 @@ pa_status read_stats(pa_ctx *c, uint64_t out[3])
         out[k] = 0;
         for (int q = 0; q < STAT_SLOTS; ++q) out[k] += slots[(size_t)q * NSTAT + k];
     }
-    return PA_OK;
+    uint64_t stalls = 0;
+    for (int q = 0; q < STAT_SLOTS; ++q) stalls += slots[(size_t)q * NSTAT + ST_STALL];
+    return stalls ? PA_ERR_STATE : PA_OK;
 }
 
 // A captured step graph holds the launch shapes it was captured with.
@@ -1254,6 +1265,26 @@ pa_status pa_set_persistent(pa_ctx *c, int32_t on)
     if (c->repr != PA_MSC64) return PA_OK;
     drop_graph(c);
     return upload_sweep_plan(c);
+}
+
+pa_status pa_set_sweep_chunks(pa_ctx *c, int32_t chunks)
+{
+    if (!c || chunks < 0 || chunks > MAX_SWEEP_CHUNKS) return PA_ERR_ARG;
+    if (c->failed) return PA_ERR_DEVICE;
+    if (c->phase != PH_MEASURED) return PA_ERR_STATE;
+    c->sweep_chunks = chunks;
+    if (c->repr != PA_MSC64) return PA_OK;
+    drop_graph(c);
+    return upload_sweep_plan(c);
+}
+
+pa_status pa_get_sweep_chunks(pa_ctx *c, int32_t *out)
+{
+    if (!c || !out) return PA_ERR_ARG;
+    int K = 1;
+    for (int k = 0; k < c->lc.n_sweep_classes; ++k) K = std::max(K, c->lc.sweep_cls[k].nchunk);
+    *out = K;
+    return PA_OK;
 }
 
 pa_status pa_set_pooled(pa_ctx *c, int32_t on)

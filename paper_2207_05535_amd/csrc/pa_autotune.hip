@@ -1,10 +1,11 @@
 // pa_autotune.hip -- launch-shape search for the batched sweep.
 //
-// The batched sweep has four knobs that change its speed and never its
-// results: threads per workgroup, replica groups per workgroup (per lattice
-// size L), Philox calls made in lockstep before the undecided sites are
-// compacted, and one-workgroup-per-item versus a persistent ticket-queue
-// grid.  The tuner runs a few real temperature steps of the caller's own
+// The batched sweep has knobs that change its speed and never its results:
+// threads per workgroup, replica groups per workgroup (per lattice size L),
+// Philox calls made in lockstep before the undecided sites are compacted,
+// one-workgroup-per-item versus a persistent ticket-queue grid, one list of
+// undecided sites per wavefront or per workgroup, and (persistent grid) the
+// chunks of sweeps each item is split into.  The tuner runs a few real temperature steps of the caller's own
 // context from a snapshot for each candidate, times the sweep launches with
 // HIP events, and keeps the fastest candidate whose records and exact work
 // counters hash to the same value as the starting shape's; a candidate with
@@ -30,7 +31,7 @@ using namespace pa;
 namespace {
 
 struct Shape {
-    int threads, dense, persistent, pooled;
+    int threads, dense, persistent, pooled, chunks;
     std::map<int, int> groups;   // L -> groups per workgroup
 };
 
@@ -38,6 +39,7 @@ struct CacheEntry {
     std::string arch, repr;
     int L, threads, groups, dense, persistent, pooled;
     double sweep_us;
+    int chunks;
 };
 
 std::string device_arch()
@@ -61,12 +63,14 @@ std::vector<CacheEntry> read_cache(const char *path)
         CacheEntry e;
         e.sweep_us = 0.0;
         e.pooled = 0;
+        e.chunks = 1;   // entries written before the chunk knob existed
         const int n = std::sscanf(line,
                                   " {\"arch\": \"%63[^\"]\", \"repr\": \"%15[^\"]\", \"L\": %d, \"threads\": %d, "
                                   "\"groups\": %d, \"dense\": %d, \"persistent\": %d, \"pooled\": %d, "
-                                  "\"sweep_us\": %lf",
+                                  "\"sweep_us\": %lf, \"chunks\": %d",
                                   arch, repr, &e.L, &e.threads, &e.groups, &e.dense, &e.persistent, &e.pooled,
-                                  &e.sweep_us);
+                                  &e.sweep_us, &e.chunks);
+        if (e.chunks < 1 || e.chunks > MAX_SWEEP_CHUNKS) e.chunks = 1;
         if (n >= 7) {
             e.arch = arch;
             e.repr = repr;
@@ -87,9 +91,9 @@ bool write_cache(const char *path, const std::vector<CacheEntry> &entries)
         const CacheEntry &e = entries[k];
         std::fprintf(f,
                      "  {\"arch\": \"%s\", \"repr\": \"%s\", \"L\": %d, \"threads\": %d, \"groups\": %d, "
-                     "\"dense\": %d, \"persistent\": %d, \"pooled\": %d, \"sweep_us\": %.3f}%s\n",
+                     "\"dense\": %d, \"persistent\": %d, \"pooled\": %d, \"sweep_us\": %.3f, \"chunks\": %d}%s\n",
                      e.arch.c_str(), e.repr.c_str(), e.L, e.threads, e.groups, e.dense, e.persistent, e.pooled,
-                     e.sweep_us, k + 1 < entries.size() ? "," : "");
+                     e.sweep_us, e.chunks, k + 1 < entries.size() ? "," : "");
     }
     std::fprintf(f, "]}\n");
     const bool ok = std::fclose(f) == 0;
@@ -109,13 +113,14 @@ uint64_t fnv1a(uint64_t h, const void *p, size_t n)
 // Applies a shape; false if it does not fit the device (nothing changed).
 bool apply_shape(pa_ctx *c, const Shape &s)
 {
-    const int t0 = c->sweep_threads, d0 = c->sweep_dense;
+    const int t0 = c->sweep_threads, d0 = c->sweep_dense, k0 = c->sweep_chunks;
     const bool p0 = c->sweep_persistent, q0 = c->sweep_pooled;
     const auto g0 = c->groups_per_wg;
     c->sweep_threads = s.threads;
     c->sweep_dense = s.dense;
     c->sweep_persistent = s.persistent != 0;
     c->sweep_pooled = s.pooled != 0;
+    c->sweep_chunks = s.chunks;
     for (const auto &kv : s.groups) c->groups_per_wg[kv.first] = kv.second;
     std::vector<SweepItem> probe;
     size_t lds = 0;
@@ -124,6 +129,7 @@ bool apply_shape(pa_ctx *c, const Shape &s)
         c->sweep_dense = d0;
         c->sweep_persistent = p0;
         c->sweep_pooled = q0;
+        c->sweep_chunks = k0;
         c->groups_per_wg = g0;
         return false;
     }
@@ -200,6 +206,7 @@ Shape current_shape(const pa_ctx *c, const std::vector<int> &Ls)
     s.dense = c->sweep_dense;
     s.persistent = c->sweep_persistent ? 1 : 0;
     s.pooled = c->sweep_pooled ? 1 : 0;
+    s.chunks = c->sweep_chunks;
     for (int L : Ls) s.groups[L] = groups_for(c, L);
     return s;
 }
@@ -260,6 +267,7 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
                         s.dense = e.dense;
                         s.persistent = e.persistent;
                         s.pooled = e.pooled;
+                        s.chunks = e.chunks;
                     }
                     break;
                 }
@@ -318,6 +326,7 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
                     s.dense = dense;
                     s.persistent = pers;
                     s.pooled = pool;
+                    s.chunks = 1;
                     if ((st = consider(s)) != PA_OK) return st;
                 }
     // groups per workgroup, one L at a time
@@ -336,6 +345,15 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
         }
     }
 
+    // chunks of sweeps on the persistent grid (they take effect only where
+    // the items outnumber the resident workgroups)
+    if (best.persistent)
+        for (int k = 2; k <= MAX_SWEEP_CHUNKS; ++k) {
+            Shape s = best;
+            s.chunks = k;
+            if ((st = consider(s)) != PA_OK) return st;
+        }
+
     // leave the context where it started, with the chosen shape
     (void)apply_shape(c, best);
     if ((st = T.restore()) != PA_OK) return st;
@@ -346,8 +364,8 @@ extern "C" pa_status pa_autotune(pa_ctx *c, int32_t steps, const char *cache_pat
 
     if (cache_path) {
         for (int L : Ls) {
-            CacheEntry e{arch, "msc", L, best.threads, best.groups[L], best.dense, best.persistent, best.pooled,
-                         1e3 * best_ms / steps};
+            CacheEntry e{arch,        "msc",           L, best.threads, best.groups[L], best.dense, best.persistent,
+                         best.pooled, 1e3 * best_ms / steps, best.chunks};
             bool replaced = false;
             for (auto &x : cache)
                 if (x.arch == arch && x.repr == "msc" && x.L == L) {

@@ -102,7 +102,7 @@ struct PopState {
 // They are striped over STAT_SLOTS slots of 64 bytes (NSTAT counters each)
 // so that concurrent wavefronts add to different cache lines; a reader sums
 // the slots.
-enum Stat { ST_WORDS = 0, ST_CALLS = 1, ST_FLIPS = 2, NSTAT = 8 };
+enum Stat { ST_WORDS = 0, ST_CALLS = 1, ST_FLIPS = 2, ST_STALL = 3, NSTAT = 8 };
 constexpr int STAT_SLOTS = 256;
 constexpr size_t STAT_BYTES = sizeof(uint64_t) * NSTAT * STAT_SLOTS;
 
@@ -112,7 +112,13 @@ struct Item {         // one replica group (64 replicas) of one (run, pop)
 
 struct SweepItem {    // groups [group0, group0 + ngroups) of one (run, pop), one workgroup
     int32_t run, pop, group0, ngroups;
+    // sweeps chunk * theta / nchunk .. (chunk + 1) * theta / nchunk - 1 of
+    // those groups (nchunk 0: all theta sweeps); chunk > 0 waits for the
+    // previous chunk of the same groups, whose completion is published in
+    // flag slot `base`
+    int32_t chunk, nchunk, base, pad;
 };
+constexpr int MAX_SWEEP_CHUNKS = 4;
 
 struct ChunkItem {    // one chunk of CH replicas of one (run, pop)
     int32_t run, pop, chunk, pad;

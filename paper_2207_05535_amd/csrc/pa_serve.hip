@@ -381,7 +381,7 @@ pa_status pa_server_create(pa_repr repr, void *dev_arena, size_t arena_bytes, in
     const size_t runinfo = P.take(sizeof(RunInfo) * max_slots);
     const size_t popstate = P.take(sizeof(PopState) * max_slots * MAX_POP);
     const size_t stats = P.take(STAT_BYTES);
-    const size_t queue = P.take(sizeof(uint32_t) * 2);
+    const size_t queue = P.take(sizeof(uint32_t) * 4);
     if (arena_bytes < P.off + 4096) return PA_ERR_NOMEM;
 
     pa_server *s = new pa_server();

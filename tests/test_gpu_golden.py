@@ -48,7 +48,8 @@ def golden():
 
 def apply_tuning_cache(ctx, L, path=TUNING):
     """Sets the cache entry's launch shape for L (threads, groups, lockstep
-    calls, persistent grid, pooled sparse rounds) and checks it took."""
+    calls, persistent grid, pooled sparse rounds, chunks of sweeps) and
+    checks it took."""
     with open(path) as fh:
         ent = [e for e in json.load(fh)["entries"] if e["repr"] == "msc" and e["L"] == L]
     assert ent, f"no tuning entry for L={L}"
@@ -56,6 +57,7 @@ def apply_tuning_cache(ctx, L, path=TUNING):
     ctx.set_tuning(L, e["threads"], e["groups"], e["dense"])
     ctx.set_persistent(e["persistent"])
     ctx.set_pooled(e["pooled"])
+    ctx.set_sweep_chunks(e.get("chunks", 1))
     got = ctx.tuning(L)
     for k in ("threads", "groups", "dense", "persistent", "pooled"):
         assert got[k] == e[k], (k, got, e)

@@ -521,6 +521,50 @@ def test_sweep_statistics_are_shape_independent():
         assert got == ref, (threads, groups, dense, pooled, got, ref)
 
 
+def _digest(ctx, d, steps):
+    import hashlib
+    h = hashlib.sha256()
+    h.update(ctx.obs()[0, :, :1 + steps].tobytes())
+    for p in range(2 if d["overlap"] == W.Q_TWO_POP else 1):
+        for a in ctx.state(0, p):
+            h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("workload", ["fm_L64_R100k", "ea_L32_two_pop"])
+def test_sweep_chunks_bit_exact_at_full_size(workload):
+    """Items split into chunks of consecutive sweeps on the persistent grid
+    (each chunk waiting on the device for the previous chunk of its replica
+    groups) give the records, states and work counters of whole items.  At
+    these sizes the items outnumber the resident workgroups (1563 of one
+    group at L = 64 with 512 threads; 3125 of two groups at L = 32), so the
+    chunks are really used; the automatic choice (0) is checked too."""
+    d = W.fm_L64_R100k() if workload == "fm_L64_R100k" else W.ea_L32_two_pop()
+    G = 1 if d["L"] == 64 else 2
+    steps = 3
+    ref = None
+    for K in (1, 2, 3, 4, 0):
+        say(f"sweep chunks {workload}: K={K}")
+        ctx = pa.Context([d], "msc")
+        ctx.set_tuning(d["L"], 512, G, 3)
+        ctx.set_persistent(1)
+        ctx.set_sweep_chunks(K)
+        used = ctx.sweep_chunks()
+        assert used == K if K else used >= 1, (K, used)
+        ctx.run(1, 1 + steps)
+        got = (_digest(ctx, d, steps), tuple(int(x) for x in ctx.stats().values()))
+        ctx.close()
+        if ref is None:
+            ref = got
+        assert got == ref, (K, used)
+    with pytest.raises(pa.PAError):
+        ctx = pa.Context([d], "msc")
+        try:
+            ctx.set_sweep_chunks(5)
+        finally:
+            ctx.close()
+
+
 @pytest.mark.parametrize("repr_", REPRS)
 def test_multichunk_and_small_runs_in_one_context(repr_):
     """A run of several 2048-replica chunks next to single-chunk runs: the
