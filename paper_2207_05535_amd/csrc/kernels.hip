@@ -1701,32 +1701,43 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
         }
     } else {
         // energies and magnetisations only: carry-save counting
+        const bool ea = R.model == PA_EA_PMJ;      // the ferromagnet's bond signs are all +1
+        const int gl = live ? g : it.group0;       // a group that exists, for lanes that drop their loads
         for (int b0 = 64 * sub; b0 < N; b0 += 16 * 64 * wpg) {
             const int tsites = min(16, (N - b0 + 64 * wpg - 1) / (64 * wpg));
             Csa2 cU;
             Csa1 cD;
-            // two sites unrolled at a time (their loads in flight together);
-            // the carries of weight 4 and up pair up on uniform branches
+            // U sites at a time, all their loads issued before the first use
+            // and none behind a branch (a wavefront or lane with no site
+            // there loads one that exists and drops it); the carries of
+            // weight 4 and up pair up on uniform branches
+            constexpr int U = REPR == PA_MSC64 ? 4 : 2;
 #pragma unroll 1
-            for (int t2 = 0; t2 < 16; t2 += 2)
+            for (int t0 = 0; t0 < 16; t0 += U) {
+                uint64_t w[U], wr[U], wd[U];
+                uint32_t jn[U];
+                bool ok[U];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int t = t2 + u;
-                const int n = b0 + t * 64 * wpg + lane;
-                uint64_t w = 0, ur = 0, ud = 0;   // zero inputs past the last site
-                if (live && n < N) {
-                    const int y = n / L, x = n - y * L;
+                for (int u = 0; u < U; ++u) {
+                    const int n = b0 + (t0 + u) * 64 * wpg + lane;
+                    ok[u] = live && n < N;
+                    const int nn = ok[u] ? n : 0;
+                    const int y = nn / L, x = nn - y * L;
                     const int nr = y * L + (x + 1 == L ? 0 : x + 1);
                     const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
-                    const uint8_t jn = R.jbits[n];
-                    w = load_word<REPR>(buf, g, n, N);
-                    const uint64_t wr = load_word<REPR>(buf, g, nr, N);
-                    const uint64_t wd = load_word<REPR>(buf, g, nd, N);
-                    ur = w ^ wr ^ ((jn & 1) ? ~0ull : 0ull);
-                    ud = w ^ wd ^ ((jn & 2) ? ~0ull : 0ull);
+                    jn[u] = ea ? R.jbits[nn] : 0u;
+                    w[u] = load_word<REPR>(buf, gl, nn, N);
+                    wr[u] = load_word<REPR>(buf, gl, nr, N);
+                    wd[u] = load_word<REPR>(buf, gl, nd, N);
                 }
-                cU.add(t, ur, ud);
-                cD.add(t, w);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t z = ok[u] ? ~0ull : 0ull;   // zero inputs past the last site
+                    const uint64_t ur = (w[u] ^ wr[u] ^ ((jn[u] & 1) ? ~0ull : 0ull)) & z;
+                    const uint64_t ud = (w[u] ^ wd[u] ^ ((jn[u] & 2) ? ~0ull : 0ull)) & z;
+                    cU.add(t0 + u, ur, ud);
+                    cD.add(t0 + u, w[u] & z);
+                }
             }
             uint64_t pl[VB];
             cU.planes(pl);
