@@ -290,7 +290,10 @@ pa_status pa_checkpoint(pa_ctx *ctx, void *host_buf, size_t *bytes);
  * uninterrupted run bit for bit.  The checkpoint carries a hash of every run
  * descriptor and schedule: a checkpoint of other runs (another seed, theta,
  * model, schedule, ...) is rejected with PA_ERR_ARG and the context is left
- * unchanged. */
+ * unchanged.  The launch shapes are the context's own, not the checkpoint's:
+ * a restore after pa_set_tuning, pa_set_persistent or pa_set_sweep_chunks
+ * (or into another context with other shapes) continues with the current
+ * ones, and the results do not depend on them. */
 pa_status pa_restore(pa_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Launch-shape knobs of the batched sweep, chosen by the autotuner per
@@ -368,7 +371,9 @@ pa_status pa_autotune(pa_ctx *ctx, int32_t steps, const char *cache_path, int32_
  * single-spin flips}.  Used to express sweep throughput against the
  * integer-ALU roofline.  Returns PA_ERR_STATE (counters still written) if a
  * sweep chunk ever gave up waiting for the chunk before it (see
- * pa_set_sweep_chunks): the steps since then are not to be trusted. */
+ * pa_set_sweep_chunks) or a sweep item was skipped for not fitting the
+ * launch's LDS (a device work list out of step with the plan; never expected):
+ * the steps since then are not to be trusted. */
 pa_status pa_read_stats(pa_ctx *ctx, uint64_t *host_out);
 
 /* ------------------------------------------------------------------ serving

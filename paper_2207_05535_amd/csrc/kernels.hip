@@ -1443,11 +1443,17 @@ __device__ __forceinline__ void sweep_dispatch(const SweepItem &it, const RunInf
 // only the registers that one size needs).
 template <int LS, bool EA>
 __device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *runs, const PopState *st,
-                                          uint64_t *lds, int dense, unsigned long long *stats)
+                                          uint64_t *lds, uint32_t lds_bytes, int dense, unsigned long long *stats)
 {
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S) || R.theta == 0) return;
+    // an item that does not fit the LDS of this launch (a list that does not
+    // belong to the launch's plan) is skipped and counted, never run
+    if (msc_lds_need(R.N, it.ngroups) > lds_bytes) {
+        if (threadIdx.x == 0) atomicAdd(&stats[ST_STALL], 1ull);
+        return;
+    }
     if constexpr (LS >= 0) {
         sweep_item<LS, EA>(it, R, S, lds, dense, stats);
     } else {
@@ -1481,11 +1487,11 @@ constexpr unsigned int SWEEP_WAIT_SPINS = 1u << 22;
 template <int LS, bool EA>
 __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int n_items, const RunInfo *runs,
                                                     const PopState *st, int dense, unsigned long long *stats,
-                                                    unsigned int *queue, unsigned int *flags)
+                                                    unsigned int *queue, unsigned int *flags, uint32_t lds_bytes)
 {
     extern __shared__ uint64_t lds[];
     if (queue == nullptr) {
-        sweep_one<LS, EA>(items[blockIdx.x], runs, st, lds, dense, stats);
+        sweep_one<LS, EA>(items[blockIdx.x], runs, st, lds, lds_bytes, dense, stats);
         return;
     }
     __shared__ unsigned int ticket, gen;
@@ -1512,7 +1518,7 @@ __global__ void __launch_bounds__(1024) k_sweep_msc(const SweepItem *items, int 
             }
             __syncthreads();
         }
-        sweep_one<LS, EA>(it, runs, st, lds, dense, stats);
+        sweep_one<LS, EA>(it, runs, st, lds, lds_bytes, dense, stats);
         if (it.chunk + 1 < it.nchunk) {
             // every wavefront waits for its own lattice stores (a barrier
             // alone does not), so that the release by the first thread,
@@ -2802,16 +2808,12 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
     return hipSuccess;
 }
 
-size_t msc_lds_bytes(int N, int groups)
-{
-    const size_t units = (size_t)groups * (N / 2);
-    return (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
-}
+size_t msc_lds_bytes(int N, int groups) { return msc_lds_need(N, groups); }
 
 // The sweep kernel for a launch: one compiled for a single (L, model) when
 // every run of the context has it, else the one that dispatches per item.
 using SweepKernel = void (*)(const SweepItem *, int, const RunInfo *, const PopState *, int, unsigned long long *,
-                             unsigned int *, unsigned int *);
+                             unsigned int *, unsigned int *, uint32_t);
 
 SweepKernel msc_kernel(int L, int ea)
 {
@@ -2866,7 +2868,7 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
         const int grid = persistent ? q.grid : q.count;
         msc_kernel(q.L, q.ea)<<<grid, c.sweep_threads, q.lds, c.stream>>>(
             c.sweep_items + q.first, q.count, c.runs, c.st, c.sweep_dense | (c.sweep_pooled << 8), c.stats,
-            persistent ? c.sweep_queue : nullptr, c.sweep_flags);
+            persistent ? c.sweep_queue : nullptr, c.sweep_flags, (uint32_t)q.lds);
         PA_CHECK_LAUNCH();
     }
     return hipSuccess;

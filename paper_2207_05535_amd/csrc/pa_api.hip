@@ -1228,6 +1228,10 @@ pa_status pa_restore(pa_ctx *c, const void *host_buf, size_t bytes)
     PA_HIP(c, hipStreamSynchronize(c->stream));
     c->i = h.i;
     c->phase = h.phase;
+    // the workspace copy brought back the sweep list of the plan at
+    // checkpoint time; the launches use the current plan, so its list is
+    // written again (the tuning may have changed since)
+    if (c->repr == PA_MSC64) return upload_sweep_plan(c);
     return PA_OK;
 }
 

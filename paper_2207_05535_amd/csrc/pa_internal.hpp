@@ -120,6 +120,15 @@ struct SweepItem {    // groups [group0, group0 + ngroups) of one (run, pop), on
 };
 constexpr int MAX_SWEEP_CHUNKS = 4;
 
+// LDS bytes of a batched-sweep workgroup holding `groups` replica groups of
+// N sites: the colour-split lattices, the lists of undecided sites (two
+// 64-bit masks and a 32-bit entry per unit), the bond signs and the counters.
+__host__ __device__ inline size_t msc_lds_need(int N, int groups)
+{
+    const size_t units = (size_t)groups * (N / 2);
+    return (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
+}
+
 struct ChunkItem {    // one chunk of CH replicas of one (run, pop)
     int32_t run, pop, chunk, pad;
 };

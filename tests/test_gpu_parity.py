@@ -248,6 +248,33 @@ def test_checkpoint_restore_bit_exact(repr_):
     ctx2.close()
 
 
+def test_restore_after_launch_shape_change():
+    """A restore after the launch shapes changed continues with the current
+    shapes: the sweep's device work list is the current plan's, not the one
+    saved with the checkpoint (items of four replica groups launched with the
+    LDS of one would not fit).  The continued run equals the uninterrupted
+    one bit for bit, and no sweep item was skipped (the work counters read
+    without error)."""
+    d = W.run_desc(32, W.FM, seed=0x532, R=20000, theta=2, K=9, beta_f=0.5)
+    ref = pa.Context([d], "msc")
+    ref.run(1, 9)
+    want = (ref.obs().tobytes(), [np.ascontiguousarray(a).tobytes() for a in ref.state(0, 0)], ref.stats())
+    ref.close()
+    ctx = pa.Context([d], "msc")
+    ctx.run(1, 5)
+    ck = ctx.checkpoint()
+    for threads, groups, dense, persistent, chunks in [(256, 1, 2, 1, 2), (1024, 2, 4, 0, 1)]:
+        say(f"restore after shape change: threads={threads} groups={groups} persistent={persistent}")
+        ctx.set_tuning(32, threads, groups, dense)
+        ctx.set_persistent(persistent)
+        ctx.set_sweep_chunks(chunks)
+        ctx.restore(ck)
+        ctx.run(5, 9)
+        got = (ctx.obs().tobytes(), [np.ascontiguousarray(a).tobytes() for a in ctx.state(0, 0)], ctx.stats())
+        assert got == want, (threads, groups, persistent)
+    ctx.close()
+
+
 def test_out_of_order_calls_rejected():
     d = W.run_desc(8, W.FM, R=64, theta=1, K=5, beta_f=0.5)
     ctx = pa.Context([d], "msc")
