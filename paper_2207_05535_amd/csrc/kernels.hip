@@ -768,6 +768,47 @@ __device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, 
                 if (lane < cnt) dst[nb + lane] = mine;
             }
         }
+    } else if ((__shfl(p, 63, 64) >> 6) - (__shfl(p, 0, 64) >> 6) < 2) {
+        // the parents lie in at most two source groups: each lane packs the
+        // 64 spin bytes of one site of each source group into a word (16-byte
+        // loads), the words go through the bit-packed copy above, and the
+        // child word is unpacked into 64 canonical bytes (16-byte stores)
+        const uint8_t *srcb = R.spins[pop][S.src];
+        uint8_t *dstb = R.spins[pop][S.cur] + (size_t)G * N * 64;
+        const int g_lo = __shfl(p, 0, 64) >> 6;
+        const int nsrc = (__shfl(p, 63, 64) >> 6) - g_lo + 1;   // 1 or 2, uniform
+        for (int n0 = sub * 64; n0 < N; n0 += 2 * wpg * 64) {
+            uint4 v[2][2][4];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int n = min(n0 + b * wpg * 64 + lane, N - 1);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint4 *s4 = (const uint4 *)(srcb + ((size_t)(g_lo + min(q, nsrc - 1)) * N + n) * 64);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) v[b][q][k] = s4[k];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                uint64_t row = 0;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    if (q < nsrc) {
+                        const uint64_t t = __shfl(transpose64(pack64(v[b][q])), p & 63, 64);
+                        if ((p >> 6) == g_lo + q) row = t;
+                    }
+                }
+                if (!valid) row = 0;   // slots past the population hold +1 spins
+                const uint64_t out = transpose64(row);
+                const int n = n0 + b * wpg * 64 + lane;
+                if (n0 + b * wpg * 64 < N && n < N) {
+                    uint4 *d4 = (uint4 *)(dstb + (size_t)n * 64);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) d4[k] = spins16((uint32_t)(out >> (16 * k)) & 0xFFFFu);
+                }
+            }
+        }
     } else {
         const uint8_t *src = R.spins[pop][S.src] + (size_t)(p >> 6) * N * 64 + (p & 63);
         uint8_t *dst = R.spins[pop][S.cur] + (size_t)G * N * 64 + lane;
@@ -1577,8 +1618,13 @@ __device__ __forceinline__ uint64_t load_word(const uint8_t *buf, int g, int n, 
 template <int REPR, int LT, bool WITH_Q>
 __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int sub, int wpg, bool live,
                                               const RunInfo &R, const PopState &S, const PopState *st,
-                                              uint32_t (*red)[MEAS_WAVES][64])
+                                              uint32_t (*red)[MEAS_WAVES][64], const uint64_t *lw)
 {
+    // the group's own words come from LDS when the workgroup staged them
+    // (lw != nullptr), else from memory
+    auto own = [&](int gg, int n, int NN) -> uint64_t {
+        return lw ? lw[n] : load_word<REPR>(R.spins[it.pop][S.cur], gg, n, NN);
+    };
     const int L = LT ? LT : R.L;
     const int N = L * L;
     const int Rc = S.Rcur;
@@ -1666,9 +1712,9 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
                     const int nr = y * L + (x + 1 == L ? 0 : x + 1);
                     const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
                     const uint8_t jn = R.jbits[n];
-                    const uint64_t w = load_word<REPR>(buf, g, n, N);
-                    const uint64_t wr = load_word<REPR>(buf, g, nr, N);
-                    const uint64_t wd = load_word<REPR>(buf, g, nd, N);
+                    const uint64_t w = own(g, n, N);
+                    const uint64_t wr = own(g, nr, N);
+                    const uint64_t wd = own(g, nd, N);
                     const uint64_t br = w ^ wr, bd = w ^ wd;
                     vinc2(cU, br ^ ((jn & 1) ? ~0ull : 0ull), bd ^ ((jn & 2) ? ~0ull : 0ull));
                     vinc(cD, w);
@@ -1732,9 +1778,9 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
                     const int nr = y * L + (x + 1 == L ? 0 : x + 1);
                     const int nd = (y + 1 == L ? 0 : y + 1) * L + x;
                     jn[u] = ea ? R.jbits[nn] : 0u;
-                    w[u] = load_word<REPR>(buf, gl, nn, N);
-                    wr[u] = load_word<REPR>(buf, gl, nr, N);
-                    wd[u] = load_word<REPR>(buf, gl, nd, N);
+                    w[u] = own(gl, nn, N);
+                    wr[u] = own(gl, nr, N);
+                    wd[u] = own(gl, nd, N);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -1807,6 +1853,7 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
                                                           const PopState *st)
 {
     __shared__ uint32_t red[4][MEAS_WAVES][64];
+    extern __shared__ uint64_t words[];   // [groups of the item][N] when staged
     const SweepItem it = items[blockIdx.x];
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
@@ -1816,14 +1863,34 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
     const int k = wv / wpg, sub = wv - k * wpg;
     const int g = it.group0 + k;
     const bool live = k < it.ngroups && g * 64 < S.Rcur;
+    // int8 layout: each group's words are read once from memory into LDS
+    // (four 16-byte loads per site, packed on the way), then every site reads
+    // itself and its neighbours from there instead of loading and packing
+    // three 64-byte rows.  Not for lattices above MEAS_STAGE_N sites, nor at
+    // theta = infinity (no lattice to read).  The bit-packed layout reads its
+    // 8-byte words straight from memory: staging them measured slower (34
+    // against 22 us at L = 64, R = 1e5), the barrier after the staging pass
+    // keeping loads and counting from overlapping.
+    const bool staged = REPR == PA_INT8 && R.N <= MEAS_STAGE_N && !(R.exact_dos && S.i > 0);
+    const uint64_t *lw = nullptr;
+    if (staged) {
+        uint64_t *mine = words + (size_t)k * R.N;
+        if (live) {
+            const uint8_t *buf = R.spins[it.pop][S.cur];
+            for (int n = sub * 64 + (threadIdx.x & 63); n < R.N; n += 64 * wpg)
+                mine[n] = load_word<REPR>(buf, g, n, R.N);
+        }
+        __syncthreads();
+        lw = mine;
+    }
     switch (R.L) {
-    case 8: measure_group<REPR, 8, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 16: measure_group<REPR, 16, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 24: measure_group<REPR, 24, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 32: measure_group<REPR, 32, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 48: measure_group<REPR, 48, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
-    case 64: measure_group<REPR, 64, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
-    default: measure_group<REPR, 0, WITH_Q>(it, g, sub, wpg, live, R, S, st, red); break;
+    case 8: measure_group<REPR, 8, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
+    case 16: measure_group<REPR, 16, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
+    case 24: measure_group<REPR, 24, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
+    case 32: measure_group<REPR, 32, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
+    case 48: measure_group<REPR, 48, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
+    case 64: measure_group<REPR, 64, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
+    default: measure_group<REPR, 0, WITH_Q>(it, g, sub, wpg, live, R, S, st, red, lw); break;
     }
 }
 
@@ -2998,9 +3065,9 @@ hipError_t launch_measure(const LaunchCtx &c)
         else if (c.repr == PA_MSC64)
             k_measure<PA_MSC64, false><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
         else if (c.any_overlap)
-            k_measure<PA_INT8, true><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+            k_measure<PA_INT8, true><<<c.n_meas_items, MEAS_THREADS, MEAS_STAGE_BYTES, c.stream>>>(c.meas_items, c.runs, c.st);
         else
-            k_measure<PA_INT8, false><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+            k_measure<PA_INT8, false><<<c.n_meas_items, MEAS_THREADS, MEAS_STAGE_BYTES, c.stream>>>(c.meas_items, c.runs, c.st);
         PA_CHECK_LAUNCH();
     }
     k_meas_chunk<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);

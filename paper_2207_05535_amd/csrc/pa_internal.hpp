@@ -40,6 +40,11 @@ constexpr int NACC = 13;  // measure accumulators, see Acc
 // gets one wavefront per group up to 1024 sites, two up to 2048, else four.
 constexpr int MEAS_WAVES = 4;
 constexpr int MEAS_THREADS = 64 * MEAS_WAVES;
+// The measurement stages a workgroup's lattices in LDS up to this many sites
+// per lattice: MEAS_WAVES / waves-per-group lattices of N words, at most
+// 4096 x 8 bytes (one group of 4096 sites, or four of 1024).
+constexpr int MEAS_STAGE_N = 4096;
+constexpr size_t MEAS_STAGE_BYTES = 32768;
 // per-group partial sums: E, E^2, |M|, M^2, pairs, Q, |Q|, Q^2, Q_l, Q_l^2,
 // minimum energy
 constexpr int MEAS_PART = 11;
