@@ -181,6 +181,7 @@ def test_autotune_keeps_results_and_uses_cache(tmp_path):
     res = ctx.autotune(steps=2, cache_path=cache)
     assert res["tried"] > 10 and res["rejected"] == 0
     shapes = {L: ctx.tuning(L) for L in (8, 16, 24, 32)}
+    chunks = ctx.sweep_chunks()
     ctx.run(3, 10)                               # continues exactly as untuned
     assert ctx.obs().tobytes() == want.tobytes()
     ctx.close()
@@ -192,6 +193,8 @@ def test_autotune_keeps_results_and_uses_cache(tmp_path):
     res2 = ctx2.autotune(steps=2, cache_path=cache)
     assert res2["tried"] == 0
     assert {L: ctx2.tuning(L) for L in (8, 16, 24, 32)} == shapes
+    assert ctx2.sweep_chunks() == chunks
+    assert all("chunks" in e for e in entries)
     ctx2.run(1, 10)
     assert ctx2.obs().tobytes() == want.tobytes()
     ctx2.close()
