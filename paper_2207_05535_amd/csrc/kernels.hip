@@ -1036,8 +1036,12 @@ __global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, con
 //    dE = +8) and make calls 0 .. dense-1 in lockstep; nearly every site
 //    needs that many, so few lanes idle;
 //  - sparse rounds: the sites still undecided are kept in a wave-private LDS
-//    list that is compacted in place after every call, so each round's calls
-//    run on full wavefronts.
+//    list.  For lattices of at most 4096 sites the list is a queue whose
+//    entries carry their next call index, and every round takes the next 64
+//    entries whatever call each is at (sweep_stream_wave); otherwise the
+//    list is compacted in place after every call index (sweep_sparse_wave),
+//    or pooled over the workgroup (sweep_sparse_pooled).  Either way each
+//    round's calls run on full wavefronts until the last entries.
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
 // Sparse rounds of one wavefront over its own compacted list of `cnt`
