@@ -558,15 +558,22 @@ def _digest(ctx, d, steps):
     return h.hexdigest()
 
 
-@pytest.mark.parametrize("workload", ["fm_L64_R100k", "ea_L32_two_pop"])
+@pytest.mark.parametrize("workload", ["fm_L64_R100k", "ea_L32_two_pop", "fm_L64_R100k_theta1"])
 def test_sweep_chunks_bit_exact_at_full_size(workload):
     """Items split into chunks of consecutive sweeps on the persistent grid
     (each chunk waiting on the device for the previous chunk of its replica
     groups) give the records, states and work counters of whole items.  At
     these sizes the items outnumber the resident workgroups (1563 of one
     group at L = 64 with 512 threads; 3125 of two groups at L = 32), so the
-    chunks are really used; the automatic choice (0) is checked too."""
-    d = W.fm_L64_R100k() if workload == "fm_L64_R100k" else W.ea_L32_two_pop()
+    chunks are really used; the automatic choice (0) is checked too.  With
+    theta = 1 every chunk but one holds no sweep at all (it only loads and
+    stores its lattices)."""
+    if workload == "ea_L32_two_pop":
+        d = W.ea_L32_two_pop()
+    else:
+        d = W.fm_L64_R100k()
+        if workload.endswith("theta1"):
+            d = W.with_(d, theta=1)
     G = 1 if d["L"] == 64 else 2
     steps = 3
     ref = None
