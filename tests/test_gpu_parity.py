@@ -599,6 +599,26 @@ def test_sweep_chunks_bit_exact_at_full_size(workload):
             ctx.close()
 
 
+def test_sweep_chunks_whole_schedule():
+    """The headline workload over its whole schedule (199 steps, beta up to
+    0.6) with the cache's three chunks of sweeps on the persistent grid
+    equals the same run with whole items: every record, the final state and
+    the work counters."""
+    d = W.fm_L64_R100k()
+    got = []
+    for K in (1, 3):
+        say(f"whole schedule with {K} chunk(s)")
+        ctx = pa.Context([d], "msc")
+        ctx.set_tuning(64, 512, 1, 3)
+        ctx.set_persistent(1)
+        ctx.set_sweep_chunks(K)
+        assert ctx.sweep_chunks() == K
+        ctx.run(1, d["K"])
+        got.append((_digest(ctx, d, d["K"] - 1), ctx.stats()))
+        ctx.close()
+    assert got[0] == got[1]
+
+
 @pytest.mark.parametrize("repr_", REPRS)
 def test_multichunk_and_small_runs_in_one_context(repr_):
     """A run of several 2048-replica chunks next to single-chunk runs: the
