@@ -2125,128 +2125,142 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
         }
         __syncthreads();
     }
-    if (tid >= 64) return;
-    auto famv = [&](int m) { return in_lds ? Lfam[m] : fam[m]; };
-    auto fpiv = [&](int m) { return in_lds ? Lfpi[m] : ldc(&W.fampi[m]); };
+    // The other wavefronts wait for the repair, then load and store pi with
+    // it (the replay of the exchanges itself is one wavefront's, in order).
+    int nsw = 0, status = 0;
     int32_t *swaps = W.cnt;   // [2 B + 1] ints, B >= R_i: room for R_i exchanges
-    int nsw = 0;
+    if (tid < 64) {
+        auto famv = [&](int m) { return in_lds ? Lfam[m] : fam[m]; };
+        auto fpiv = [&](int m) { return in_lds ? Lfpi[m] : ldc(&W.fampi[m]); };
 
-    // The repair, one wavefront, over the list in batches of 64 entries.
-    // What does not change during the repair (position, its place in the
-    // search order, its family, the end of its family's run of labels, its
-    // initial partner) is loaded for a whole batch at once; an entry is
-    // still open unless an earlier exchange in this repair took its
-    // position as the partner (an exchange leaves both of its positions
-    // matched for good), which the lanes track by comparing positions.
-    // With the identity pattern the mismatches of one family come one after
-    // the other, and a candidate that failed for one of them fails for the
-    // next as well (exchanges only hand this family's replicas to
-    // candidates), so the search resumes after the previous partner
-    // (unwrapped candidate index prev_u).
-    const int lane = tid;
-    int status = 0;
-    int prev_f = -1;
-    int64_t prev_u = 0;
-    for (int e0 = 0; e0 < nlist && status == 0; e0 += 64) {
-        const int e = e0 + lane;
-        int t_l = 0, k_l = -1, f_l = 0, hi_l = 0, p_l = 0;
-        bool open_l = false;
-        if (e < nlist) {
-            t_l = ldc(&W.list[e]);
-            k_l = rdm ? ldc(&W.sigma[t_l]) : t_l;
-            f_l = famv(k_l);
-            open_l = fpiv(k_l) == f_l;
-            if (!in_lds) p_l = ldc(&W.pi[k_l]);
-            if (!rdm) {   // the first later index with another label
-                int lo = t_l + 1, hi = Rc;
-                while (lo < hi) {
-                    const int m = (lo + hi) >> 1;
-                    if (famv(m) == f_l) lo = m + 1;
-                    else hi = m;
+        // The repair, one wavefront, over the list in batches of 64 entries.
+        // What does not change during the repair (position, its place in the
+        // search order, its family, the end of its family's run of labels, its
+        // initial partner) is loaded for a whole batch at once; an entry is
+        // still open unless an earlier exchange in this repair took its
+        // position as the partner (an exchange leaves both of its positions
+        // matched for good), which the lanes track by comparing positions.
+        // With the identity pattern the mismatches of one family come one after
+        // the other, and a candidate that failed for one of them fails for the
+        // next as well (exchanges only hand this family's replicas to
+        // candidates), so the search resumes after the previous partner
+        // (unwrapped candidate index prev_u).
+        const int lane = tid;
+        int prev_f = -1;
+        int64_t prev_u = 0;
+        for (int e0 = 0; e0 < nlist && status == 0; e0 += 64) {
+            const int e = e0 + lane;
+            int t_l = 0, k_l = -1, f_l = 0, hi_l = 0, p_l = 0;
+            bool open_l = false;
+            if (e < nlist) {
+                t_l = ldc(&W.list[e]);
+                k_l = rdm ? ldc(&W.sigma[t_l]) : t_l;
+                f_l = famv(k_l);
+                open_l = fpiv(k_l) == f_l;
+                if (!in_lds) p_l = ldc(&W.pi[k_l]);
+                if (!rdm) {   // the first later index with another label
+                    int lo = t_l + 1, hi = Rc;
+                    while (lo < hi) {
+                        const int m = (lo + hi) >> 1;
+                        if (famv(m) == f_l) lo = m + 1;
+                        else hi = m;
+                    }
+                    hi_l = lo;
                 }
-                hi_l = lo;
             }
-        }
-        const int nb = min(64, nlist - e0);
-        for (int j = 0; j < nb; ++j) {
-            if (!__shfl((int)open_l, j, 64)) continue;
-            const int t = __shfl(t_l, j, 64), k = __shfl(k_l, j, 64), fk = __shfl(f_l, j, 64);
-            const int pk = __shfl(p_l, j, 64);
-            int64_t u = t + 1;
-            if (!rdm) {
-                u = __shfl(hi_l, j, 64);
-                if (fk == prev_f && prev_u + 1 > u) u = prev_u + 1;
-            }
-            const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
-            int found = -1, fm = 0;
-            for (; u < uend; u += 64) {
-                const int64_t uu = u + lane;
-                bool ok = false;
-                int m = 0, fpm = 0;
-                if (uu < uend) {
-                    const int q = (int)(uu >= Rc ? uu - Rc : uu);
-                    m = rdm ? ldc(&W.sigma[q]) : q;
-                    fpm = fpiv(m);
-                    ok = famv(m) != fk && fpm != fk;
+            const int nb = min(64, nlist - e0);
+            for (int j = 0; j < nb; ++j) {
+                if (!__shfl((int)open_l, j, 64)) continue;
+                const int t = __shfl(t_l, j, 64), k = __shfl(k_l, j, 64), fk = __shfl(f_l, j, 64);
+                const int pk = __shfl(p_l, j, 64);
+                int64_t u = t + 1;
+                if (!rdm) {
+                    u = __shfl(hi_l, j, 64);
+                    if (fk == prev_f && prev_u + 1 > u) u = prev_u + 1;
                 }
-                const uint64_t bal = __ballot(ok);
-                if (bal) {
-                    const int first = __ffsll((unsigned long long)bal) - 1;
-                    found = __shfl(m, first, 64);
-                    fm = __shfl(fpm, first, 64);
-                    prev_u = u + first;
+                const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
+                int found = -1, fm = 0;
+                for (; u < uend; u += 64) {
+                    const int64_t uu = u + lane;
+                    bool ok = false;
+                    int m = 0, fpm = 0;
+                    if (uu < uend) {
+                        const int q = (int)(uu >= Rc ? uu - Rc : uu);
+                        m = rdm ? ldc(&W.sigma[q]) : q;
+                        fpm = fpiv(m);
+                        ok = famv(m) != fk && fpm != fk;
+                    }
+                    const uint64_t bal = __ballot(ok);
+                    if (bal) {
+                        const int first = __ffsll((unsigned long long)bal) - 1;
+                        found = __shfl(m, first, 64);
+                        fm = __shfl(fpm, first, 64);
+                        prev_u = u + first;
+                        break;
+                    }
+                }
+                if (found < 0) {   // impossible with no family above Rc / 2
+                    status = 2;
                     break;
                 }
-            }
-            if (found < 0) {   // impossible with no family above Rc / 2
-                status = 2;
-                break;
-            }
-            if (in_lds) {
-                if (lane == 0) {
-                    Lfpi[k] = fm;
-                    Lfpi[found] = fk;
-                    swaps[2 * nsw] = k;
-                    swaps[2 * nsw + 1] = found;
+                if (in_lds) {
+                    if (lane == 0) {
+                        Lfpi[k] = fm;
+                        Lfpi[found] = fk;
+                        swaps[2 * nsw] = k;
+                        swaps[2 * nsw + 1] = found;
+                    }
+                    ++nsw;
+                } else {
+                    if (lane == 0) {
+                        const int pm = ldc(&W.pi[found]);
+                        stc(&W.pi[k], pm);
+                        stc(&W.pi[found], pk);
+                        stc(&W.fampi[k], fm);
+                        stc(&W.fampi[found], fk);
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
                 }
-                ++nsw;
-            } else {
-                if (lane == 0) {
-                    const int pm = ldc(&W.pi[found]);
-                    stc(&W.pi[k], pm);
-                    stc(&W.pi[found], pk);
-                    stc(&W.fampi[k], fm);
-                    stc(&W.fampi[found], fk);
-                }
-                __builtin_amdgcn_s_waitcnt(0);
+                if (k_l == found) open_l = false;
+                prev_f = fk;
             }
-            if (k_l == found) open_l = false;
-            prev_f = fk;
+        }
+        if (lane == 0) {
+            sh[0] = nsw;
+            sh[1] = status;
         }
     }
+    __syncthreads();
+    nsw = sh[0];
+    status = sh[1];
     if (in_lds && status == 0) {   // replay the exchanges onto pi, in LDS
-        __builtin_amdgcn_s_waitcnt(0);
-        int32_t *Lpi = Lfam;
-        for (int k = lane; k < Rc; k += 64) Lpi[k] = ldc(&W.pi[k]);
-        for (int s0 = 0; s0 < nsw; s0 += 64) {
-            int a = 0, b = 0;
-            if (s0 + lane < nsw) {
-                a = ldc(&swaps[2 * (s0 + lane)]);
-                b = ldc(&swaps[2 * (s0 + lane) + 1]);
-            }
-            const int ns = min(64, nsw - s0);
-            for (int j = 0; j < ns; ++j) {
-                const int x = __shfl(a, j, 64), y = __shfl(b, j, 64);
-                if (lane == 0) {
-                    const int px = Lpi[x], py = Lpi[y];
-                    Lpi[x] = py;
-                    Lpi[y] = px;
+        int32_t *Lpi = Lfam;       // the family labels are no longer needed
+        for (int k = tid; k < Rc; k += T) Lpi[k] = ldc(&W.pi[k]);
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            __builtin_amdgcn_s_waitcnt(0);   // this wavefront's exchange log is written
+            for (int s0 = 0; s0 < nsw; s0 += 64) {
+                int a = 0, b = 0;
+                if (s0 + lane < nsw) {
+                    a = ldc(&swaps[2 * (s0 + lane)]);
+                    b = ldc(&swaps[2 * (s0 + lane) + 1]);
+                }
+                const int ns = min(64, nsw - s0);
+                for (int j = 0; j < ns; ++j) {
+                    const int x = __shfl(a, j, 64), y = __shfl(b, j, 64);
+                    if (lane == 0) {
+                        const int px = Lpi[x], py = Lpi[y];
+                        Lpi[x] = py;
+                        Lpi[y] = px;
+                    }
                 }
             }
         }
-        for (int k = lane; k < Rc; k += 64) stc(&W.pi[k], Lpi[k]);
+        __syncthreads();
+        for (int k = tid; k < Rc; k += T) stc(&W.pi[k], Lpi[k]);
     }
-    if (lane == 0) {
+    if (tid == 0) {
         stc(&W.hdr[0], status);
         stc(&W.hdr[1], nlist);
     }
