@@ -1044,6 +1044,20 @@ __global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, con
 //    round's calls run on full wavefronts until the last entries.
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
+// b plus the number of lanes below this one whose bit is set in the
+// wavefront mask m (two mbcnt instructions).
+__device__ __forceinline__ int rank_below(uint64_t m, int b)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)b));
+}
+
+// x mod m for 0 <= x < 2m: an unsigned minimum instead of a compare and a
+// select.
+__device__ __forceinline__ int wrap_once(int x, int m)
+{
+    return (int)min((uint32_t)x, (uint32_t)x - (uint32_t)m);
+}
+
 // Sparse rounds of one wavefront over its own compacted list of `cnt`
 // undecided sites (entries: lanes of each class, LDS word << 16 | site):
 // call c for every entry, survivors compacted in place; once one pass holds
@@ -1054,7 +1068,6 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
                                                   uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
 {
     const int lane = threadIdx.x & 63;
-    const uint64_t lt_mask = __lanemask_lt();
     for (int c = c_first; c < 16 && cnt > 0; ++c) {
         if (cnt <= 64) {
             uint64_t und4 = 0, und8 = 0, acc = 0;
@@ -1094,7 +1107,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
             }
             const uint64_t need = __ballot((und4 | und8) != 0);
             if ((und4 | und8) != 0) {
-                const int slot = wcnt + __popcll(need & lt_mask);
+                const int slot = rank_below(need, wcnt);
                 e4[slot] = und4;
                 e8[slot] = und8;
                 en[slot] = pk;
@@ -1119,13 +1132,11 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
                                                   uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
 {
     const int lane = threadIdx.x & 63;
-    const uint64_t lt_mask = __lanemask_lt();
     int left = cnt;          // entries in the queue
     int hs = 0, ts = cnt;    // slots of the head and of the tail (ts < cap unless the ring is full)
     if (ts >= cap) ts -= cap;
     while (left > 64) {
-        int slot = hs + lane;
-        if (slot >= cap) slot -= cap;
+        const int slot = wrap_once(hs + lane, cap);
         uint64_t und4 = e4[slot], und8 = e8[slot], acc = 0;
         const uint32_t pk = en[slot];
         const int addr = (int)(pk >> 16);
@@ -1137,8 +1148,7 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
         const bool more = (und4 | und8) != 0 && c < 15u;
         const uint64_t need = __ballot(more);
         if (more) {
-            int out = ts + __popcll(need & lt_mask);
-            if (out >= cap) out -= cap;
+            const int out = wrap_once(rank_below(need, ts), cap);
             e4[out] = und4;
             e8[out] = und8;
             en[out] = (pk & 0xFFFF0FFFu) | ((c + 1u) << 12);
@@ -1154,8 +1164,7 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
     int addr = 0;
     uint32_t n = 0, g = 0, c = 16;
     if (lane < left) {
-        int slot = hs + lane;
-        if (slot >= cap) slot -= cap;
+        const int slot = wrap_once(hs + lane, cap);
         und4 = e4[slot];
         und8 = e8[slot];
         const uint32_t pk = en[slot];
@@ -1192,7 +1201,6 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                                                     uint32_t key1, uint32_t &wcalls)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const uint64_t lt_mask = __lanemask_lt();
     const int tailw = min(2, nw);   // wavefronts that finish the last entries
     __syncthreads();   // every wavefront's appends are in the list
     int cnt = ctl[h & 1];
@@ -1249,7 +1257,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                 tot += v;
             }
             if ((und4 | und8) != 0) {
-                const int slot = off + __popcll(need & lt_mask);
+                const int slot = rank_below(need, off);
                 e4[slot] = und4;
                 e8[slot] = und8;
                 en[slot] = pk;
@@ -1272,15 +1280,20 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int L = LT ? LT : __builtin_amdgcn_readfirstlane(R.L);
     const int N = L * L, half = L >> 1, nh = N >> 1;
     const int T = blockDim.x, tid = threadIdx.x;
-    const int lane = tid & 63, wv = tid >> 6, nw = T >> 6;
+    // the wavefront index is uniform in a wavefront; saying so keeps every
+    // range, count and loop bound derived from it in scalar registers
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = T >> 6;
     const int Rc = __builtin_amdgcn_readfirstlane(S.Rcur);
     const int group0 = __builtin_amdgcn_readfirstlane(item.group0);
     const int pop = __builtin_amdgcn_readfirstlane(item.pop);
     const int theta = __builtin_amdgcn_readfirstlane(R.theta);
-    // this item's sweeps (a chunk of them, or all theta)
+    // this item's sweeps (a chunk of them, or all theta); when theta is not
+    // a multiple of the chunk count the first chunks take one sweep more, so
+    // the chunks taken last from the queue are the shortest
     const int nchunk = max(1, __builtin_amdgcn_readfirstlane(item.nchunk));
     const int chunk = __builtin_amdgcn_readfirstlane(item.chunk);
-    const int s_begin = chunk * theta / nchunk, s_end = (chunk + 1) * theta / nchunk;
+    const int sq = theta / nchunk, sr = theta - sq * nchunk;
+    const int s_begin = chunk * sq + min(chunk, sr), s_end = s_begin + sq + (chunk < sr ? 1 : 0);
     const uint32_t key0 = __builtin_amdgcn_readfirstlane(R.key0), key1 = __builtin_amdgcn_readfirstlane(R.key1);
     const int G = min(__builtin_amdgcn_readfirstlane(item.ngroups), (Rc + 63) / 64 - group0);
     if (G <= 0) return;
@@ -1327,7 +1340,6 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const uint64_t vlast = (Rc - lastg * 64 >= 64) ? ~0ull : ((1ull << (Rc - lastg * 64)) - 1);
     const int upw = (units + nw - 1) / nw;
     const int ub = min(units, wv * upw), ue = min(units, ub + upw);
-    const uint64_t lt_mask = __lanemask_lt();
     uint32_t wcalls = 0;   // Philox calls of this wavefront (uniform)
     if (tid == 0) ctl[0] = ctl[1] = 0;
     for (int s = s_begin; s < s_end; ++s) {
@@ -1357,10 +1369,13 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                         if (Th.all4) { sc.flip |= sc.one; sc.one = 0; }
                         if (Th.all8) { sc.flip |= sc.zero; sc.zero = 0; }
                     }
-                    const uint64_t valid = group0 + gs == lastg ? vlast : ~0ull;
                     acc = sc.flip;
-                    und4 = sc.one & valid;
-                    und8 = sc.zero & valid;
+                    und4 = sc.one;
+                    und8 = sc.zero;
+                    if (group0 + gs == lastg) {   // only its valid replicas draw
+                        und4 &= vlast;
+                        und8 &= vlast;
+                    }
                 }
                 for (int c = 0; c < dense; ++c) {
                     const uint64_t live = __ballot((und4 | und8) != 0);
@@ -1378,7 +1393,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     base_slot = __shfl(b0, 0, 64);
                 }
                 if ((und4 | und8) != 0) {
-                    const int slot = base_slot + __popcll(need & lt_mask);
+                    const int slot = rank_below(need, base_slot);
                     e4[slot] = und4;
                     e8[slot] = und8;
                     en[slot] = ((uint32_t)addr << 16) | (stream ? (uint32_t)dense << 12 : 0u) | n;
@@ -1397,7 +1412,8 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
             if (STEP_ROWS && (ub & 63) == 0 && ub < ue) {
                 constexpr int RS = STEP_ROWS ? 64 / (LT / 2) : 0;   // rows per pass
                 int gs = __builtin_amdgcn_readfirstlane(ub / nh);
-                int k = ub - gs * nh + lane;
+                int kb = ub - gs * nh;   // lane 0's unit in its group: uniform, so the group change is too
+                int k = kb + lane;
                 int y = k / half;
                 const int m = k - y * half;
                 const int p = (y + colour) & 1;   // constant: y advances by an even count
@@ -1410,11 +1426,13 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     const int ku = y == 0 ? k + nh - half : k - half;
                     const int kd = y + 1 == L ? k - nh + half : k + half;
                     chunk(u0 + lane < ue, gs, k, k + dh, ku, kd, addr, n);
+                    kb += 64;
                     k += 64;
                     y += RS;
                     n += (uint32_t)(RS * L);
                     addr += 64;
-                    if (k >= nh) {   // every lane at once: the next replica group
+                    if (kb >= nh) {   // every lane at once: the next replica group
+                        kb -= nh;
                         k -= nh;
                         y -= L;
                         n -= (uint32_t)N;
