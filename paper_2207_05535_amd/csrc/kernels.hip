@@ -34,6 +34,14 @@
 
 namespace pa {
 
+// Index of this thread's wavefront in the workgroup, as a value the compiler
+// knows to be uniform in the wavefront (loop bounds and counts derived from it
+// then stay in scalar registers).
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 // ------------------------------------------------------------- utilities
 
 __device__ __forceinline__ uint64_t umul64hi(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
@@ -242,7 +250,7 @@ __device__ __forceinline__ int planes_for(int c) { return 32 - __clz(c); }
 template <typename T, int BS>
 __device__ __forceinline__ T block_exscan(T v, T *lds, T *total)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     T incl = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -858,7 +866,7 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, c
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
     const int wpg = meas_waves_per_group(R.N);
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_id();
     const int k = wv / wpg, sub = wv - k * wpg;
     const int G = it.group0 + k;
     if (k >= it.ngroups || G * 64 >= S.Rcur) return;
@@ -1126,12 +1134,16 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
 // their next call, so rounds stay full until fewer than 64 entries remain;
 // those then run all their remaining calls without being written back.
 // Each site keeps the plain most-significant-first comparison of its own
-// bit planes; only the order of the work changes.
+// bit planes; only the order of the work changes.  tmask[c] holds T's bits
+// at the planes of call c (call_masks); with ONE_GROUP (the workgroup holds
+// one replica group) every entry's group is group0, a uniform value.
+template <bool ONE_GROUP>
 __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en, int cnt,
-                                                  int cap, int N, int group0, const Thresholds &Th, uint32_t i,
+                                                  int cap, int N, int group0, const uint4 *tmask, uint32_t i,
                                                   uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
 {
     const int lane = threadIdx.x & 63;
+    auto group_of = [&](int addr) { return (uint32_t)(ONE_GROUP ? group0 : group0 + addr / N); };
     int left = cnt;          // entries in the queue
     int hs = 0, ts = cnt;    // slots of the head and of the tail (ts < cap unless the ring is full)
     if (ts >= cap) ts -= cap;
@@ -1141,8 +1153,7 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
         const uint32_t pk = en[slot];
         const int addr = (int)(pk >> 16);
         const uint32_t c = (pk >> 12) & 15u;
-        const uint32_t g = (uint32_t)(group0 + addr / N);
-        draw_call_lane(c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFu, g, i, c3, key0, key1);
+        draw_call_masks(c, tmask[c], und4, und8, acc, pk & 0xFFFu, group_of(addr), i, c3, key0, key1);
         wcalls += 64;
         if (acc) lat[addr] ^= acc;
         const bool more = (und4 | und8) != 0 && c < 15u;
@@ -1162,7 +1173,7 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
     }
     uint64_t und4 = 0, und8 = 0, acc = 0;
     int addr = 0;
-    uint32_t n = 0, g = 0, c = 16;
+    uint32_t n = 0, c = 16;
     if (lane < left) {
         const int slot = wrap_once(hs + lane, cap);
         und4 = e4[slot];
@@ -1171,15 +1182,15 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
         addr = (int)(pk >> 16);
         c = (pk >> 12) & 15u;
         n = pk & 0xFFFu;
-        g = (uint32_t)(group0 + addr / N);
     }
+    const uint32_t g = group_of(addr);
     for (;;) {
         const bool live = (und4 | und8) != 0 && c < 16u;
         const uint64_t lv = __ballot(live);
         if (lv == 0) break;
         wcalls += (uint32_t)__popcll(lv);
         if (live) {
-            draw_call_lane(c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
+            draw_call_masks(c, tmask[c], und4, und8, acc, n, g, i, c3, key0, key1);
             ++c;
         }
     }
@@ -1200,7 +1211,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                                                     const Thresholds &Th, uint32_t i, uint32_t c3, uint32_t key0,
                                                     uint32_t key1, uint32_t &wcalls)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id(), nw = blockDim.x >> 6;
     const int tailw = min(2, nw);   // wavefronts that finish the last entries
     __syncthreads();   // every wavefront's appends are in the list
     int cnt = ctl[h & 1];
@@ -1280,9 +1291,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int L = LT ? LT : __builtin_amdgcn_readfirstlane(R.L);
     const int N = L * L, half = L >> 1, nh = N >> 1;
     const int T = blockDim.x, tid = threadIdx.x;
-    // the wavefront index is uniform in a wavefront; saying so keeps every
-    // range, count and loop bound derived from it in scalar registers
-    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6), nw = T >> 6;
+    const int lane = tid & 63, wv = wave_id(), nw = T >> 6;
     const int Rc = __builtin_amdgcn_readfirstlane(S.Rcur);
     const int group0 = __builtin_amdgcn_readfirstlane(item.group0);
     const int pop = __builtin_amdgcn_readfirstlane(item.pop);
@@ -1304,6 +1313,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     uint32_t *en = (uint32_t *)(e8 + units);              // [units] (LDS word << 16) | site
     uint8_t *jb = (uint8_t *)(en + units);                // [2][nh] bond signs of each site (spin glass)
     int *ctl = (int *)(jb + N);                           // pooled list counts [2], pass counts [2][16]
+    uint4 *tmask = (uint4 *)(lds + msc_lds_tmask_off(N, G) / 8);   // [16] T's bits at each call's planes
     const bool pool = (mode >> 8) & 1;
     const int dense = mode & 0xFF;
     // the streamed sparse rounds keep each entry's next call in its site
@@ -1335,6 +1345,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int i = __builtin_amdgcn_readfirstlane(S.i);
     const Thresholds Th = thresholds_of(R.tabT, i);
     const bool saturated = Th.all4 || Th.all8;
+    if (tid < 16) tmask[tid] = call_masks(Th.t4, Th.t8, (uint32_t)tid);   // read after the next barrier
     const uint32_t c3p = (TAG_SWEEP << 28) | ((uint32_t)pop << 24);
     const int lastg = group0 + G - 1;
     const uint64_t vlast = (Rc - lastg * 64 >= 64) ? ~0ull : ((1ull << (Rc - lastg * 64)) - 1);
@@ -1459,9 +1470,12 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
             if (pool)
                 sweep_sparse_pooled(lat, e4, e8, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
                                     wcalls);
+            else if (stream && G == 1)
+                sweep_stream_wave<true>(lat, e4 + ub, e8 + ub, en + ub, cnt, ue - ub, N, group0, tmask,
+                                        (uint32_t)i, c3, key0, key1, wcalls);
             else if (stream)
-                sweep_stream_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, ue - ub, N, group0, Th, (uint32_t)i, c3,
-                                  key0, key1, wcalls);
+                sweep_stream_wave<false>(lat, e4 + ub, e8 + ub, en + ub, cnt, ue - ub, N, group0, tmask,
+                                         (uint32_t)i, c3, key0, key1, wcalls);
             else
                 sweep_sparse_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, dense, N, group0, Th, (uint32_t)i, c3, key0,
                                   key1, wcalls);
@@ -1650,7 +1664,7 @@ __device__ __forceinline__ void measure_group(const SweepItem &it, int g, int su
     const int L = LT ? LT : R.L;
     const int N = L * L;
     const int Rc = S.Rcur;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     const uint8_t *buf = R.spins[it.pop][S.cur];
     // overlap partners of this group's replicas
     int mode = 0;                      // 0 none, 1 index shift, 2 two populations, 3 permutation pairs
@@ -1881,7 +1895,7 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
     const int wpg = meas_waves_per_group(R.N);
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_id();
     const int k = wv / wpg, sub = wv - k * wpg;
     const int g = it.group0 + k;
     const bool live = k < it.ngroups && g * 64 < S.Rcur;
@@ -1926,7 +1940,7 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_measure(const SweepItem *items
 __global__ void __launch_bounds__(256) k_dos_sample(const Item *items, int n_items, const RunInfo *runs,
                                                     const PopState *st)
 {
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wave_id(), lane = threadIdx.x & 63;
     if (idx >= n_items) return;
     const Item it = items[idx];
     const RunInfo &R = runs[it.run];
@@ -2003,7 +2017,7 @@ __device__ __forceinline__ uint64_t perm_key(int k, int i, int which, uint32_t k
 // the sum.  sh: 17 ints of LDS.
 __device__ int block_scan_excl(int v, int *sh, int *total)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id(), nw = blockDim.x >> 6;
     int x = v;
     for (int o = 1; o < 64; o <<= 1) {
         const int y = __shfl_up(x, o, 64);
@@ -2328,7 +2342,7 @@ template <int REPR>
 __global__ void __launch_bounds__(256) k_wang_rows(const Item *items, int n_items, const RunInfo *runs,
                                                    const PopState *st)
 {
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wave_id(), lane = threadIdx.x & 63;
     if (idx >= n_items) return;
     const Item it = items[idx];
     const RunInfo &R = runs[it.run];
@@ -2354,7 +2368,7 @@ __global__ void __launch_bounds__(256) k_wang_rows(const Item *items, int n_item
 __global__ void __launch_bounds__(256) k_wang_gather(const Item *items, int n_items, const RunInfo *runs,
                                                      const PopState *st)
 {
-    const int idx = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wave_id(), lane = threadIdx.x & 63;
     if (idx >= n_items) return;
     const Item it = items[idx];
     const RunInfo &R = runs[it.run];
@@ -2398,7 +2412,7 @@ __global__ void __launch_bounds__(CH_THREADS) k_meas_chunk(const ChunkItem *item
     const int Rc = S.Rcur;
     const int j0 = it.chunk * CH;
     if (j0 >= Rc) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = wave_id();
     // group partials: groups [j0/64, j0/64 + CH/64), one per lane of wave 0
     int64_t part[MEAS_PART];
 #pragma unroll

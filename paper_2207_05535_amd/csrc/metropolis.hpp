@@ -111,19 +111,27 @@ __device__ __forceinline__ void draw_call(uint32_t c, uint32_t t4, uint32_t t8, 
     plane_both(pb, 0u - ((t4 >> (sh - 1u)) & 1u), 0u - ((t8 >> (sh - 1u)) & 1u), und4, und8, acc);
 }
 
-// draw_call for a call index c that differs between lanes (T's bits at the
-// call's planes are then per-lane masks instead of scalars).
-__device__ __forceinline__ void draw_call_lane(uint32_t c, uint32_t t4, uint32_t t8, uint64_t &und4, uint64_t &und8,
-                                               uint64_t &acc, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1)
+// T's bits at the planes of call c as all-ones or zero masks: x = plane 2c
+// (bit 31 - 2c), y = plane 2c + 1 (bit 30 - 2c), for dE = +4 (x, y) and
+// +8 (z, w).
+__device__ __forceinline__ uint4 call_masks(uint32_t t4, uint32_t t8, uint32_t c)
+{
+    const uint32_t sh = 31u - 2u * c;
+    return make_uint4(0u - ((t4 >> sh) & 1u), 0u - ((t4 >> (sh - 1u)) & 1u), 0u - ((t8 >> sh) & 1u),
+                      0u - ((t8 >> (sh - 1u)) & 1u));
+}
+
+// draw_call for a call index c that differs between lanes, with T's bits
+// at its planes given as masks (call_masks of each lane's c).
+__device__ __forceinline__ void draw_call_masks(uint32_t c, uint4 m, uint64_t &und4, uint64_t &und8, uint64_t &acc,
+                                                uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1)
 {
     const u32x4 o = philox10_sweep(c0 | (c << 20), c1, c2, c3, k0, k1);
-    const uint32_t up = 2u * c;   // T's bit 31 - 2c moved to bit 31, bit 30 - 2c to bit 30
-    const int32_t a4 = (int32_t)(t4 << up), a8 = (int32_t)(t8 << up);
     const uint64_t pa = (uint64_t)o.x | ((uint64_t)o.y << 32);
     const uint64_t pb = (uint64_t)o.z | ((uint64_t)o.w << 32);
-    plane_both(pa, (uint32_t)(a4 >> 31), (uint32_t)(a8 >> 31), und4, und8, acc);
-    plane_both(pb, (uint32_t)((a4 << 1) >> 31), (uint32_t)((a8 << 1) >> 31), und4, und8, acc);
+    plane_both(pa, m.x, m.z, und4, und8, acc);
+    plane_both(pb, m.y, m.w, und4, und8, acc);
 }
 
 // Flip mask of one site, all draws done here (used by the plain path).

@@ -128,10 +128,20 @@ constexpr int MAX_SWEEP_CHUNKS = 4;
 // LDS bytes of a batched-sweep workgroup holding `groups` replica groups of
 // N sites: the colour-split lattices, the lists of undecided sites (two
 // 64-bit masks and a 32-bit entry per unit), the bond signs and the counters.
-__host__ __device__ inline size_t msc_lds_need(int N, int groups)
+// Layout: lattices [groups][N] u64, undecided lanes of the two classes
+// [units] u64 each, list entries [units] u32, bond signs [N] u8, list
+// counts [34] int, then (16-byte aligned) T's bits at the planes of each
+// call [16] uint4.
+__host__ __device__ inline size_t msc_lds_tmask_off(int N, int groups)
 {
     const size_t units = (size_t)groups * (N / 2);
-    return (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
+    const size_t end = (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
+    return (end + 15) & ~(size_t)15;
+}
+
+__host__ __device__ inline size_t msc_lds_need(int N, int groups)
+{
+    return msc_lds_tmask_off(N, groups) + 16 * 16;
 }
 
 struct ChunkItem {    // one chunk of CH replicas of one (run, pop)
