@@ -1127,27 +1127,34 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
 }
 
 // Sparse rounds of one wavefront as a stream (lattices of at most 4096
-// sites): its undecided sites form a queue in a ring of `cap` slots (its
-// own range of the lists; an entry is LDS word << 16 | its next call << 12 |
-// site).  Every round takes the next 64 entries, whatever call each is at,
-// makes that call, and appends the sites still undecided at the tail with
-// their next call, so rounds stay full until fewer than 64 entries remain;
-// those then run all their remaining calls without being written back.
-// Each site keeps the plain most-significant-first comparison of its own
-// bit planes; only the order of the work changes.  tmask[c] holds T's bits
-// at the planes of call c (call_masks); with ONE_GROUP (the workgroup holds
-// one replica group) every entry's group is group0, a uniform value.
+// sites): its undecided sites form a queue in a ring of `cap` slots (an
+// entry is LDS word << 16 | its next call << 12 | site).  Every round takes
+// the next 64 entries, whatever call each is at, makes that call, and
+// appends the sites still undecided at the tail with their next call, so
+// rounds stay full until fewer than 64 entries remain; those then run all
+// their remaining calls without being written back (stream_tail).  The
+// dense chunks append to the same ring; when it is smaller than the
+// wavefront's range, full rounds run between chunks whenever it holds more
+// than 64 entries, so the next chunk's entries always fit.  Each site keeps
+// the plain most-significant-first comparison of its own bit planes; only
+// the order of the work changes.  tmask[c] holds T's bits at the planes of
+// call c (call_masks); with ONE_GROUP (the workgroup holds one replica
+// group) every entry's group is group0, a uniform value.
+struct Ring {
+    int hs, ts, left;   // slot of the head, slot of the tail, entries
+};
+
+// Full rounds while the ring holds more than `limit` (>= 64) entries.
 template <bool ONE_GROUP>
-__device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en, int cnt,
-                                                  int cap, int N, int group0, const uint4 *tmask, uint32_t i,
-                                                  uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
+__device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat, uint64_t *e4, uint64_t *e8,
+                                              uint32_t *en, int cap, int N, int group0, const uint4 *tmask,
+                                              uint32_t i, uint32_t c3, uint32_t key0, uint32_t key1,
+                                              uint32_t &wcalls)
 {
     const int lane = threadIdx.x & 63;
     auto group_of = [&](int addr) { return (uint32_t)(ONE_GROUP ? group0 : group0 + addr / N); };
-    int left = cnt;          // entries in the queue
-    int hs = 0, ts = cnt;    // slots of the head and of the tail (ts < cap unless the ring is full)
-    if (ts >= cap) ts -= cap;
-    while (left > 64) {
+    int left = q.left, hs = q.hs, ts = q.ts;
+    while (left > limit) {
         const int slot = wrap_once(hs + lane, cap);
         uint64_t und4 = e4[slot], und8 = e8[slot], acc = 0;
         const uint32_t pk = en[slot];
@@ -1171,11 +1178,25 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
         if (hs >= cap) hs -= cap;
         left += nn - 64;
     }
+    q.left = left;
+    q.hs = hs;
+    q.ts = ts;
+}
+
+// The last (at most 64) entries: each lane runs all the remaining calls of
+// its own entry.
+template <bool ONE_GROUP>
+__device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const uint64_t *e4, const uint64_t *e8,
+                                            const uint32_t *en, int cap, int N, int group0, const uint4 *tmask,
+                                            uint32_t i, uint32_t c3, uint32_t key0, uint32_t key1,
+                                            uint32_t &wcalls)
+{
+    const int lane = threadIdx.x & 63;
     uint64_t und4 = 0, und8 = 0, acc = 0;
     int addr = 0;
     uint32_t n = 0, c = 16;
-    if (lane < left) {
-        const int slot = wrap_once(hs + lane, cap);
+    if (lane < q.left) {
+        const int slot = wrap_once(q.hs + lane, cap);
         und4 = e4[slot];
         und8 = e8[slot];
         const uint32_t pk = en[slot];
@@ -1183,7 +1204,7 @@ __device__ __forceinline__ void sweep_stream_wave(uint64_t *lat, uint64_t *e4, u
         c = (pk >> 12) & 15u;
         n = pk & 0xFFFu;
     }
-    const uint32_t g = group_of(addr);
+    const uint32_t g = (uint32_t)(ONE_GROUP ? group0 : group0 + addr / N);
     for (;;) {
         const bool live = (und4 | und8) != 0 && c < 16u;
         const uint64_t lv = __ballot(live);
@@ -1307,18 +1328,20 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int G = min(__builtin_amdgcn_readfirstlane(item.ngroups), (Rc + 63) / 64 - group0);
     if (G <= 0) return;
     const int units = G * nh;
-    uint64_t *lat = lds;                                  // [G][2][nh]
-    uint64_t *e4 = lds + (size_t)G * N;                   // [units] undecided lanes of class dE = +4
-    uint64_t *e8 = e4 + units;                            // [units] undecided lanes of class dE = +8
-    uint32_t *en = (uint32_t *)(e8 + units);              // [units] (LDS word << 16) | site
-    uint8_t *jb = (uint8_t *)(en + units);                // [2][nh] bond signs of each site (spin glass)
-    int *ctl = (int *)(jb + N);                           // pooled list counts [2], pass counts [2][16]
-    uint4 *tmask = (uint4 *)(lds + msc_lds_tmask_off(N, G) / 8);   // [16] T's bits at each call's planes
     const bool pool = (mode >> 8) & 1;
     const int dense = mode & 0xFF;
     // the streamed sparse rounds keep each entry's next call in its site
     // word's top bits (sites < 4096); calls 0 .. 15 only
-    const bool stream = !pool && N <= 4096 && dense < 16;
+    const bool stream = msc_streamed(N, mode);
+    const int ents = msc_list_entries(N, G, nw, mode);   // units, or a ring per wavefront
+    const bool bounded = ents < units;
+    uint64_t *lat = lds;                                  // [G][2][nh]
+    uint64_t *e4 = lds + (size_t)G * N;                   // [ents] undecided lanes of class dE = +4
+    uint64_t *e8 = e4 + ents;                             // [ents] undecided lanes of class dE = +8
+    uint32_t *en = (uint32_t *)(e8 + ents);               // [ents] (LDS word << 16) | site
+    uint8_t *jb = (uint8_t *)(en + ents);                 // [2][nh] bond signs of each site (spin glass)
+    int *ctl = (int *)(jb + (EA ? N : 0));                // pooled list counts [2], pass counts [2][16]
+    uint4 *tmask = (uint4 *)(lds + msc_lds_tmask_off(N, G, EA, nw, mode) / 8);   // [16] T's bits per call
     uint64_t *base = (uint64_t *)R.spins[pop][S.cur] + (size_t)group0 * N;
     for (int u = tid; u < G * N; u += T) {
         const int gs = u / N, n = u - gs * N;
@@ -1351,6 +1374,9 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const uint64_t vlast = (Rc - lastg * 64 >= 64) ? ~0ull : ((1ull << (Rc - lastg * 64)) - 1);
     const int upw = (units + nw - 1) / nw;
     const int ub = min(units, wv * upw), ue = min(units, ub + upw);
+    // this wavefront's ring of streamed entries: its own range of the lists,
+    // or MSC_QUEUE_SLOTS slots of its own
+    const int rb = bounded ? wv * MSC_QUEUE_SLOTS : ub, rcap = bounded ? MSC_QUEUE_SLOTS : ue - ub;
     uint32_t wcalls = 0;   // Philox calls of this wavefront (uniform)
     if (tid == 0) ctl[0] = ctl[1] = 0;
     for (int s = s_begin; s < s_end; ++s) {
@@ -1360,6 +1386,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
             __syncthreads();
             if (tid == 0) ctl[(h + 1) & 1] = 0;   // the next half-sweep's count; last read before this barrier
             int cnt = 0;
+            Ring q = {0, 0, 0};
             // dense rounds, 64 units per pass; one unit (lane) per site word
             auto chunk = [&](bool live_unit, int gs, int k, int kh, int ku, int kd, int addr, uint32_t n) {
                 uint64_t und4 = 0, und8 = 0, acc = 0;
@@ -1404,12 +1431,26 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     base_slot = __shfl(b0, 0, 64);
                 }
                 if ((und4 | und8) != 0) {
-                    const int slot = rank_below(need, base_slot);
+                    const int slot =
+                        stream ? rb + wrap_once(rank_below(need, q.ts), rcap) : rank_below(need, base_slot);
                     e4[slot] = und4;
                     e8[slot] = und8;
                     en[slot] = ((uint32_t)addr << 16) | (stream ? (uint32_t)dense << 12 : 0u) | n;
                 }
                 cnt += __popcll(need);
+                if (stream) {
+                    q.ts += __popcll(need);
+                    if (q.ts >= rcap) q.ts -= rcap;
+                    q.left += __popcll(need);
+                    if (bounded && q.left > rcap - 64) {   // room for the next chunk's entries
+                        if (G == 1)
+                            stream_rounds<true>(q, rcap - 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask,
+                                                (uint32_t)i, c3, key0, key1, wcalls);
+                        else
+                            stream_rounds<false>(q, rcap - 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0,
+                                                 tmask, (uint32_t)i, c3, key0, key1, wcalls);
+                    }
+                }
             };
             // Strength-reduced indices: when a pass starts on a multiple of
             // 64 units, a row half (L/2 words) divides 64 an even number of
@@ -1470,12 +1511,17 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
             if (pool)
                 sweep_sparse_pooled(lat, e4, e8, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
                                     wcalls);
-            else if (stream && G == 1)
-                sweep_stream_wave<true>(lat, e4 + ub, e8 + ub, en + ub, cnt, ue - ub, N, group0, tmask,
-                                        (uint32_t)i, c3, key0, key1, wcalls);
-            else if (stream)
-                sweep_stream_wave<false>(lat, e4 + ub, e8 + ub, en + ub, cnt, ue - ub, N, group0, tmask,
-                                         (uint32_t)i, c3, key0, key1, wcalls);
+            else if (stream && G == 1) {
+                stream_rounds<true>(q, 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3,
+                                    key0, key1, wcalls);
+                stream_tail<true>(q, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3, key0,
+                                  key1, wcalls);
+            } else if (stream) {
+                stream_rounds<false>(q, 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3,
+                                     key0, key1, wcalls);
+                stream_tail<false>(q, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3, key0,
+                                   key1, wcalls);
+            }
             else
                 sweep_sparse_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, dense, N, group0, Th, (uint32_t)i, c3, key0,
                                   key1, wcalls);
@@ -1527,7 +1573,7 @@ __device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *ru
     if (!pop_active(S) || R.theta == 0) return;
     // an item that does not fit the LDS of this launch (a list that does not
     // belong to the launch's plan) is skipped and counted, never run
-    if (msc_lds_need(R.N, it.ngroups) > lds_bytes) {
+    if (msc_lds_need(R.N, it.ngroups, R.model == PA_EA_PMJ, (int)(blockDim.x >> 6), dense) > lds_bytes) {
         if (threadIdx.x == 0) atomicAdd(&stats[ST_STALL], 1ull);
         return;
     }
@@ -2925,7 +2971,10 @@ hipError_t launch_sweep_int8_run(const LaunchCtx &c, int run, int L, int groups_
     return hipSuccess;
 }
 
-size_t msc_lds_bytes(int N, int groups) { return msc_lds_need(N, groups); }
+size_t msc_lds_bytes(int N, int groups, bool ea, int threads, int mode)
+{
+    return msc_lds_need(N, groups, ea, threads / 64, mode);
+}
 
 // The sweep kernel for a launch: one compiled for a single (L, model) when
 // every run of the context has it, else the one that dispatches per item.
@@ -2992,7 +3041,7 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
 }
 
 int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, const std::vector<int> &run_ea,
-                  SweepClass *cls)
+                  SweepClass *cls, int threads, int mode)
 {
     // items of runs without Metropolis sweeps are not launched at all (the
     // kernel of another size must never see them)
@@ -3017,7 +3066,7 @@ int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, 
     C.lds = 0;
     for (const SweepItem &it : items) {
         const int L = run_L[it.run];
-        C.lds = std::max(C.lds, msc_lds_bytes(L * L, it.ngroups));
+        C.lds = std::max(C.lds, msc_lds_bytes(L * L, it.ngroups, run_ea[it.run] != 0, threads, mode));
     }
     return 1;
 }

@@ -65,7 +65,10 @@ hipError_t launch_wqhist(const LaunchCtx &c, const pa_obs *obs, int M, int kind,
                          double *logw, double *qw, double *out);
 hipError_t launch_famstats(const LaunchCtx &c, const pa_obs *obs, int pop, int K, int i_done, pa_famstat *out);
 int int8_tile_rows(int L);
-size_t msc_lds_bytes(int N, int groups);
+// LDS bytes of a batched-sweep workgroup of `threads` holding `groups`
+// replica groups of N sites (ea: the spin glass), launched with mode =
+// lockstep calls | pooled << 8.
+size_t msc_lds_bytes(int N, int groups, bool ea, int threads, int mode);
 hipError_t prepare_msc_lds(size_t bytes);
 int sweep_msc_resident(int threads, size_t lds, int L, int ea);   // workgroups resident on the device, 0 on error
 bool msc_specialised(int L);   // a sweep kernel compiled for this L alone exists
@@ -74,8 +77,9 @@ bool msc_specialised(int L);   // a sweep kernel compiled for this L alone exist
 // theta = 0 or the theta = infinity limit) and fills cls with the classes
 // to launch (run_L[r], run_ea[r]: run r's lattice size and model).  Returns
 // the number of classes (at most MAX_SWEEP_CLASSES), or -1 on error.
+// threads and mode: the launch's workgroup size and mode (msc_lds_bytes).
 int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, const std::vector<int> &run_ea,
-                  SweepClass *cls);
+                  SweepClass *cls, int threads, int mode);
 // Persistent grids of the classes (threads per workgroup as launched).
 bool sweep_class_grids(SweepClass *cls, int n, int threads, bool persistent);
 // Chunks of sweeps per item for a persistent launch of n items on `slots`

@@ -605,7 +605,8 @@ bool plan_sweep(const pa_ctx *c, std::vector<SweepItem> &items, size_t &lds)
         const pa_run_desc &d = c->descs[r];
         const int N = d.L * d.L;
         if ((size_t)groups_for(c, d.L) * N > 65535) return false;   // 16-bit LDS word indices
-        lds = std::max(lds, msc_lds_bytes(N, groups_for(c, d.L)));
+        lds = std::max(lds, msc_lds_bytes(N, groups_for(c, d.L), d.model == PA_EA_PMJ, c->sweep_threads,
+                                          c->sweep_dense | (c->sweep_pooled ? 1 << 8 : 0)));
     }
     if (lds > (size_t)c->lds_limit) return false;
     for (int r = 0; r < c->n_runs; ++r) {
@@ -636,7 +637,8 @@ pa_status upload_sweep_plan(pa_ctx *c)
         run_ea[r] = c->descs[r].model == PA_EA_PMJ;
     }
     SweepClass cls[MAX_SWEEP_CLASSES];
-    const int ncls = sweep_classes(items, run_L, run_ea, cls);
+    const int ncls = sweep_classes(items, run_L, run_ea, cls, c->sweep_threads,
+                                   c->sweep_dense | (c->sweep_pooled ? 1 << 8 : 0));
     if (ncls < 0) return PA_ERR_ARG;
     if (prepare_msc_lds(lds) != hipSuccess) return dev_fail(c);
     if (!sweep_class_grids(cls, ncls, c->sweep_threads, c->sweep_persistent)) return dev_fail(c);

@@ -128,20 +128,45 @@ constexpr int MAX_SWEEP_CHUNKS = 4;
 // LDS bytes of a batched-sweep workgroup holding `groups` replica groups of
 // N sites: the colour-split lattices, the lists of undecided sites (two
 // 64-bit masks and a 32-bit entry per unit), the bond signs and the counters.
-// Layout: lattices [groups][N] u64, undecided lanes of the two classes
-// [units] u64 each, list entries [units] u32, bond signs [N] u8, list
-// counts [34] int, then (16-byte aligned) T's bits at the planes of each
-// call [16] uint4.
-__host__ __device__ inline size_t msc_lds_tmask_off(int N, int groups)
+// Queue slots per wavefront of the streamed sparse rounds: a wavefront
+// that owns more site words than this keeps its undecided sites in a ring
+// of this many entries, run down by full rounds whenever it holds more than
+// one chunk's worth (a chunk adds at most 64, and full rounds leave at most
+// 64), so the lists take less LDS and more workgroups fit on a CU.
+constexpr int MSC_QUEUE_SLOTS = 128;
+
+// mode = lockstep calls | pooled << 8, as the batched sweep is launched.
+// The sparse rounds are streamed for lattices of at most 4096 sites when
+// they are not pooled and there are sparse rounds at all.
+__host__ __device__ inline bool msc_streamed(int N, int mode)
 {
-    const size_t units = (size_t)groups * (N / 2);
-    const size_t end = (size_t)groups * N * 8 + units * 20 + (size_t)N + sizeof(int) * 34;
+    return !((mode >> 8) & 1) && N <= 4096 && (mode & 0xFF) < 16;
+}
+
+// Entries of a workgroup's lists of undecided sites: one per site word of
+// one colour of its groups, or MSC_QUEUE_SLOTS per wavefront when streamed
+// rounds let that be fewer.
+__host__ __device__ inline int msc_list_entries(int N, int groups, int nw, int mode)
+{
+    const int units = groups * (N / 2);
+    const int upw = (units + nw - 1) / nw;
+    return msc_streamed(N, mode) && upw > MSC_QUEUE_SLOTS ? nw * MSC_QUEUE_SLOTS : units;
+}
+
+// Layout: lattices [groups][N] u64, undecided lanes of the two classes
+// [entries] u64 each, list entries [entries] u32, bond signs [N] u8 (spin
+// glass only), list counts [34] int, then (16-byte aligned) T's bits at the
+// planes of each call [16] uint4.  nw: wavefronts of the workgroup.
+__host__ __device__ inline size_t msc_lds_tmask_off(int N, int groups, bool ea, int nw, int mode)
+{
+    const size_t ent = (size_t)msc_list_entries(N, groups, nw, mode);
+    const size_t end = (size_t)groups * N * 8 + ent * 20 + (ea ? (size_t)N : 0) + sizeof(int) * 34;
     return (end + 15) & ~(size_t)15;
 }
 
-__host__ __device__ inline size_t msc_lds_need(int N, int groups)
+__host__ __device__ inline size_t msc_lds_need(int N, int groups, bool ea, int nw, int mode)
 {
-    return msc_lds_tmask_off(N, groups) + 16 * 16;
+    return msc_lds_tmask_off(N, groups, ea, nw, mode) + 16 * 16;
 }
 
 struct ChunkItem {    // one chunk of CH replicas of one (run, pop)

@@ -207,6 +207,12 @@ pa_status upload(pa_server *s, void *dst, const void *src, size_t n)
     return PA_OK;
 }
 
+// The batched sweep's launch mode: lockstep calls | pooled << 8.
+int serve_mode(const pa_server *s)
+{
+    return s->dense | (s->pooled ? 1 << 8 : 0);
+}
+
 int groups_of(const pa_server *s, int L)
 {
     auto it = s->groups.find(L);
@@ -259,7 +265,7 @@ pa_status rebuild(pa_server *s)
             const int G = groups_of(s, sl.d.L);
             const int N = sl.d.L * sl.d.L;
             if ((size_t)G * N > 65535) return PA_ERR_ARG;
-            lds = std::max(lds, msc_lds_bytes(N, G));
+            lds = std::max(lds, msc_lds_bytes(N, G, sl.d.model == PA_EA_PMJ, s->threads, serve_mode(s)));
             for (int p = 0; p < npop; ++p)
                 for (int g = 0; g < groups_cap_of(sl.d); g += G)
                     sweep.push_back({k, p, g, std::min(G, groups_cap_of(sl.d) - g)});
@@ -280,7 +286,8 @@ pa_status rebuild(pa_server *s)
         }
     if (s->repr == PA_MSC64) {
         SweepClass probe[MAX_SWEEP_CLASSES];
-        if (sweep_classes(sweep, run_L, run_ea, probe) < 0) return PA_ERR_ARG;   // orders the list by class
+        if (sweep_classes(sweep, run_L, run_ea, probe, s->threads, serve_mode(s)) < 0)   // orders the list by class
+            return PA_ERR_ARG;
     }
     if (!grow(s, s->items_off, s->items_cap, sizeof(Item) * std::max<size_t>(n_items, 1)) ||
         !grow(s, s->chunks_off, s->chunks_cap, sizeof(ChunkItem) * std::max<size_t>(n_chunks, 1)) ||
@@ -338,7 +345,7 @@ pa_status rebuild(pa_server *s)
     c.n_sweep_classes = 0;
     if (s->repr == PA_MSC64 && !sweep.empty()) {
         if (prepare_msc_lds(lds) != hipSuccess) return sfail(s);
-        const int ncls = sweep_classes(sweep, run_L, run_ea, c.sweep_cls);
+        const int ncls = sweep_classes(sweep, run_L, run_ea, c.sweep_cls, s->threads, serve_mode(s));
         if (ncls < 0) return PA_ERR_ARG;
         if (!sweep_class_grids(c.sweep_cls, ncls, s->threads, s->persistent)) return sfail(s);
         c.n_sweep_classes = ncls;
@@ -446,7 +453,9 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     const pa_run_desc &d = *desc;
     if (s->repr == PA_MSC64) {
         const int N = d.L * d.L, G = groups_of(s, d.L);
-        if ((size_t)G * N > 65535 || msc_lds_bytes(N, G) > (size_t)s->lds_limit) return PA_ERR_ARG;
+        if ((size_t)G * N > 65535 ||
+            msc_lds_bytes(N, G, d.model == PA_EA_PMJ, s->threads, serve_mode(s)) > (size_t)s->lds_limit)
+            return PA_ERR_ARG;
     }
     const int N = d.L * d.L;
     int t = -1;
