@@ -1302,7 +1302,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
     }
 }
 
-template <int LT, bool EA>
+template <int LT, bool EA, bool RING>
 __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo &R, const PopState &S,
                                            uint64_t *lds, int mode, unsigned long long *stats)
 {
@@ -1333,7 +1333,9 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     // the streamed sparse rounds keep each entry's next call in its site
     // word's top bits (sites < 4096); calls 0 .. 15 only
     const bool stream = msc_streamed(N, mode);
-    const int ents = msc_list_entries(N, G, nw, mode);   // units, or a ring per wavefront
+    // one list entry per unit, or (RING: the kernels compiled for one size)
+    // a ring of MSC_QUEUE_SLOTS per wavefront
+    const int ents = RING ? msc_list_entries(N, G, nw, mode) : units;
     const bool bounded = ents < units;
     uint64_t *lat = lds;                                  // [G][2][nh]
     uint64_t *e4 = lds + (size_t)G * N;                   // [ents] undecided lanes of class dE = +4
@@ -1442,7 +1444,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     q.ts += __popcll(need);
                     if (q.ts >= rcap) q.ts -= rcap;
                     q.left += __popcll(need);
-                    if (bounded && q.left > rcap - 64) {   // room for the next chunk's entries
+                    if (RING && bounded && q.left > rcap - 64) {   // room for the next chunk's entries
                         if (G == 1)
                             stream_rounds<true>(q, rcap - 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask,
                                                 (uint32_t)i, c3, key0, key1, wcalls);
@@ -1550,14 +1552,14 @@ __device__ __forceinline__ void sweep_dispatch(const SweepItem &it, const RunInf
                                                uint64_t *lds, int dense, unsigned long long *stats)
 {
     switch (R.L) {
-    case 8: sweep_item<8, EA>(it, R, S, lds, dense, stats); break;
-    case 16: sweep_item<16, EA>(it, R, S, lds, dense, stats); break;
-    case 24: sweep_item<24, EA>(it, R, S, lds, dense, stats); break;
-    case 32: sweep_item<32, EA>(it, R, S, lds, dense, stats); break;
-    case 48: sweep_item<48, EA>(it, R, S, lds, dense, stats); break;
-    case 64: sweep_item<64, EA>(it, R, S, lds, dense, stats); break;
-    case 128: sweep_item<128, EA>(it, R, S, lds, dense, stats); break;
-    default: sweep_item<0, EA>(it, R, S, lds, dense, stats); break;
+    case 8: sweep_item<8, EA, false>(it, R, S, lds, dense, stats); break;
+    case 16: sweep_item<16, EA, false>(it, R, S, lds, dense, stats); break;
+    case 24: sweep_item<24, EA, false>(it, R, S, lds, dense, stats); break;
+    case 32: sweep_item<32, EA, false>(it, R, S, lds, dense, stats); break;
+    case 48: sweep_item<48, EA, false>(it, R, S, lds, dense, stats); break;
+    case 64: sweep_item<64, EA, false>(it, R, S, lds, dense, stats); break;
+    case 128: sweep_item<128, EA, false>(it, R, S, lds, dense, stats); break;
+    default: sweep_item<0, EA, false>(it, R, S, lds, dense, stats); break;
     }
 }
 
@@ -1573,12 +1575,13 @@ __device__ __forceinline__ void sweep_one(const SweepItem &it, const RunInfo *ru
     if (!pop_active(S) || R.theta == 0) return;
     // an item that does not fit the LDS of this launch (a list that does not
     // belong to the launch's plan) is skipped and counted, never run
-    if (msc_lds_need(R.N, it.ngroups, R.model == PA_EA_PMJ, (int)(blockDim.x >> 6), dense) > lds_bytes) {
+    if (msc_lds_need(R.N, it.ngroups, R.model == PA_EA_PMJ, (int)(blockDim.x >> 6),
+                     LS >= 0 ? dense : dense | MSC_WHOLE_LISTS) > lds_bytes) {
         if (threadIdx.x == 0) atomicAdd(&stats[ST_STALL], 1ull);
         return;
     }
     if constexpr (LS >= 0) {
-        sweep_item<LS, EA>(it, R, S, lds, dense, stats);
+        sweep_item<LS, EA, true>(it, R, S, lds, dense, stats);
     } else {
         if (R.model == PA_EA_PMJ) sweep_dispatch<true>(it, R, S, lds, dense, stats);
         else sweep_dispatch<false>(it, R, S, lds, dense, stats);
@@ -3032,8 +3035,9 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
         // the persistent grid makes safe
         if (q.nchunk > 1 && !persistent) return hipErrorInvalidConfiguration;
         const int grid = persistent ? q.grid : q.count;
+        const int mode = c.sweep_dense | (c.sweep_pooled << 8) | (q.L > 0 ? 0 : MSC_WHOLE_LISTS);
         msc_kernel(q.L, q.ea)<<<grid, c.sweep_threads, q.lds, c.stream>>>(
-            c.sweep_items + q.first, q.count, c.runs, c.st, c.sweep_dense | (c.sweep_pooled << 8), c.stats,
+            c.sweep_items + q.first, q.count, c.runs, c.st, mode, c.stats,
             persistent ? c.sweep_queue : nullptr, c.sweep_flags, (uint32_t)q.lds);
         PA_CHECK_LAUNCH();
     }
@@ -3064,9 +3068,10 @@ int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, 
     C.ea = key & 1;
     C.grid = 0;
     C.lds = 0;
+    const int cmode = C.L > 0 ? mode : mode | MSC_WHOLE_LISTS;
     for (const SweepItem &it : items) {
         const int L = run_L[it.run];
-        C.lds = std::max(C.lds, msc_lds_bytes(L * L, it.ngroups, run_ea[it.run] != 0, threads, mode));
+        C.lds = std::max(C.lds, msc_lds_bytes(L * L, it.ngroups, run_ea[it.run] != 0, threads, cmode));
     }
     return 1;
 }
@@ -3074,13 +3079,15 @@ int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, 
 int sweep_chunks_auto(int n, int slots)
 {
     // makespan in units of one whole item when every item takes the same
-    // time: ceil(n K / slots) rounds of 1/K each, plus a small cost per
-    // extra chunk for loading and storing the lattices once more
+    // time: ceil(n K / slots) rounds of 1/K each, plus a cost per extra
+    // chunk (loading and storing the lattices once more, a wait on the
+    // previous chunk, the chunk's own partial last rounds), measured at
+    // about a fifth of an item at L = 64 with three workgroups per CU
     if (slots <= 0 || n <= slots) return 1;
     int best = 1;
     double best_t = 1e300;
     for (int K = 1; K <= MAX_SWEEP_CHUNKS; ++K) {
-        const double t = (double)((n * (long)K + slots - 1) / slots) / K + 0.03 * (K - 1);
+        const double t = (double)((n * (long)K + slots - 1) / slots) / K + 0.2 * (K - 1);
         if (t < best_t - 1e-9) {
             best_t = t;
             best = K;

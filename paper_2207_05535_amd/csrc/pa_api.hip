@@ -605,8 +605,9 @@ bool plan_sweep(const pa_ctx *c, std::vector<SweepItem> &items, size_t &lds)
         const pa_run_desc &d = c->descs[r];
         const int N = d.L * d.L;
         if ((size_t)groups_for(c, d.L) * N > 65535) return false;   // 16-bit LDS word indices
+        // the larger, whole-list size: the kernel the plan launches is chosen later
         lds = std::max(lds, msc_lds_bytes(N, groups_for(c, d.L), d.model == PA_EA_PMJ, c->sweep_threads,
-                                          c->sweep_dense | (c->sweep_pooled ? 1 << 8 : 0)));
+                                          c->sweep_dense | (c->sweep_pooled ? 1 << 8 : 0) | MSC_WHOLE_LISTS));
     }
     if (lds > (size_t)c->lds_limit) return false;
     for (int r = 0; r < c->n_runs; ++r) {

@@ -134,10 +134,14 @@ constexpr int MAX_SWEEP_CHUNKS = 4;
 // one chunk's worth (a chunk adds at most 64, and full rounds leave at most
 // 64), so the lists take less LDS and more workgroups fit on a CU.
 constexpr int MSC_QUEUE_SLOTS = 128;
+constexpr int MSC_WHOLE_LISTS = 1 << 9;
 
-// mode = lockstep calls | pooled << 8, as the batched sweep is launched.
-// The sparse rounds are streamed for lattices of at most 4096 sites when
-// they are not pooled and there are sparse rounds at all.
+// mode = lockstep calls | pooled << 8 | whole lists << 9, as the batched
+// sweep is launched (whole lists: one entry per site word even when the
+// rounds are streamed; the kernel that dispatches per item uses them, its
+// many registers leaving no room for more workgroups per CU anyway).  The
+// sparse rounds are streamed for lattices of at most 4096 sites when they
+// are not pooled and there are sparse rounds at all.
 __host__ __device__ inline bool msc_streamed(int N, int mode)
 {
     return !((mode >> 8) & 1) && N <= 4096 && (mode & 0xFF) < 16;
@@ -150,7 +154,8 @@ __host__ __device__ inline int msc_list_entries(int N, int groups, int nw, int m
 {
     const int units = groups * (N / 2);
     const int upw = (units + nw - 1) / nw;
-    return msc_streamed(N, mode) && upw > MSC_QUEUE_SLOTS ? nw * MSC_QUEUE_SLOTS : units;
+    return msc_streamed(N, mode) && !(mode & MSC_WHOLE_LISTS) && upw > MSC_QUEUE_SLOTS ? nw * MSC_QUEUE_SLOTS
+                                                                                        : units;
 }
 
 // Layout: lattices [groups][N] u64, undecided lanes of the two classes

@@ -265,7 +265,8 @@ pa_status rebuild(pa_server *s)
             const int G = groups_of(s, sl.d.L);
             const int N = sl.d.L * sl.d.L;
             if ((size_t)G * N > 65535) return PA_ERR_ARG;
-            lds = std::max(lds, msc_lds_bytes(N, G, sl.d.model == PA_EA_PMJ, s->threads, serve_mode(s)));
+            lds = std::max(lds, msc_lds_bytes(N, G, sl.d.model == PA_EA_PMJ, s->threads,
+                                              serve_mode(s) | MSC_WHOLE_LISTS));
             for (int p = 0; p < npop; ++p)
                 for (int g = 0; g < groups_cap_of(sl.d); g += G)
                     sweep.push_back({k, p, g, std::min(G, groups_cap_of(sl.d) - g)});
@@ -454,7 +455,8 @@ pa_status pa_server_admit(pa_server *s, const pa_run_desc *desc, int32_t *slot)
     if (s->repr == PA_MSC64) {
         const int N = d.L * d.L, G = groups_of(s, d.L);
         if ((size_t)G * N > 65535 ||
-            msc_lds_bytes(N, G, d.model == PA_EA_PMJ, s->threads, serve_mode(s)) > (size_t)s->lds_limit)
+            msc_lds_bytes(N, G, d.model == PA_EA_PMJ, s->threads, serve_mode(s) | MSC_WHOLE_LISTS) >
+                (size_t)s->lds_limit)
             return PA_ERR_ARG;
     }
     const int N = d.L * d.L;
