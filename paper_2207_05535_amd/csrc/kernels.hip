@@ -1044,14 +1044,17 @@ __global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, con
 //    dE = +8) and make calls 0 .. dense-1 in lockstep; nearly every site
 //    needs that many, so few lanes idle;
 //  - sparse rounds: the sites still undecided are kept in a wave-private LDS
-//    list.  For lattices of at most 4096 sites the list is a queue whose
-//    entries carry their next call index, and every round takes the next 64
-//    entries whatever call each is at (sweep_stream_wave); otherwise the
-//    list is compacted in place after every call index (sweep_sparse_wave),
-//    or pooled over the workgroup (sweep_sparse_pooled).  Either way each
-//    round's calls run on full wavefronts until the last entries.
+//    list.  For lattices of at most 4096 sites the list is a queue (a ring
+//    of at most MSC_QUEUE_SLOTS entries in the kernels compiled for one
+//    size) whose entries carry their next call index, and every round takes
+//    the next 64 entries whatever call each is at (stream_rounds,
+//    stream_tail); otherwise the list is compacted in place after every
+//    call index (sweep_sparse_wave), or pooled over the workgroup
+//    (sweep_sparse_pooled).  Either way each round's calls run on full
+//    wavefronts until the last entries.
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
+
 // b plus the number of lanes below this one whose bit is set in the
 // wavefront mask m (two mbcnt instructions).
 __device__ __forceinline__ int rank_below(uint64_t m, int b)
@@ -1335,7 +1338,8 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const bool stream = msc_streamed(N, mode);
     // one list entry per unit, or (RING: the kernels compiled for one size)
     // a ring of MSC_QUEUE_SLOTS per wavefront
-    const int ents = RING ? msc_list_entries(N, G, nw, mode) : units;
+    const int lmode = RING ? mode : mode | MSC_WHOLE_LISTS;   // the layout the launch sized
+    const int ents = msc_list_entries(N, G, nw, lmode);
     const bool bounded = ents < units;
     uint64_t *lat = lds;                                  // [G][2][nh]
     uint64_t *e4 = lds + (size_t)G * N;                   // [ents] undecided lanes of class dE = +4
@@ -1343,7 +1347,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     uint32_t *en = (uint32_t *)(e8 + ents);               // [ents] (LDS word << 16) | site
     uint8_t *jb = (uint8_t *)(en + ents);                 // [2][nh] bond signs of each site (spin glass)
     int *ctl = (int *)(jb + (EA ? N : 0));                // pooled list counts [2], pass counts [2][16]
-    uint4 *tmask = (uint4 *)(lds + msc_lds_tmask_off(N, G, EA, nw, mode) / 8);   // [16] T's bits per call
+    uint4 *tmask = (uint4 *)(lds + msc_lds_tmask_off(N, G, EA, nw, lmode) / 8);   // [16] T's bits per call
     uint64_t *base = (uint64_t *)R.spins[pop][S.cur] + (size_t)group0 * N;
     for (int u = tid; u < G * N; u += T) {
         const int gs = u / N, n = u - gs * N;
