@@ -333,6 +333,14 @@ pa_status pa_set_sweep_chunks(pa_ctx *ctx, int32_t chunks);
  * whole). */
 pa_status pa_get_sweep_chunks(pa_ctx *ctx, int32_t *out);
 
+/* Launches of the batched sweep per temperature step in the current plan
+ * (host *out): 0 without Metropolis sweeps; 1 when the sweeping runs share
+ * one lattice size and model, or for a mix that one dispatching kernel
+ * serves; one per (size, model) when the runs mix sizes that each have a
+ * kernel of their own and every size fills at least half of the
+ * workgroups its kernel keeps resident.  Results never depend on it. */
+pa_status pa_get_sweep_launches(pa_ctx *ctx, int32_t *out);
+
 /* Sparse rounds of the batched sweep: on = 1 pools the sites still
  * undecided after the lockstep calls into one list per workgroup, so the
  * compacted rounds run on full wavefronts; on = 0 keeps one list per

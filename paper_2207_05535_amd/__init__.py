@@ -98,6 +98,7 @@ def lib():
             "pa_set_pooled": [vp, i32],
             "pa_set_sweep_chunks": [vp, i32],
             "pa_get_sweep_chunks": [vp, vp],
+            "pa_get_sweep_launches": [vp, vp],
             "pa_autotune": [vp, i32, C.c_char_p, vp, vp],
             "pa_read_stats": [vp, vp],
             "pa_destroy": [vp],
@@ -294,6 +295,12 @@ def pa_set_sweep_chunks(h, chunks):
 def pa_get_sweep_chunks(h):
     v = C.c_int32(0)
     _chk("pa_get_sweep_chunks", lib().pa_get_sweep_chunks(h, C.byref(v)), h)
+    return v.value
+
+
+def pa_get_sweep_launches(h):
+    v = C.c_int32(0)
+    _chk("pa_get_sweep_launches", lib().pa_get_sweep_launches(h, C.byref(v)), h)
     return v.value
 
 
@@ -513,6 +520,10 @@ class Context:
     def sweep_chunks(self):
         """Chunks per item of the current sweep plan (1: whole items)."""
         return pa_get_sweep_chunks(self.h)
+
+    def sweep_launches(self):
+        """Launches of the batched sweep per temperature step."""
+        return pa_get_sweep_launches(self.h)
 
     def tuning(self, L):
         return pa_get_tuning(self.h, L)

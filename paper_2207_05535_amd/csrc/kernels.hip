@@ -3022,13 +3022,12 @@ hipError_t prepare_msc_lds(size_t bytes)
     return hipSuccess;
 }
 
-// One launch per class.  The plan below makes at most one: the kernel
-// compiled for the lattice size and model when every sweeping run shares
-// them, else the kernel that dispatches per item.  (Separate launches per
-// size, one after another on the stream, were measured slower: on the
-// 4096-run batch 7.26 against 7.10 ms per sweep, and on the serving mix,
-// whose per-size launches are too small to fill the chip, 3.03 against
-// 3.54 thousand flips/ns while busy.)
+// One launch per class (sweep_classes below): the kernel compiled for the
+// lattice size and model when every sweeping run shares them; one such
+// kernel per (size, model) when every class is large enough to fill the
+// chip; else the kernel that dispatches per item.  (On the serving mix,
+// whose per-size launches are too small to fill the chip, launching each
+// size on its own measured 3.03 against 3.54 thousand flips/ns while busy.)
 hipError_t launch_sweep_msc(const LaunchCtx &c)
 {
     for (int k = 0; k < c.n_sweep_classes; ++k) {
@@ -3049,22 +3048,66 @@ hipError_t launch_sweep_msc(const LaunchCtx &c)
 }
 
 int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, const std::vector<int> &run_ea,
-                  SweepClass *cls, int threads, int mode)
+                  SweepClass *cls, int threads, int mode, bool split_ok)
 {
     // items of runs without Metropolis sweeps are not launched at all (the
     // kernel of another size must never see them)
     std::vector<SweepItem> out;
     out.reserve(items.size());
-    int key = -1;   // 2 L + ea shared by every item, 0 if they differ or L has no kernel of its own
+    std::vector<int> keys;   // per kept item: 2 L + ea, 0 if L has no kernel of its own
     for (const SweepItem &it : items) {
         const int L = run_L[it.run];
         if (L == 0) continue;
-        const int k = msc_specialised(L) ? 2 * L + (run_ea[it.run] ? 1 : 0) : 0;
-        key = key < 0 ? k : (key == k ? key : 0);
+        keys.push_back(msc_specialised(L) ? 2 * L + (run_ea[it.run] ? 1 : 0) : 0);
         out.push_back(it);
     }
     items.swap(out);
     if (items.empty()) return 0;
+    auto lds_of = [&](const SweepItem &it, int cmode) {
+        const int L = run_L[it.run];
+        return msc_lds_bytes(L * L, it.ngroups, run_ea[it.run] != 0, threads, cmode);
+    };
+    // One launch per (size, model) when every item has a kernel compiled
+    // for its size and each class fills at least half of the workgroups
+    // that kernel keeps resident: those kernels use fewer registers and the
+    // queue rings, so they run more workgroups per CU than the dispatching
+    // kernel (the 4096-run batch of four sizes: 6.00 against 6.63 ms per
+    // sweep).  Small classes (a serving mix) keep one dispatching launch,
+    // since launches that cannot fill the chip one after another are slower.
+    std::vector<int> ks(keys);
+    std::sort(ks.begin(), ks.end());
+    ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+    bool split = split_ok && ks.size() > 1 && (int)ks.size() <= MAX_SWEEP_CLASSES && ks[0] != 0;
+    std::vector<SweepClass> cand(ks.size());
+    for (size_t q = 0; split && q < ks.size(); ++q) {
+        SweepClass &C = cand[q];
+        C.L = ks[q] / 2;
+        C.ea = ks[q] & 1;
+        C.count = 0;
+        C.lds = 0;
+        C.grid = 0;
+        for (size_t t = 0; t < items.size(); ++t)
+            if (keys[t] == ks[q]) {
+                ++C.count;
+                C.lds = std::max(C.lds, lds_of(items[t], mode));
+            }
+        const int resident = sweep_msc_resident(threads, C.lds, C.L, C.ea);
+        if (resident <= 0 || 2 * C.count < resident) split = false;
+    }
+    if (split) {
+        // the items of each class together, in their largest-first order
+        std::vector<SweepItem> sorted;
+        sorted.reserve(items.size());
+        for (size_t q = 0; q < ks.size(); ++q) {
+            cand[q].first = (int)sorted.size();
+            for (size_t t = 0; t < items.size(); ++t)
+                if (keys[t] == ks[q]) sorted.push_back(items[t]);
+            cls[q] = cand[q];
+        }
+        items.swap(sorted);
+        return (int)ks.size();
+    }
+    const int key = ks.size() == 1 ? ks[0] : 0;
     SweepClass &C = cls[0];
     C.first = 0;
     C.count = (int)items.size();
@@ -3073,10 +3116,7 @@ int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, 
     C.grid = 0;
     C.lds = 0;
     const int cmode = C.L > 0 ? mode : mode | MSC_WHOLE_LISTS;
-    for (const SweepItem &it : items) {
-        const int L = run_L[it.run];
-        C.lds = std::max(C.lds, msc_lds_bytes(L * L, it.ngroups, run_ea[it.run] != 0, threads, cmode));
-    }
+    for (const SweepItem &it : items) C.lds = std::max(C.lds, lds_of(it, cmode));
     return 1;
 }
 

@@ -78,8 +78,10 @@ bool msc_specialised(int L);   // a sweep kernel compiled for this L alone exist
 // to launch (run_L[r], run_ea[r]: run r's lattice size and model).  Returns
 // the number of classes (at most MAX_SWEEP_CLASSES), or -1 on error.
 // threads and mode: the launch's workgroup size and mode (msc_lds_bytes).
+// split_ok: mixed sizes may get one launch per size when every class fills
+// the chip (this queries occupancy: the LDS limit must already be set).
 int sweep_classes(std::vector<SweepItem> &items, const std::vector<int> &run_L, const std::vector<int> &run_ea,
-                  SweepClass *cls, int threads, int mode);
+                  SweepClass *cls, int threads, int mode, bool split_ok);
 // Persistent grids of the classes (threads per workgroup as launched).
 bool sweep_class_grids(SweepClass *cls, int n, int threads, bool persistent);
 // Chunks of sweeps per item for a persistent launch of n items on `slots`

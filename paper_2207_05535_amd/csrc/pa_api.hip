@@ -638,10 +638,10 @@ pa_status upload_sweep_plan(pa_ctx *c)
         run_ea[r] = c->descs[r].model == PA_EA_PMJ;
     }
     SweepClass cls[MAX_SWEEP_CLASSES];
-    const int ncls = sweep_classes(items, run_L, run_ea, cls, c->sweep_threads,
-                                   c->sweep_dense | (c->sweep_pooled ? 1 << 8 : 0));
-    if (ncls < 0) return PA_ERR_ARG;
     if (prepare_msc_lds(lds) != hipSuccess) return dev_fail(c);
+    const int ncls = sweep_classes(items, run_L, run_ea, cls, c->sweep_threads,
+                                   c->sweep_dense | (c->sweep_pooled ? 1 << 8 : 0), true);
+    if (ncls < 0) return PA_ERR_ARG;
     if (!sweep_class_grids(cls, ncls, c->sweep_threads, c->sweep_persistent)) return dev_fail(c);
     if (ncls == 1 && cls[0].grid > 0 && cls[0].grid < cls[0].count) {
         const int K = c->sweep_chunks > 0 ? c->sweep_chunks : sweep_chunks_auto(cls[0].count, cls[0].grid);
@@ -1291,6 +1291,15 @@ pa_status pa_get_sweep_chunks(pa_ctx *c, int32_t *out)
     int K = 1;
     for (int k = 0; k < c->lc.n_sweep_classes; ++k) K = std::max(K, c->lc.sweep_cls[k].nchunk);
     *out = K;
+    return PA_OK;
+}
+
+pa_status pa_get_sweep_launches(pa_ctx *c, int32_t *out)
+{
+    if (!c || !out) return PA_ERR_ARG;
+    int n = 0;
+    for (int k = 0; k < c->lc.n_sweep_classes; ++k) n += c->lc.sweep_cls[k].count > 0 ? 1 : 0;
+    *out = n;
     return PA_OK;
 }
 

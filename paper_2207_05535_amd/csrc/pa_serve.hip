@@ -287,7 +287,9 @@ pa_status rebuild(pa_server *s)
         }
     if (s->repr == PA_MSC64) {
         SweepClass probe[MAX_SWEEP_CLASSES];
-        if (sweep_classes(sweep, run_L, run_ea, probe, s->threads, serve_mode(s)) < 0)   // orders the list by class
+        // orders the list by class; a serving mix keeps one launch for its
+        // sizes (their classes are too small to fill the chip one by one)
+        if (sweep_classes(sweep, run_L, run_ea, probe, s->threads, serve_mode(s), false) < 0)
             return PA_ERR_ARG;
     }
     if (!grow(s, s->items_off, s->items_cap, sizeof(Item) * std::max<size_t>(n_items, 1)) ||
@@ -346,7 +348,7 @@ pa_status rebuild(pa_server *s)
     c.n_sweep_classes = 0;
     if (s->repr == PA_MSC64 && !sweep.empty()) {
         if (prepare_msc_lds(lds) != hipSuccess) return sfail(s);
-        const int ncls = sweep_classes(sweep, run_L, run_ea, c.sweep_cls, s->threads, serve_mode(s));
+        const int ncls = sweep_classes(sweep, run_L, run_ea, c.sweep_cls, s->threads, serve_mode(s), false);
         if (ncls < 0) return PA_ERR_ARG;
         if (!sweep_class_grids(c.sweep_cls, ncls, s->threads, s->persistent)) return sfail(s);
         c.n_sweep_classes = ncls;

@@ -548,6 +548,51 @@ def test_sweep_statistics_are_shape_independent():
         assert got == ref, (threads, groups, dense, pooled, got, ref)
 
 
+def test_mixed_sizes_one_launch_per_size():
+    """Runs of two lattice sizes, each size with enough replica groups to
+    fill the chip with the launch shapes of the tuning cache, sweep in one
+    launch per size with the kernels compiled for each size (the plan reports
+    two launches, where a mix of small runs keeps one dispatching launch);
+    every run's records, spins, energies and family labels equal those of
+    the same run swept in a context of its own size, which the single-size
+    tests tie to the oracle."""
+    import json
+    import os
+    cache = os.path.join(os.path.dirname(pa.__file__), "tuning_cache.json")
+    with open(cache) as fh:
+        shape = {e["L"]: e for e in json.load(fh)["entries"] if e["repr"] == "msc"}
+    Ls = (16, 32)
+    runs = W.batched_fm_uneven(n_per_L=192, Ls=Ls, R=2000, K=6)
+
+    def context(rs, sizes):
+        c = pa.Context(rs, "msc")
+        for L in sizes:
+            c.set_tuning(L, shape[L]["threads"], shape[L]["groups"], shape[L]["dense"])
+        c.set_persistent(0)
+        return c
+
+    say("mixed sizes, one sweep launch per size")
+    mixed = context(runs, Ls)
+    assert mixed.sweep_launches() == 2
+    mixed.run(1, 6)
+    small = context(runs[:2] + runs[192:194], Ls)
+    assert small.sweep_launches() == 1   # too few groups per size to fill the chip
+    small.close()
+    obs = mixed.obs()
+    for k, L in enumerate(Ls):
+        part = runs[k * 192:(k + 1) * 192]
+        alone = context(part, (L,))
+        assert alone.sweep_launches() == 1
+        alone.run(1, 6)
+        ref = alone.obs()
+        assert obs[k * 192:(k + 1) * 192].tobytes() == ref.tobytes(), f"L={L}: records differ"
+        for r in (0, 77, 191):
+            for a, b in zip(mixed.state(k * 192 + r, 0), alone.state(r, 0)):
+                assert np.array_equal(np.asarray(a), np.asarray(b)), f"L={L} run {r}: state differs"
+        alone.close()
+    mixed.close()
+
+
 def _digest(ctx, d, steps):
     import hashlib
     h = hashlib.sha256()
