@@ -857,11 +857,16 @@ __device__ __forceinline__ int xcd_item(int b, int n)
 // gets meas_waves_per_group(N) wavefronts, which split its sites.  The
 // children of neighbouring groups have parents in shared source groups, so
 // neighbouring items run on one XCD.
+// split workgroups share an item: workgroup h of it takes the h-th share of
+// each group's 64-site blocks (more wavefronts in flight for large lattices,
+// each with a shorter chain of loads and transposes).
 template <int REPR>
 __global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, const RunInfo *runs,
-                                                       const PopState *st)
+                                                       const PopState *st, int split)
 {
-    const SweepItem it = items[xcd_item(blockIdx.x, gridDim.x)];
+    const int b = xcd_item(blockIdx.x, gridDim.x);
+    const SweepItem it = items[b / split];
+    const int h = b - (b / split) * split;
     const RunInfo &R = runs[it.run];
     const PopState &S = st[it.run * MAX_POP + it.pop];
     if (!pop_active(S)) return;
@@ -870,7 +875,7 @@ __global__ void __launch_bounds__(MEAS_THREADS) k_copy(const SweepItem *items, c
     const int k = wv / wpg, sub = wv - k * wpg;
     const int G = it.group0 + k;
     if (k >= it.ngroups || G * 64 >= S.Rcur) return;
-    copy_group<REPR>(R, S, it.pop, G, sub, wpg);
+    copy_group<REPR>(R, S, it.pop, G, h * wpg + sub, split * wpg);
 }
 
 // ------------------------------------------------------------- step (iv)
@@ -2943,9 +2948,11 @@ hipError_t launch_resample(const LaunchCtx &c)
     PA_CHECK_LAUNCH();
     if (c.n_meas_items > 0) {
         if (c.repr == PA_MSC64)
-            k_copy<PA_MSC64><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+            k_copy<PA_MSC64><<<c.n_meas_items * c.copy_split, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs,
+                                                                                         c.st, c.copy_split);
         else
-            k_copy<PA_INT8><<<c.n_meas_items, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st);
+            k_copy<PA_INT8><<<c.n_meas_items * c.copy_split, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs,
+                                                                                        c.st, c.copy_split);
     }
     return hipGetLastError();
 }
