@@ -2947,12 +2947,13 @@ hipError_t launch_resample(const LaunchCtx &c)
     k_parent<<<c.n_chunk_items, CH_THREADS, 0, c.stream>>>(c.chunk_items, c.runs, c.st);
     PA_CHECK_LAUNCH();
     if (c.n_meas_items > 0) {
+        const int split = c.copy_split > 1 ? c.copy_split : 1;
         if (c.repr == PA_MSC64)
-            k_copy<PA_MSC64><<<c.n_meas_items * c.copy_split, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs,
-                                                                                         c.st, c.copy_split);
+            k_copy<PA_MSC64><<<c.n_meas_items * split, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st,
+                                                                                  split);
         else
-            k_copy<PA_INT8><<<c.n_meas_items * c.copy_split, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs,
-                                                                                        c.st, c.copy_split);
+            k_copy<PA_INT8><<<c.n_meas_items * split, MEAS_THREADS, 0, c.stream>>>(c.meas_items, c.runs, c.st,
+                                                                                 split);
     }
     return hipGetLastError();
 }

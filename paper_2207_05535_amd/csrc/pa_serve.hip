@@ -329,6 +329,7 @@ pa_status rebuild(pa_server *s)
     c.npop_ctx = npop_ctx;
     c.any_multinomial = mn;
     c.mn_split = mn_wide ? CH_PER : 1;
+    c.copy_split = 1;   // requests of any size share the copy launch
     c.any_overlap = ovl;
     c.any_wang = wang;
     {
@@ -594,9 +595,11 @@ pa_status pa_server_step(pa_server *s, int32_t *finished, int32_t *n_finished)
     pa_status st;
     if (s->dirty && (st = rebuild(s)) != PA_OK) return st;
     const LaunchCtx &c = s->lc;
-    if (launch_anneal(c) != hipSuccess || launch_resample(c) != hipSuccess) return sfail(s);
+    hipError_t e = launch_anneal(c);
+    if (e == hipSuccess) e = launch_resample(c);
+    if (e != hipSuccess) return sfail(s, e);
     if (s->repr == PA_MSC64) {
-        if (launch_sweep_msc(c) != hipSuccess) return sfail(s);
+        if ((e = launch_sweep_msc(c)) != hipSuccess) return sfail(s, e);
     } else {
         for (int k = 0; k < s->max_slots; ++k) {
             const Slot &sl = s->slots[k];
@@ -606,8 +609,8 @@ pa_status pa_server_step(pa_server *s, int32_t *finished, int32_t *n_finished)
                 return sfail(s);
         }
     }
-    if (launch_dos_sample(c) != hipSuccess) return sfail(s);
-    if (launch_measure(c) != hipSuccess) return sfail(s);
+    if ((e = launch_dos_sample(c)) != hipSuccess) return sfail(s, e);
+    if ((e = launch_measure(c)) != hipSuccess) return sfail(s, e);
     for (int k = 0; k < s->max_slots; ++k) {
         Slot &sl = s->slots[k];
         if (!sl.used || sl.done >= sl.d.K - 1) continue;
