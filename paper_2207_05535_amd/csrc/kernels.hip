@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 #include <math.h>
 #include <stdint.h>
@@ -2219,9 +2220,21 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
     // it (the replay of the exchanges itself is one wavefront's, in order).
     int nsw = 0, status = 0;
     int32_t *swaps = W.cnt;   // [2 B + 1] ints, B >= R_i: room for R_i exchanges
-    if (tid < 64) {
-        auto famv = [&](int m) { return in_lds ? Lfam[m] : fam[m]; };
-        auto fpiv = [&](int m) { return in_lds ? Lfpi[m] : ldc(&W.fampi[m]); };
+    // IN_LDS (a constant in each copy of the repair): the labels are read
+    // with LDS instructions only, not through generic pointers that would
+    // make every probe wait for both memory counters.  Values of one lane
+    // that the whole wavefront needs are read with readlane (the lane index
+    // is uniform), not with a permute through LDS.
+    auto repair = [&](auto in_lds_c) {
+        constexpr bool IN_LDS = decltype(in_lds_c)::value;
+        auto famv = [&](int m) {
+            if constexpr (IN_LDS) return Lfam[m];
+            else return fam[m];
+        };
+        auto fpiv = [&](int m) {
+            if constexpr (IN_LDS) return Lfpi[m];
+            else return ldc(&W.fampi[m]);
+        };
 
         // The repair, one wavefront, over the list in batches of 64 entries.
         // What does not change during the repair (position, its place in the
@@ -2247,7 +2260,7 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                 k_l = rdm ? ldc(&W.sigma[t_l]) : t_l;
                 f_l = famv(k_l);
                 open_l = fpiv(k_l) == f_l;
-                if (!in_lds) p_l = ldc(&W.pi[k_l]);
+                if (!IN_LDS) p_l = ldc(&W.pi[k_l]);
                 if (!rdm) {   // the first later index with another label
                     int lo = t_l + 1, hi = Rc;
                     while (lo < hi) {
@@ -2260,12 +2273,12 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
             }
             const int nb = min(64, nlist - e0);
             for (int j = 0; j < nb; ++j) {
-                if (!__shfl((int)open_l, j, 64)) continue;
-                const int t = __shfl(t_l, j, 64), k = __shfl(k_l, j, 64), fk = __shfl(f_l, j, 64);
-                const int pk = __shfl(p_l, j, 64);
+                if (!__builtin_amdgcn_readlane((int)open_l, j)) continue;
+                const int t = __builtin_amdgcn_readlane(t_l, j), k = __builtin_amdgcn_readlane(k_l, j);
+                const int fk = __builtin_amdgcn_readlane(f_l, j), pk = __builtin_amdgcn_readlane(p_l, j);
                 int64_t u = t + 1;
                 if (!rdm) {
-                    u = __shfl(hi_l, j, 64);
+                    u = __builtin_amdgcn_readlane(hi_l, j);
                     if (fk == prev_f && prev_u + 1 > u) u = prev_u + 1;
                 }
                 const int64_t uend = (int64_t)t + Rc;   // candidates t + 1 .. t + Rc - 1, indices mod Rc
@@ -2283,8 +2296,8 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                     const uint64_t bal = __ballot(ok);
                     if (bal) {
                         const int first = __ffsll((unsigned long long)bal) - 1;
-                        found = __shfl(m, first, 64);
-                        fm = __shfl(fpm, first, 64);
+                        found = __builtin_amdgcn_readlane(m, first);
+                        fm = __builtin_amdgcn_readlane(fpm, first);
                         prev_u = u + first;
                         break;
                     }
@@ -2293,7 +2306,7 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                     status = 2;
                     break;
                 }
-                if (in_lds) {
+                if constexpr (IN_LDS) {
                     if (lane == 0) {
                         Lfpi[k] = fm;
                         Lfpi[found] = fk;
@@ -2319,6 +2332,10 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
             sh[0] = nsw;
             sh[1] = status;
         }
+    };
+    if (tid < 64) {
+        if (in_lds) repair(std::true_type{});
+        else repair(std::false_type{});
     }
     __syncthreads();
     nsw = sh[0];
@@ -2338,7 +2355,7 @@ __global__ void __launch_bounds__(WANG_THREADS) k_wang_pairs(const RunInfo *runs
                 }
                 const int ns = min(64, nsw - s0);
                 for (int j = 0; j < ns; ++j) {
-                    const int x = __shfl(a, j, 64), y = __shfl(b, j, 64);
+                    const int x = __builtin_amdgcn_readlane(a, j), y = __builtin_amdgcn_readlane(b, j);
                     if (lane == 0) {
                         const int px = Lpi[x], py = Lpi[y];
                         Lpi[x] = py;
