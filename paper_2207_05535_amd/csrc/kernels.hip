@@ -703,7 +703,8 @@ __global__ void __launch_bounds__(CH_THREADS) k_parent(const ChunkItem *items, c
         while (big) {
             const int src = __ffsll((unsigned long long)big) - 1;
             big &= big - 1;
-            const int bj = __shfl(j, src, 64), bc = __shfl(cj, src, 64), br = __shfl(rj, src, 64);
+            const int bj = __builtin_amdgcn_readlane(j, src), bc = __builtin_amdgcn_readlane(cj, src),
+                      br = __builtin_amdgcn_readlane(rj, src);
             for (int m = PARENT_LANE_MAX + lane; m < br; m += 64) par[bc + m] = bj;
         }
     }
@@ -732,8 +733,9 @@ __device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, 
     if (REPR == PA_MSC64) {
         const uint64_t *src = (const uint64_t *)R.spins[pop][S.src];
         uint64_t *dst = (uint64_t *)R.spins[pop][S.cur] + (size_t)G * N;
-        const int g_lo = __shfl(p, 0, 64) >> 6;
-        const int g_hi = __shfl(p, 63, 64) >> 6;
+        // parents ascend with the children: the first and last lanes bound them
+        const int g_lo = __builtin_amdgcn_readlane(p, 0) >> 6;
+        const int g_hi = __builtin_amdgcn_readlane(p, 63) >> 6;
         if (g_hi - g_lo < COPY_MAX_SRC) {
             const int nsrc = g_hi - g_lo + 1;   // uniform over the wavefront
             // two 64-site blocks per step: their source loads are issued together
@@ -777,15 +779,15 @@ __device__ __forceinline__ void copy_group(const RunInfo &R, const PopState &S, 
                 if (lane < cnt) dst[nb + lane] = mine;
             }
         }
-    } else if ((__shfl(p, 63, 64) >> 6) - (__shfl(p, 0, 64) >> 6) < 2) {
+    } else if ((__builtin_amdgcn_readlane(p, 63) >> 6) - (__builtin_amdgcn_readlane(p, 0) >> 6) < 2) {
         // the parents lie in at most two source groups: each lane packs the
         // 64 spin bytes of one site of each source group into a word (16-byte
         // loads), the words go through the bit-packed copy above, and the
         // child word is unpacked into 64 canonical bytes (16-byte stores)
         const uint8_t *srcb = R.spins[pop][S.src];
         uint8_t *dstb = R.spins[pop][S.cur] + (size_t)G * N * 64;
-        const int g_lo = __shfl(p, 0, 64) >> 6;
-        const int nsrc = (__shfl(p, 63, 64) >> 6) - g_lo + 1;   // 1 or 2, uniform
+        const int g_lo = __builtin_amdgcn_readlane(p, 0) >> 6;
+        const int nsrc = (__builtin_amdgcn_readlane(p, 63) >> 6) - g_lo + 1;   // 1 or 2, uniform
         for (int n0 = sub * 64; n0 < N; n0 += 2 * wpg * 64) {
             uint4 v[2][2][4];
 #pragma unroll
@@ -1440,7 +1442,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                 if (pool && need) {
                     int b0 = 0;
                     if (lane == 0) b0 = atomicAdd(&ctl[h & 1], __popcll(need));
-                    base_slot = __shfl(b0, 0, 64);
+                    base_slot = __builtin_amdgcn_readlane(b0, 0);
                 }
                 if ((und4 | und8) != 0) {
                     const int slot =
