@@ -33,7 +33,7 @@ struct LaunchCtx {
     bool any_multinomial;
     bool any_overlap = true;       // some run measures overlaps (index shift, two populations, pairing)
     int mn_split = CH_PER;         // workgroups per chunk of multinomial draws: CH_PER if a run spans chunks, else 1
-    int copy_split = 1;            // workgroups per copy item (4 when every lattice has at least 4096 sites)
+    int copy_split = 1;            // workgroups per copy item, each taking a share of every group's 64-site blocks
     bool any_wang;                 // some run pairs replicas by permutations
     int wang_lds_ints;             // LDS of the pairing repair (2 R_cap of the largest run that fits, or 0)
     bool any_exact_dos;            // some run is at theta = infinity

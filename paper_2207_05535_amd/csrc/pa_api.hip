@@ -808,9 +808,16 @@ pa_status pa_create(const pa_run_desc *runs, int32_t n_runs, pa_repr repr, void 
     c->lc.any_multinomial = c->any_multinomial;
     c->lc.mn_split = 1;
     c->lc.any_overlap = false;
-    c->lc.copy_split = 4;   // L = 64: 40 -> 35 us per copy at R = 1e5 against one workgroup per item
+    // copy workgroups per item: each wavefront keeps about four 64-site blocks
+    // of its group (L = 64: 40 -> 35 us per copy at R = 1e5 against one
+    // workgroup per item); set by the smallest lattice of the context
+    int min_n = 1 << 30;
+    for (int r = 0; r < n_runs; ++r) min_n = std::min(min_n, runs[r].L * runs[r].L);
+    {
+        const int blocks_per_wave = (min_n / 64) / meas_waves_per_group(min_n);
+        c->lc.copy_split = std::max(1, std::min(4, blocks_per_wave / 4));
+    }
     for (int r = 0; r < n_runs; ++r) {
-        if (runs[r].L * runs[r].L < 4096) c->lc.copy_split = 1;
         if (runs[r].resampling == PA_MULTINOMIAL && runs[r].R > CH) c->lc.mn_split = CH_PER;
         if (runs[r].overlap != PA_Q_NONE) c->lc.any_overlap = true;
     }
