@@ -90,8 +90,9 @@ bool sweep_class_grids(SweepClass *cls, int n, int threads, bool persistent);
 // count that least quantises the launch into rounds.
 int sweep_chunks_auto(int n, int slots);
 // Replaces the (single) class's items by K chunks of each, all first chunks
-// first; 0 on success, -1 if the class does not cover the whole list.
-int expand_sweep_chunks(std::vector<SweepItem> &items, SweepClass &cls, int K);
+// first, with the sweeps of each chunk (run_theta[r]: run r's theta); 0 on
+// success, -1 if the class does not cover the whole list.
+int expand_sweep_chunks(std::vector<SweepItem> &items, SweepClass &cls, int K, const std::vector<int> &run_theta);
 hipError_t prepare_wang_lds(size_t bytes);
 hipError_t launch_philox_rate(int calls, hipStream_t s, int *blocks, int *threads);
 

@@ -645,7 +645,9 @@ pa_status upload_sweep_plan(pa_ctx *c)
     if (!sweep_class_grids(cls, ncls, c->sweep_threads, c->sweep_persistent)) return dev_fail(c);
     if (ncls == 1 && cls[0].grid > 0 && cls[0].grid < cls[0].count) {
         const int K = c->sweep_chunks > 0 ? c->sweep_chunks : sweep_chunks_auto(cls[0].count, cls[0].grid);
-        if (expand_sweep_chunks(items, cls[0], K) != 0) return PA_ERR_ARG;
+        std::vector<int> run_theta(c->n_runs);
+        for (int r = 0; r < c->n_runs; ++r) run_theta[r] = std::max(0, c->descs[r].theta);
+        if (expand_sweep_chunks(items, cls[0], K, run_theta) != 0) return PA_ERR_ARG;
     }
     if (!items.empty())
         PA_HIP(c, hipMemcpyAsync(at<SweepItem>(c, c->lo.sweep_items), items.data(),

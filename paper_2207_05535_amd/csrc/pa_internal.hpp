@@ -117,11 +117,12 @@ struct Item {         // one replica group (64 replicas) of one (run, pop)
 
 struct SweepItem {    // groups [group0, group0 + ngroups) of one (run, pop), one workgroup
     int32_t run, pop, group0, ngroups;
-    // sweeps chunk * theta / nchunk .. (chunk + 1) * theta / nchunk - 1 of
-    // those groups (nchunk 0: all theta sweeps); chunk > 0 waits for the
-    // previous chunk of the same groups, whose completion is published in
+    // chunk `chunk` of `nchunk` of those groups' theta sweeps (nchunk <= 1:
+    // all of them): with two chunks, sweeps 0 .. cut - 1 and cut .. theta - 1;
+    // with more, as even as possible, the larger first.  chunk > 0 waits for
+    // the previous chunk of the same groups, whose completion is published in
     // flag slot `base`
-    int32_t chunk, nchunk, base, pad;
+    int32_t chunk, nchunk, base, cut;
 };
 constexpr int MAX_SWEEP_CHUNKS = 4;
 
