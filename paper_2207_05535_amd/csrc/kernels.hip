@@ -1064,6 +1064,15 @@ __global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, con
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
 
+// Flips the accepted replicas of a lattice word in LDS with one atomic XOR
+// that returns nothing: no read into registers, no wait, and no test for an
+// empty mask (XOR with zero changes nothing).  The words of one round are
+// distinct sites, and a wavefront's LDS operations complete in order.
+__device__ __forceinline__ void flip_word(uint64_t *w, uint64_t acc)
+{
+    __hip_atomic_fetch_xor(w, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // b plus the number of lanes below this one whose bit is set in the
 // wavefront mask m (two mbcnt instructions).
 __device__ __forceinline__ int rank_below(uint64_t m, int b)
@@ -1107,7 +1116,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
                 wcalls += (uint32_t)__popcll(live);
                 if ((und4 | und8) != 0) draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
             }
-            if (acc) lat[addr] ^= acc;
+            flip_word(&lat[addr], acc);
             return;
         }
         int wcnt = 0;
@@ -1123,7 +1132,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
                 const int addr = (int)(pk >> 16);
                 const uint32_t g = (uint32_t)(group0 + addr / N);
                 draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, i, c3, key0, key1);
-                if (acc) lat[addr] ^= acc;
+                flip_word(&lat[addr], acc);
             }
             const uint64_t need = __ballot((und4 | und8) != 0);
             if ((und4 | und8) != 0) {
@@ -1174,7 +1183,7 @@ __device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat,
         const uint32_t c = (pk >> 12) & 15u;
         draw_call_masks(c, tmask[c], und4, und8, acc, pk & 0xFFFu, group_of(addr), i, c3, key0, key1);
         wcalls += 64;
-        if (acc) lat[addr] ^= acc;
+        flip_word(&lat[addr], acc);
         const bool more = (und4 | und8) != 0 && c < 15u;
         const uint64_t need = __ballot(more);
         if (more) {
@@ -1227,7 +1236,7 @@ __device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const 
             ++c;
         }
     }
-    if (acc) lat[addr] ^= acc;
+    flip_word(&lat[addr], acc);
 }
 
 // Sparse rounds over one list shared by the workgroup (ctl[h & 1] entries,
@@ -1271,7 +1280,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                     if ((und4 | und8) != 0)
                         draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
                 }
-                if (acc) lat[addr] ^= acc;
+                flip_word(&lat[addr], acc);
             }
             return;
         }
@@ -1288,7 +1297,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                 const int addr = (int)(pk >> 16);
                 const uint32_t g = (uint32_t)(group0 + addr / N);
                 draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, i, c3, key0, key1);
-                if (acc) lat[addr] ^= acc;
+                flip_word(&lat[addr], acc);
             }
             const uint64_t need = __ballot((und4 | und8) != 0);
             int *cw = ctl + 2 + 16 * par;
@@ -1444,7 +1453,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     if ((und4 | und8) != 0)
                         draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, (uint32_t)i, c3, key0, key1);
                 }
-                if (acc) lat[addr] ^= acc;
+                flip_word(&lat[addr], acc);
                 const uint64_t need = __ballot((und4 | und8) != 0);
                 int base_slot = ub + cnt;
                 if (pool && need) {
