@@ -1064,6 +1064,14 @@ __global__ void __launch_bounds__(THREADS) k_sweep_int8(const RunInfo *runs, con
 // Every site's result is still the plain most-significant-first comparison
 // of its own bit planes; only the order of the work changes.
 
+// Lanes of the wavefront where p holds.  Unlike __ballot(int), the
+// predicate stays a lane mask: a condition combined from several compares
+// is not turned into an integer and compared again.
+__device__ __forceinline__ uint64_t wave_ballot(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(p);
+}
+
 // Flips the accepted replicas of a lattice word in LDS with one atomic XOR
 // that returns nothing: no read into registers, no wait, and no test for an
 // empty mask (XOR with zero changes nothing).  The words of one round are
@@ -1111,7 +1119,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
                 g = (uint32_t)(group0 + addr / N);
             }
             for (; c < 16; ++c) {
-                const uint64_t live = __ballot((und4 | und8) != 0);
+                const uint64_t live = wave_ballot((und4 | und8) != 0);
                 if (live == 0) break;
                 wcalls += (uint32_t)__popcll(live);
                 if ((und4 | und8) != 0) draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, i, c3, key0, key1);
@@ -1134,7 +1142,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
                 draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, i, c3, key0, key1);
                 flip_word(&lat[addr], acc);
             }
-            const uint64_t need = __ballot((und4 | und8) != 0);
+            const uint64_t need = wave_ballot((und4 | und8) != 0);
             if ((und4 | und8) != 0) {
                 const int slot = rank_below(need, wcnt);
                 e4[slot] = und4;
@@ -1185,7 +1193,8 @@ __device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat,
         wcalls += 64;
         flip_word(&lat[addr], acc);
         const bool more = (und4 | und8) != 0 && c < 15u;
-        const uint64_t need = __ballot(more);
+        // the two compares' masks, combined on the scalar unit
+        const uint64_t need = wave_ballot((und4 | und8) != 0) & wave_ballot(c < 15u);
         if (more) {
             const int out = wrap_once(rank_below(need, ts), cap);
             e4[out] = und4;
@@ -1228,7 +1237,7 @@ __device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const 
     const uint32_t g = (uint32_t)(ONE_GROUP ? group0 : group0 + addr / N);
     for (;;) {
         const bool live = (und4 | und8) != 0 && c < 16u;
-        const uint64_t lv = __ballot(live);
+        const uint64_t lv = wave_ballot((und4 | und8) != 0) & wave_ballot(c < 16u);
         if (lv == 0) break;
         wcalls += (uint32_t)__popcll(lv);
         if (live) {
@@ -1274,7 +1283,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                     g = (uint32_t)(group0 + addr / N);
                 }
                 for (; c < 16; ++c) {
-                    const uint64_t live = __ballot((und4 | und8) != 0);
+                    const uint64_t live = wave_ballot((und4 | und8) != 0);
                     if (live == 0) break;
                     wcalls += (uint32_t)__popcll(live);
                     if ((und4 | und8) != 0)
@@ -1299,7 +1308,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                 draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, pk & 0xFFFFu, g, i, c3, key0, key1);
                 flip_word(&lat[addr], acc);
             }
-            const uint64_t need = __ballot((und4 | und8) != 0);
+            const uint64_t need = wave_ballot((und4 | und8) != 0);
             int *cw = ctl + 2 + 16 * par;
             if (lane == 0) cw[wv] = __popcll(need);
             __syncthreads();
@@ -1447,14 +1456,14 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     }
                 }
                 for (int c = 0; c < dense; ++c) {
-                    const uint64_t live = __ballot((und4 | und8) != 0);
+                    const uint64_t live = wave_ballot((und4 | und8) != 0);
                     if (live == 0) break;
                     wcalls += (uint32_t)__popcll(live);
                     if ((und4 | und8) != 0)
                         draw_call((uint32_t)c, Th.t4, Th.t8, und4, und8, acc, n, g, (uint32_t)i, c3, key0, key1);
                 }
                 flip_word(&lat[addr], acc);
-                const uint64_t need = __ballot((und4 | und8) != 0);
+                const uint64_t need = wave_ballot((und4 | und8) != 0);
                 int base_slot = ub + cnt;
                 if (pool && need) {
                     int b0 = 0;
