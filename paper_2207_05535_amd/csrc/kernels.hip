@@ -1095,12 +1095,35 @@ __device__ __forceinline__ int wrap_once(int x, int m)
     return (int)min((uint32_t)x, (uint32_t)x - (uint32_t)m);
 }
 
+// A list entry's undecided lanes of the two classes (dE = +4, dE = +8), kept
+// side by side so that one LDS address serves both.  Reads are one 16-byte
+// access (ds_read_b128).  Writes go out as two 8-byte halves of one
+// instruction (ds_write2_b64): with 16-byte writes the wavefronts waited
+// longer for LDS issue and the sweep was slower.
+struct alignas(16) UndPair {
+    uint64_t u4, u8;
+};
+
+__device__ __forceinline__ void und_load(const UndPair *p, uint64_t &u4, uint64_t &u8)
+{
+    const UndPair v = *p;
+    u4 = v.u4;
+    u8 = v.u8;
+}
+
+__device__ __forceinline__ void und_store(UndPair *p, uint64_t u4, uint64_t u8)
+{
+    uint64_t *w = (uint64_t *)(void *)p;   // 8-byte alignment: two 8-byte halves
+    w[0] = u4;
+    w[1] = u8;
+}
+
 // Sparse rounds of one wavefront over its own compacted list of `cnt`
 // undecided sites (entries: lanes of each class, LDS word << 16 | site):
 // call c for every entry, survivors compacted in place; once one pass holds
 // every remaining entry it runs all their remaining calls without writing
 // the list back.
-__device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en, int cnt,
+__device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, UndPair *eu, uint32_t *en, int cnt,
                                                   int c_first, int N, int group0, const Thresholds &Th, uint32_t i,
                                                   uint32_t c3, uint32_t key0, uint32_t key1, uint32_t &wcalls)
 {
@@ -1111,8 +1134,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
             int addr = 0;
             uint32_t n = 0, g = 0;
             if (lane < cnt) {
-                und4 = e4[lane];
-                und8 = e8[lane];
+                und_load(&eu[lane], und4, und8);
                 const uint32_t pk = en[lane];
                 addr = (int)(pk >> 16);
                 n = pk & 0xFFFFu;
@@ -1134,8 +1156,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
             uint32_t pk = 0;
             wcalls += (uint32_t)min(64, cnt - e0);
             if (e < cnt) {
-                und4 = e4[e];
-                und8 = e8[e];
+                und_load(&eu[e], und4, und8);
                 pk = en[e];
                 const int addr = (int)(pk >> 16);
                 const uint32_t g = (uint32_t)(group0 + addr / N);
@@ -1145,8 +1166,7 @@ __device__ __forceinline__ void sweep_sparse_wave(uint64_t *lat, uint64_t *e4, u
             const uint64_t need = wave_ballot((und4 | und8) != 0);
             if ((und4 | und8) != 0) {
                 const int slot = rank_below(need, wcnt);
-                e4[slot] = und4;
-                e8[slot] = und8;
+                und_store(&eu[slot], und4, und8);
                 en[slot] = pk;
             }
             wcnt += __popcll(need);
@@ -1175,7 +1195,7 @@ struct Ring {
 
 // Full rounds while the ring holds more than `limit` (>= 64) entries.
 template <bool ONE_GROUP>
-__device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat, uint64_t *e4, uint64_t *e8,
+__device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat, UndPair *eu,
                                               uint32_t *en, int cap, int N, int group0, const uint4 *tmask,
                                               uint32_t i, uint32_t c3, uint32_t key0, uint32_t key1,
                                               uint32_t &wcalls)
@@ -1185,7 +1205,8 @@ __device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat,
     int left = q.left, hs = q.hs, ts = q.ts;
     while (left > limit) {
         const int slot = wrap_once(hs + lane, cap);
-        uint64_t und4 = e4[slot], und8 = e8[slot], acc = 0;
+        uint64_t und4, und8, acc = 0;
+        und_load(&eu[slot], und4, und8);
         const uint32_t pk = en[slot];
         const int addr = (int)(pk >> 16);
         const uint32_t c = (pk >> 12) & 15u;
@@ -1197,8 +1218,7 @@ __device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat,
         const uint64_t need = wave_ballot((und4 | und8) != 0) & wave_ballot(c < 15u);
         if (more) {
             const int out = wrap_once(rank_below(need, ts), cap);
-            e4[out] = und4;
-            e8[out] = und8;
+            und_store(&eu[out], und4, und8);
             en[out] = (pk & 0xFFFF0FFFu) | ((c + 1u) << 12);
         }
         const int nn = __popcll(need);
@@ -1216,7 +1236,7 @@ __device__ __forceinline__ void stream_rounds(Ring &q, int limit, uint64_t *lat,
 // The last (at most 64) entries: each lane runs all the remaining calls of
 // its own entry.
 template <bool ONE_GROUP>
-__device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const uint64_t *e4, const uint64_t *e8,
+__device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const UndPair *eu,
                                             const uint32_t *en, int cap, int N, int group0, const uint4 *tmask,
                                             uint32_t i, uint32_t c3, uint32_t key0, uint32_t key1,
                                             uint32_t &wcalls)
@@ -1227,8 +1247,7 @@ __device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const 
     uint32_t n = 0, c = 16;
     if (lane < q.left) {
         const int slot = wrap_once(q.hs + lane, cap);
-        und4 = e4[slot];
-        und8 = e8[slot];
+        und_load(&eu[slot], und4, und8);
         const uint32_t pk = en[slot];
         addr = (int)(pk >> 16);
         c = (pk >> 12) & 15u;
@@ -1257,7 +1276,7 @@ __device__ __forceinline__ void stream_tail(const Ring &q, uint64_t *lat, const 
 // When at most two wavefront-loads remain, two wavefronts (one if the
 // workgroup has only one) run all their remaining calls without writing the
 // list back.
-__device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4, uint64_t *e8, uint32_t *en,
+__device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, UndPair *eu, uint32_t *en,
                                                     int *ctl, int h, int c_first, int N, int group0,
                                                     const Thresholds &Th, uint32_t i, uint32_t c3, uint32_t key0,
                                                     uint32_t key1, uint32_t &wcalls)
@@ -1275,8 +1294,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
                 int addr = 0;
                 uint32_t n = 0, g = 0;
                 if (e < cnt) {
-                    und4 = e4[e];
-                    und8 = e8[e];
+                    und_load(&eu[e], und4, und8);
                     const uint32_t pk = en[e];
                     addr = (int)(pk >> 16);
                     n = pk & 0xFFFFu;
@@ -1300,8 +1318,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
             uint32_t pk = 0;
             wcalls += (uint32_t)max(0, min(64, cnt - (s0 + wv * 64)));
             if (e < cnt) {
-                und4 = e4[e];
-                und8 = e8[e];
+                und_load(&eu[e], und4, und8);
                 pk = en[e];
                 const int addr = (int)(pk >> 16);
                 const uint32_t g = (uint32_t)(group0 + addr / N);
@@ -1320,8 +1337,7 @@ __device__ __forceinline__ void sweep_sparse_pooled(uint64_t *lat, uint64_t *e4,
             }
             if ((und4 | und8) != 0) {
                 const int slot = rank_below(need, off);
-                e4[slot] = und4;
-                e8[slot] = und8;
+                und_store(&eu[slot], und4, und8);
                 en[slot] = pk;
             }
             out += tot;
@@ -1376,9 +1392,8 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
     const int ents = msc_list_entries(N, G, nw, lmode);
     const bool bounded = ents < units;
     uint64_t *lat = lds;                                  // [G][2][nh]
-    uint64_t *e4 = lds + (size_t)G * N;                   // [ents] undecided lanes of class dE = +4
-    uint64_t *e8 = e4 + ents;                             // [ents] undecided lanes of class dE = +8
-    uint32_t *en = (uint32_t *)(e8 + ents);               // [ents] (LDS word << 16) | site
+    UndPair *eu = (UndPair *)(lds + (size_t)G * N);       // [ents] undecided lanes of the two classes
+    uint32_t *en = (uint32_t *)(eu + ents);               // [ents] (LDS word << 16) | site
     uint8_t *jb = (uint8_t *)(en + ents);                 // [2][nh] bond signs of each site (spin glass)
     int *ctl = (int *)(jb + (EA ? N : 0));                // pooled list counts [2], pass counts [2][16]
     uint4 *tmask = (uint4 *)(lds + msc_lds_tmask_off(N, G, EA, nw, lmode) / 8);   // [16] T's bits per call
@@ -1473,8 +1488,7 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                 if ((und4 | und8) != 0) {
                     const int slot =
                         stream ? rb + wrap_once(rank_below(need, q.ts), rcap) : rank_below(need, base_slot);
-                    e4[slot] = und4;
-                    e8[slot] = und8;
+                    und_store(&eu[slot], und4, und8);
                     en[slot] = ((uint32_t)addr << 16) | (stream ? (uint32_t)dense << 12 : 0u) | n;
                 }
                 cnt += __popcll(need);
@@ -1484,10 +1498,10 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                     q.left += __popcll(need);
                     if (RING && bounded && q.left > rcap - 64) {   // room for the next chunk's entries
                         if (G == 1)
-                            stream_rounds<true>(q, rcap - 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask,
+                            stream_rounds<true>(q, rcap - 64, lat, eu + rb, en + rb, rcap, N, group0, tmask,
                                                 (uint32_t)i, c3, key0, key1, wcalls);
                         else
-                            stream_rounds<false>(q, rcap - 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0,
+                            stream_rounds<false>(q, rcap - 64, lat, eu + rb, en + rb, rcap, N, group0,
                                                  tmask, (uint32_t)i, c3, key0, key1, wcalls);
                     }
                 }
@@ -1549,21 +1563,21 @@ __device__ __forceinline__ void sweep_item(const SweepItem &item, const RunInfo 
                 }
             }
             if (pool)
-                sweep_sparse_pooled(lat, e4, e8, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
+                sweep_sparse_pooled(lat, eu, en, ctl, h, dense, N, group0, Th, (uint32_t)i, c3, key0, key1,
                                     wcalls);
             else if (stream && G == 1) {
-                stream_rounds<true>(q, 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3,
+                stream_rounds<true>(q, 64, lat, eu + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3,
                                     key0, key1, wcalls);
-                stream_tail<true>(q, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3, key0,
+                stream_tail<true>(q, lat, eu + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3, key0,
                                   key1, wcalls);
             } else if (stream) {
-                stream_rounds<false>(q, 64, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3,
+                stream_rounds<false>(q, 64, lat, eu + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3,
                                      key0, key1, wcalls);
-                stream_tail<false>(q, lat, e4 + rb, e8 + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3, key0,
+                stream_tail<false>(q, lat, eu + rb, en + rb, rcap, N, group0, tmask, (uint32_t)i, c3, key0,
                                    key1, wcalls);
             }
             else
-                sweep_sparse_wave(lat, e4 + ub, e8 + ub, en + ub, cnt, dense, N, group0, Th, (uint32_t)i, c3, key0,
+                sweep_sparse_wave(lat, eu + ub, en + ub, cnt, dense, N, group0, Th, (uint32_t)i, c3, key0,
                                   key1, wcalls);
         }
     }
