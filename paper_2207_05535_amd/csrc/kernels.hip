@@ -2692,24 +2692,46 @@ __global__ void k_finalize(const RunInfo *runs, PopState *st, int n_runs)
 // Log free-energy weights per run and temperature: simplified
 // ln R_i + A_i (Eq. (simpleWeight)) and full ln R_i + sum_{k<=i}
 // ln(R_{k-1}/R) + A_i (Eq. (appropriateWeight)); NaN where the record is not
-// OK or the temperature is not reached yet.
-__global__ void k_logw(const RunInfo *runs, const pa_obs *obs, int n_runs, int npop_ctx, int pop,
-                       int kind, int i_done, double *logw)
+// OK or the temperature is not reached yet.  One workgroup per run, over the
+// temperatures a tile at a time: every thread reads its temperature's
+// records and takes the logarithms, then one thread adds the ln(R_{k-1}/R)
+// terms from LDS in order of k (the same sums as a sequential pass), instead
+// of one thread per run walking all K records with a load and a logarithm in
+// each step of a dependent chain.
+constexpr int SCAN_THREADS = 256;
+
+__global__ void __launch_bounds__(SCAN_THREADS) k_logw(const RunInfo *runs, const pa_obs *obs, int n_runs,
+                                                       int npop_ctx, int pop, int kind, int i_done, double *logw)
 {
-    const int run = blockIdx.x * blockDim.x + threadIdx.x;
-    if (run >= n_runs) return;
+    __shared__ double term[SCAN_THREADS];   // ln(R_{i-1}/R) of the tile's temperatures, then the running sums
+    __shared__ double carry;
+    const int run = blockIdx.x, t = threadIdx.x;
     const RunInfo &R = runs[run];
-    double cum = 0.0;
-    for (int i = 0; i < R.K; ++i) {
-        const pa_obs &o = obs[((size_t)i * n_runs + run) * npop_ctx + pop];
-        if (i > 0) {
-            const pa_obs &op = obs[((size_t)(i - 1) * n_runs + run) * npop_ctx + pop];
-            cum += log((double)op.R_i / (double)R.R);
+    const bool full = (kind & 1) == PA_W_FULL;
+    if (t == 0) carry = 0.0;
+    for (int base = 0; base < R.K; base += SCAN_THREADS) {
+        const int i = base + t;
+        double a = NAN;   // ln R_i + A_i
+        if (i < R.K) {
+            const pa_obs &o = obs[((size_t)i * n_runs + run) * npop_ctx + pop];
+            term[t] = i > 0 ? log((double)obs[((size_t)(i - 1) * n_runs + run) * npop_ctx + pop].R_i /
+                                  (double)R.R)
+                            : 0.0;
+            if (i <= i_done && o.status == PA_OK && pop < R.npop) a = log((double)o.R_i) + o.A;
         }
-        double a = NAN;
-        if (i <= i_done && o.status == PA_OK && pop < R.npop)
-            a = log((double)o.R_i) + o.A + ((kind & 1) == PA_W_FULL ? cum : 0.0);
-        logw[(size_t)run * R.K + i] = a;
+        __syncthreads();
+        if (t == 0) {
+            double cum = carry;
+            const int n = min(SCAN_THREADS, R.K - base);
+            for (int k = 0; k < n; ++k) {
+                if (base + k > 0) cum += term[k];
+                term[k] = cum;
+            }
+            carry = cum;
+        }
+        __syncthreads();
+        if (i < R.K) logw[(size_t)run * R.K + i] = a + (full ? term[t] : 0.0);
+        __syncthreads();   // the next tile rewrites term
     }
 }
 
@@ -2939,17 +2961,39 @@ __global__ void k_famstats(const RunInfo *runs, const pa_obs *obs, int n_runs, i
     out[gi] = f;
 }
 
-// -beta_i W[F_i] = ln Z(beta_0) + sum_{k=1..i} ln W[Q_k], Eq. (W_F).
-__global__ void k_wavg_cumsum(pa_wavg *out, int ngroups, int K)
+// -beta_i W[F_i] = ln Z(beta_0) + sum_{k=1..i} ln W[Q_k], Eq. (W_F); NaN
+// from the first temperature with no run included on.  One workgroup per
+// group of runs: the tile's terms are staged in LDS by all threads and
+// summed in order of i by one thread.
+__global__ void __launch_bounds__(SCAN_THREADS) k_wavg_cumsum(pa_wavg *out, int ngroups, int K)
 {
-    const int grp = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double v[SCAN_THREADS];
+    __shared__ uint8_t none[SCAN_THREADS];   // no run included at that temperature
+    __shared__ double carry;
+    const int grp = blockIdx.x, t = threadIdx.x;
     if (grp >= ngroups) return;
-    double c = 0.0;
-    for (int i = 0; i < K; ++i) {
-        pa_wavg &w = out[(size_t)grp * K + i];
-        if (w.n_included == 0) c = NAN;
-        else c = i == 0 ? w.minus_beta_WF : c + w.minus_beta_WF;
-        w.minus_beta_WF = c;
+    if (t == 0) carry = 0.0;
+    for (int base = 0; base < K; base += SCAN_THREADS) {
+        const int i = base + t;
+        if (i < K) {
+            const pa_wavg &w = out[(size_t)grp * K + i];
+            v[t] = w.minus_beta_WF;
+            none[t] = w.n_included == 0;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double c = carry;
+            const int n = min(SCAN_THREADS, K - base);
+            for (int k = 0; k < n; ++k) {
+                if (none[k]) c = NAN;
+                else c = base + k == 0 ? v[k] : c + v[k];
+                v[k] = c;
+            }
+            carry = c;
+        }
+        __syncthreads();
+        if (i < K) out[(size_t)grp * K + i].minus_beta_WF = v[t];
+        __syncthreads();   // the next tile rewrites v and none
     }
 }
 
@@ -3343,8 +3387,7 @@ hipError_t launch_measure(const LaunchCtx &c)
 hipError_t launch_qweights(const LaunchCtx &c, const pa_obs *obs, int M, int kind, int pop, int K, int i_done,
                            double *logw, double *qw)
 {
-    k_logw<<<(c.n_runs + 255) / 256, 256, 0, c.stream>>>(c.runs, obs, c.n_runs, c.npop_ctx, pop, kind, i_done,
-                                                        logw);
+    k_logw<<<c.n_runs, SCAN_THREADS, 0, c.stream>>>(c.runs, obs, c.n_runs, c.npop_ctx, pop, kind, i_done, logw);
     PA_CHECK_LAUNCH();
     const int ng = c.n_runs / M;
     k_qweights<<<(ng * K + 127) / 128, 128, 0, c.stream>>>(c.runs, obs, logw, c.n_runs, c.npop_ctx, pop, M, K,
@@ -3376,7 +3419,7 @@ hipError_t launch_wavg(const LaunchCtx &c, const pa_obs *obs, int M, int kind, i
     k_wavg<<<(ng * K + 127) / 128, 128, 0, c.stream>>>(c.runs, obs, logw, qw, c.n_runs, c.npop_ctx, pop, M, K,
                                                       out);
     PA_CHECK_LAUNCH();
-    k_wavg_cumsum<<<(ng + 127) / 128, 128, 0, c.stream>>>(out, ng, K);
+    k_wavg_cumsum<<<ng, SCAN_THREADS, 0, c.stream>>>(out, ng, K);
     return hipGetLastError();
 }
 
